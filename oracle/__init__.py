@@ -1,0 +1,151 @@
+"""CPU oracle for suffix-array construction by prefix doubling.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of
+the benchmark may import this package; the product path (the HIP library and
+its binding) never does, and shares no code with it.
+
+The arithmetic lives in ``oracle.cpp`` (plain C++17, ``std::sort``). This module
+compiles it with g++ on demand and wraps it with ctypes over numpy arrays:
+
+* :func:`sa` -- plain prefix doubling (paper Alg. 1 with the inverse-suffix-array
+  pairing of Alg. 4), no discarding; 1-based names with 0 as the sentinel.
+* :func:`pd_names` -- the names after a given number of doubling sorts.
+* :func:`prefix_ranks` -- the closed form of the names for prefix length ``h``:
+  1 + the number of suffixes whose padded length-``h`` prefix is smaller.
+* :func:`brute_sa` -- the definition: sort all suffixes lexicographically.
+* :func:`check_sa` -- linear-time suffix-array check (permutation plus an
+  adjacent-pair test against the inverse of the array under test).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+LIB_SEQ = os.path.join(_HERE, "liboracle.so")
+LIB_PAR = os.path.join(_HERE, "liboracle_par.so")
+
+_lock = threading.Lock()
+_libs: dict[bool, ctypes.CDLL] = {}
+
+
+def build(parallel: bool | None = None) -> None:
+    """Compile the sequential and the OpenMP (GNU parallel sort) builds."""
+    targets = [False, True] if parallel is None else [parallel]
+    for par in targets:
+        out = LIB_PAR if par else LIB_SEQ
+        cmd = ["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", out + ".tmp", _SRC]
+        if par:
+            cmd[1:1] = ["-fopenmp", "-D_GLIBCXX_PARALLEL"]
+        subprocess.run(cmd, check=True)
+        os.replace(out + ".tmp", out)
+
+
+def configure(lib: ctypes.CDLL) -> ctypes.CDLL:
+    """Declare the C signatures on a loaded oracle library."""
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    u64 = ctypes.c_uint64
+    lib.oracle_sa.argtypes = [u8p, u64, u32p]
+    lib.oracle_pd_names.argtypes = [u8p, u64, u64, u32p, u64p]
+    lib.oracle_prefix_ranks.argtypes = [u8p, u64, u64, u32p]
+    lib.oracle_brute_sa.argtypes = [u8p, u64, u32p]
+    lib.oracle_check_sa.argtypes = [u8p, u64, u32p, u64p]
+    for f in ("oracle_sa", "oracle_pd_names", "oracle_prefix_ranks",
+              "oracle_brute_sa", "oracle_check_sa", "oracle_num_threads"):
+        getattr(lib, f).restype = ctypes.c_int
+    return lib
+
+
+def _lib(parallel: bool = False) -> ctypes.CDLL:
+    with _lock:
+        if parallel in _libs:
+            return _libs[parallel]
+        path = LIB_PAR if parallel else LIB_SEQ
+        if not os.path.exists(path):
+            build(parallel)
+        _libs[parallel] = configure(ctypes.CDLL(path))
+        return _libs[parallel]
+
+
+def _text(t) -> np.ndarray:
+    if isinstance(t, (bytes, bytearray, memoryview)):
+        return np.frombuffer(bytes(t), dtype=np.uint8)
+    a = np.ascontiguousarray(t)
+    if a.dtype != np.uint8:
+        raise TypeError("text must be uint8")
+    return a
+
+
+def _p(a: np.ndarray, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def sa(text, parallel: bool = False) -> np.ndarray:
+    """Suffix array (uint32) by plain prefix doubling."""
+    t = _text(text)
+    out = np.empty(t.size, dtype=np.uint32)
+    rc = _lib(parallel).oracle_sa(_p(t, ctypes.c_uint8), t.size, _p(out, ctypes.c_uint32))
+    if rc:
+        raise ValueError("text too long for 32-bit suffix array")
+    return out
+
+
+def pd_names(text, steps: int) -> tuple[np.ndarray, int]:
+    """Names after ``steps`` doubling sorts, and the prefix length they resolve."""
+    t = _text(text)
+    out = np.empty(t.size, dtype=np.uint32)
+    h = ctypes.c_uint64(0)
+    rc = _lib().oracle_pd_names(_p(t, ctypes.c_uint8), t.size, steps,
+                                _p(out, ctypes.c_uint32), ctypes.byref(h))
+    if rc:
+        raise ValueError("bad arguments")
+    return out, int(h.value)
+
+
+def prefix_ranks(text, h: int) -> np.ndarray:
+    """Closed-form names for prefix length ``h`` (1-based head ranks)."""
+    t = _text(text)
+    out = np.empty(t.size, dtype=np.uint32)
+    rc = _lib().oracle_prefix_ranks(_p(t, ctypes.c_uint8), t.size, h, _p(out, ctypes.c_uint32))
+    if rc:
+        raise ValueError("bad arguments")
+    return out
+
+
+def brute_sa(text) -> np.ndarray:
+    """Suffix array straight from the definition (for small n)."""
+    t = _text(text)
+    out = np.empty(t.size, dtype=np.uint32)
+    _lib().oracle_brute_sa(_p(t, ctypes.c_uint8), t.size, _p(out, ctypes.c_uint32))
+    return out
+
+
+def check_sa(text, sa_arr) -> tuple[int, int]:
+    """Linear-time check. Returns (status, where): 0 ok, 1 not a permutation,
+    2 adjacent-order violation at SA position ``where``."""
+    t = _text(text)
+    a = np.asarray(sa_arr)
+    if a.dtype in (np.int32, np.uint32):
+        s = np.ascontiguousarray(a).view(np.uint32)
+    else:
+        if a.size and (a.min() < 0 or a.max() >= 2**32):
+            return 1, int(np.argmax((a < 0) | (a >= 2**32)))
+        s = np.ascontiguousarray(a, dtype=np.uint32)
+    if s.size != t.size:
+        return 1, 0
+    where = ctypes.c_uint64(0)
+    rc = _lib().oracle_check_sa(_p(t, ctypes.c_uint8), t.size, _p(s, ctypes.c_uint32),
+                                ctypes.byref(where))
+    return int(rc), int(where.value)
+
+
+def num_threads(parallel: bool = True) -> int:
+    return int(_lib(parallel).oracle_num_threads())

@@ -1,0 +1,216 @@
+// Oracle for suffix-array construction by prefix doubling.
+//
+// TEST INFRASTRUCTURE ONLY. Nothing in the product path may call, link or load
+// this file; only the tests, the smoke check and the CPU-baseline leg of the
+// benchmark do. It shares no code, header, table or helper with the HIP library.
+//
+// Everything here is plain, single-pass-per-step C++17 on the host. Sorting is
+// std::sort (built with -D_GLIBCXX_PARALLEL it becomes the GNU parallel sort,
+// which is how the multi-core CPU baseline is produced; the arithmetic is the
+// same). Ranks and indices are uint32_t, so n < 2^32.
+//
+// Conventions (paper, Section 2, problem statement and Section 2.1):
+//  * A suffix i is T[i, n). Bytes compare as unsigned 8-bit values, and a proper
+//    prefix is smaller than any extension of it: the past-the-end sentinel `$`
+//    is smaller than every byte, including 0x00.
+//  * Names are 1-based head ranks: the name of a suffix for prefix length h is
+//    1 + the number of suffixes whose length-h prefix is strictly smaller. The
+//    value 0 is reserved for the sentinel `$` (the paper's worked examples give
+//    the smallest group the name 0 while also using 0 as the sentinel name; the
+//    two would collide, so every name here is the paper's name + 1).
+//
+// Parity status: every function below is pinned by tests that do not call it
+// to produce their expected values (paper worked examples, brute force written
+// independently in Python, closed forms, and planted-mistake mutants).
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <numeric>
+#include <utility>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// One item of the paper's triple array S: a text position and its name pair.
+struct Triple {
+  uint64_t pair;  // (r0 << 32) | r1 ; r1 == 0 is the sentinel
+  uint32_t i;
+};
+
+// Sort S by name pair, then give every item the name 1 + (position of the last
+// item whose name pair differs from its predecessor). This is the paper's
+// name-comparison function (Alg. 2) followed by the max-PrefixSum of Alg. 1,
+// shifted to 1-based names. Returns the number of distinct name pairs.
+uint64_t sort_and_name(std::vector<Triple>& S, uint32_t* name) {
+  std::sort(S.begin(), S.end(),
+            [](const Triple& a, const Triple& b) { return a.pair < b.pair; });
+  uint64_t last_head = 0, distinct = 0;
+  for (uint64_t p = 0; p < S.size(); ++p) {
+    if (p == 0 || S[p].pair != S[p - 1].pair) {
+      last_head = p;
+      ++distinct;
+    }
+    name[S[p].i] = static_cast<uint32_t>(last_head + 1);
+  }
+  return distinct;
+}
+
+// Prefix doubling (Alg. 1) with the pairing of Alg. 4: the name of suffix i+h is
+// read from the partial inverse suffix array (the name array indexed by text
+// position), or is the sentinel 0 when i+h >= n.
+// Runs at most `max_steps` sorts (0 = until every name is distinct) and leaves
+// the names in `name`; *h_out receives the prefix length those names resolve.
+void prefix_doubling(const uint8_t* T, uint64_t n, uint64_t max_steps,
+                     uint32_t* name, uint64_t* h_out) {
+  std::vector<Triple> S(n);
+  // Initial triples (i, T[i], T[i+1]) with T[n] = `$`. Characters are shifted by
+  // one so that 0 stays the sentinel.
+  for (uint64_t i = 0; i < n; ++i) {
+    uint64_t c0 = uint64_t(T[i]) + 1;
+    uint64_t c1 = (i + 1 < n) ? uint64_t(T[i + 1]) + 1 : 0;
+    S[i] = Triple{(c0 << 32) | c1, static_cast<uint32_t>(i)};
+  }
+  uint64_t h = 2;  // prefix length resolved by the names after the next sort
+  uint64_t steps = 0;
+  for (;;) {
+    uint64_t distinct = sort_and_name(S, name);
+    ++steps;
+    if (distinct == n) break;                       // every name is unique
+    if (max_steps != 0 && steps >= max_steps) break;
+    // Next name pairs: own name and the name h positions to the right.
+    for (uint64_t i = 0; i < n; ++i) {
+      uint64_t r0 = name[i];
+      uint64_t r1 = (i + h < n) ? name[i + h] : 0;
+      S[i] = Triple{(r0 << 32) | r1, static_cast<uint32_t>(i)};
+    }
+    h *= 2;
+  }
+  if (h_out) *h_out = h;
+}
+
+// Padded-prefix comparison: T[i, min(i+h, n)) versus T[j, min(j+h, n)), unsigned
+// bytes, a proper prefix being the smaller. Returns <0, 0, >0.
+int cmp_prefix(const uint8_t* T, uint64_t n, uint64_t h, uint64_t i, uint64_t j) {
+  uint64_t li = std::min<uint64_t>(h, n - i);
+  uint64_t lj = std::min<uint64_t>(h, n - j);
+  uint64_t l = std::min(li, lj);
+  int c = (l > 0) ? std::memcmp(T + i, T + j, l) : 0;
+  if (c != 0) return c;
+  if (li == lj) return 0;
+  return li < lj ? -1 : 1;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Suffix array of T[0, n) by plain prefix doubling (no discarding): every
+// suffix is re-sorted every round until all names are distinct; then
+// SA[name[i] - 1] = i. Returns 0, or 1 if n >= 2^32.
+int oracle_sa(const uint8_t* T, uint64_t n, uint32_t* SA) {
+  if (n >= (uint64_t(1) << 32)) return 1;
+  if (n == 0) return 0;
+  if (n == 1) {
+    SA[0] = 0;
+    return 0;
+  }
+  std::vector<uint32_t> name(n);
+  prefix_doubling(T, n, 0, name.data(), nullptr);
+  for (uint64_t i = 0; i < n; ++i) SA[name[i] - 1] = static_cast<uint32_t>(i);
+  return 0;
+}
+
+// Names after `steps` doubling sorts (steps >= 1; the first sort resolves
+// prefix length 2, each further one doubles it), or after the sort that makes
+// every name distinct if that comes first. *h_out = prefix length resolved.
+int oracle_pd_names(const uint8_t* T, uint64_t n, uint64_t steps, uint32_t* names,
+                    uint64_t* h_out) {
+  if (n >= (uint64_t(1) << 32) || steps == 0) return 1;
+  if (n == 0) {
+    *h_out = 0;
+    return 0;
+  }
+  if (n == 1) {
+    names[0] = 1;
+    *h_out = 2;
+    return 0;
+  }
+  prefix_doubling(T, n, steps, names, h_out);
+  return 0;
+}
+
+// Closed form of the names for prefix length h: ranks[i] = 1 + #{ j :
+// pad_h(j) < pad_h(i) }, where pad_h(i) is T[i, i+h) cut at n (the sentinel
+// ending it). Computed by sorting positions with the padded-prefix comparison.
+int oracle_prefix_ranks(const uint8_t* T, uint64_t n, uint64_t h, uint32_t* ranks) {
+  if (n >= (uint64_t(1) << 32) || h == 0) return 1;
+  std::vector<uint32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0u);
+  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+    return cmp_prefix(T, n, h, a, b) < 0;
+  });
+  uint64_t head = 0;
+  for (uint64_t p = 0; p < n; ++p) {
+    if (p > 0 && cmp_prefix(T, n, h, idx[p - 1], idx[p]) != 0) head = p;
+    ranks[idx[p]] = static_cast<uint32_t>(head + 1);
+  }
+  return 0;
+}
+
+// Brute force from the definition: sort all suffix start positions with a
+// lexicographic comparison of unsigned bytes (shorter prefix first).
+int oracle_brute_sa(const uint8_t* T, uint64_t n, uint32_t* SA) {
+  if (n >= (uint64_t(1) << 32)) return 1;
+  std::vector<uint32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0u);
+  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+    return std::lexicographical_compare(T + a, T + n, T + b, T + n);
+  });
+  std::copy(idx.begin(), idx.end(), SA);
+  return 0;
+}
+
+// Linear-time suffix array check (Burkhardt and Kaerkkaeinen, CPM 2003): SA is
+// the suffix array of T iff it is a permutation of [0, n) and for every
+// adjacent pair (a, b) = (SA[j], SA[j+1]):  T[a] < T[b], or T[a] == T[b] and
+// R[a+1] < R[b+1], where R is the inverse of the SA under test (1-based) and
+// R[n] = 0 stands for the empty suffix.
+// Returns 0 if correct, 1 if not a permutation, 2 if an order violation;
+// *where receives the offending position of SA.
+int oracle_check_sa(const uint8_t* T, uint64_t n, const uint32_t* SA, uint64_t* where) {
+  *where = 0;
+  if (n >= (uint64_t(1) << 32)) return 1;
+  std::vector<uint32_t> R(n + 1, 0);
+  for (uint64_t j = 0; j < n; ++j) {
+    uint64_t s = SA[j];
+    if (s >= n || R[s] != 0) {
+      *where = j;
+      return 1;
+    }
+    R[s] = static_cast<uint32_t>(j + 1);
+  }
+  for (uint64_t j = 0; j + 1 < n; ++j) {
+    uint64_t a = SA[j], b = SA[j + 1];
+    bool ok = (T[a] < T[b]) || (T[a] == T[b] && R[a + 1] < R[b + 1]);
+    if (!ok) {
+      *where = j;
+      return 2;
+    }
+  }
+  return 0;
+}
+
+// Number of threads the parallel sort may use (1 in the sequential build).
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+"""Compact pin set for the oracle, run in its own interpreter.
+
+Usage: python oracle_pins.py [path/to/liboracle_variant.so]
+Exits 0 when every pin holds for the given build of the oracle (default: the
+normal build), 1 otherwise. Used to show that planted mistakes in the oracle
+source are caught. Expected values come from the paper's examples, closed forms
+and a brute-force sort written here in Python, never from the oracle.
+"""
+
+import ctypes
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import oracle  # noqa: E402
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+
+def py_brute_sa(t: bytes):
+    return sorted(range(len(t)), key=lambda i: t[i:])
+
+
+def py_prefix_ranks(t: bytes, h: int):
+    pads = [t[i:i + h] for i in range(len(t))]
+    first = {}
+    for pos, p in enumerate(sorted(pads)):
+        first.setdefault(p, pos)
+    return [first[p] + 1 for p in pads]
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+def pins_pass() -> bool:
+    for fixture in ("paper_example1_bdacbdacb.json", "banana.json"):
+        g = load(fixture)
+        t = g["text"].encode()
+        if oracle.sa(t).tolist() != g["sa"] or oracle.brute_sa(t).tolist() != g["sa"]:
+            return False
+    g = load("paper_example1_bdacbdacb.json")
+    t = g["text"].encode()
+    for steps, h in ((1, 2), (2, 4)):
+        names, h_got = oracle.pd_names(t, steps)
+        if h_got != h or names.tolist() != py_prefix_ranks(t, h):
+            return False
+        if oracle.prefix_ranks(t, h).tolist() != py_prefix_ranks(t, h):
+            return False
+    if oracle.sa(b"a\0\0").tolist() != [2, 1, 0]:
+        return False
+    m = 9
+    if oracle.sa(b"ab" * m).tolist() != list(range(2 * m - 2, -1, -2)) + list(range(2 * m - 1, 0, -2)):
+        return False
+    rng = np.random.default_rng(11)
+    for _ in range(60):
+        n = int(rng.integers(2, 120))
+        t = rng.integers(0, int(rng.choice([2, 4, 256])), n).astype(np.uint8)
+        want = py_brute_sa(t.tobytes())
+        if oracle.sa(t).tolist() != want or oracle.brute_sa(t).tolist() != want:
+            return False
+        if oracle.prefix_ranks(t, 3).tolist() != py_prefix_ranks(t.tobytes(), 3):
+            return False
+        names, h = oracle.pd_names(t, 2)
+        if names.tolist() != py_prefix_ranks(t.tobytes(), h):
+            return False
+        bad = np.array(want, dtype=np.uint32)
+        j = int(rng.integers(0, n - 1))
+        bad[j], bad[j + 1] = bad[j + 1], bad[j]
+        if oracle.check_sa(t, bad)[0] != 2:
+            return False
+    return True
+
+
+if __name__ == "__main__":
+    if len(sys.argv) > 1:
+        oracle._libs[False] = oracle.configure(ctypes.CDLL(sys.argv[1]))
+    try:
+        ok = pins_pass()
+    except Exception:
+        ok = False
+    sys.exit(0 if ok else 1)

@@ -1,0 +1,235 @@
+"""Pins for the CPU oracle (no GPU).
+
+Every expected value here comes from outside the oracle: the paper's worked
+examples (fixtures under tests/golden, each with its citation), a brute-force
+suffix sort written independently in Python, closed forms for structured texts,
+and planted mistakes (mutants of the oracle source) that these pins must catch.
+"""
+
+import itertools
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+PINS = os.path.join(os.path.dirname(__file__), "oracle_pins.py")
+
+
+def py_brute_sa(t: bytes):
+    """Definition of the suffix array: Python bytes compare as unsigned bytes and
+    a proper prefix is smaller than its extensions."""
+    return [i for i in sorted(range(len(t)), key=lambda i: t[i:])]
+
+
+def py_prefix_ranks(t: bytes, h: int):
+    """Closed form: 1 + number of positions whose padded length-h prefix is smaller."""
+    pads = [t[i:i + h] for i in range(len(t))]
+    order = sorted(pads)
+    first = {}
+    for pos, p in enumerate(order):
+        first.setdefault(p, pos)
+    return [first[p] + 1 for p in pads]
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# --------------------------------------------------------------------------
+# Paper worked examples and the textbook example.
+
+@pytest.mark.parametrize("fixture", ["paper_example1_bdacbdacb.json",
+                                     "paper_example3_dbacbacbd.json", "banana.json"])
+def test_golden_sa(fixture):
+    g = load(fixture)
+    t = g["text"].encode()
+    assert oracle.sa(t).tolist() == g["sa"]
+    assert oracle.brute_sa(t).tolist() == g["sa"]
+    assert oracle.check_sa(t, g["sa"]) == (0, 0)
+
+
+def test_golden_round_names():
+    """Names printed after each doubling iteration (Examples 1 and 2) equal both
+    the oracle's doubling names and its closed form, shifted to 1-based."""
+    g = load("paper_example1_bdacbdacb.json")
+    t = g["text"].encode()
+    for step, (h, tuples) in enumerate(sorted(g["names_printed"].items(),
+                                              key=lambda kv: int(kv[0])), start=1):
+        h = int(h)
+        want = np.zeros(len(t), dtype=np.uint32)
+        for pos, name in tuples:
+            want[pos] = name + 1
+        names, h_got = oracle.pd_names(t, step)
+        assert h_got == h
+        assert names.tolist() == want.tolist()
+        assert oracle.prefix_ranks(t, h).tolist() == want.tolist()
+
+
+# --------------------------------------------------------------------------
+# Brute force on small inputs.
+
+def test_all_binary_strings():
+    for n in range(0, 13):
+        for bits in itertools.product(b"ab", repeat=n):
+            t = bytes(bits)
+            want = py_brute_sa(t)
+            assert oracle.sa(t).tolist() == want, t
+    # spot-check length 14 (exhaustive 2^14 also passes but costs time)
+    rng = np.random.default_rng(7)
+    for _ in range(500):
+        t = bytes(rng.choice([97, 98], 14).astype(np.uint8))
+        assert oracle.sa(t).tolist() == py_brute_sa(t)
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 4, 96, 256])
+def test_random_strings(sigma):
+    rng = np.random.default_rng(100 + sigma)
+    for _ in range(300):
+        n = int(rng.integers(0, 400))
+        t = rng.integers(0, sigma, n).astype(np.uint8)
+        if sigma == 96:
+            t = np.where(t == 0, 10, t + 31).astype(np.uint8)
+        tb = t.tobytes()
+        want = py_brute_sa(tb)
+        assert oracle.sa(t).tolist() == want
+        assert oracle.brute_sa(t).tolist() == want
+        assert oracle.check_sa(t, want) == (0, 0)
+
+
+def test_prefix_ranks_closed_form():
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        n = int(rng.integers(1, 200))
+        sigma = int(rng.choice([1, 2, 3, 256]))
+        t = rng.integers(0, sigma, n).astype(np.uint8).tobytes()
+        h = int(rng.integers(1, 40))
+        assert oracle.prefix_ranks(t, h).tolist() == py_prefix_ranks(t, h)
+
+
+def test_doubling_names_match_closed_form():
+    rng = np.random.default_rng(4)
+    for _ in range(100):
+        n = int(rng.integers(2, 300))
+        t = rng.integers(0, 3, n).astype(np.uint8).tobytes()
+        for steps in (1, 2, 3, 4):
+            names, h = oracle.pd_names(t, steps)
+            assert names.tolist() == py_prefix_ranks(t, h)
+
+
+# --------------------------------------------------------------------------
+# Closed forms and special cases.
+
+def test_edge_sizes():
+    assert oracle.sa(b"").tolist() == []
+    assert oracle.sa(b"x").tolist() == [0]
+    assert oracle.sa(b"ab").tolist() == [0, 1]
+    assert oracle.sa(b"ba").tolist() == [1, 0]
+    assert oracle.sa(b"aa").tolist() == [1, 0]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 17, 1000, 4097])
+def test_unary(n):
+    assert oracle.sa(b"a" * n).tolist() == list(range(n - 1, -1, -1))
+
+
+def test_monotone():
+    inc = bytes(range(256))
+    assert oracle.sa(inc).tolist() == list(range(256))
+    dec = bytes(range(255, -1, -1))
+    assert oracle.sa(dec).tolist() == list(range(255, -1, -1))
+
+
+@pytest.mark.parametrize("m", [1, 2, 5, 64, 333])
+def test_ab_repeats(m):
+    # (ab)^m: the a-suffixes in order of increasing length, then the b-suffixes.
+    want = list(range(2 * m - 2, -1, -2)) + list(range(2 * m - 1, 0, -2))
+    assert oracle.sa(b"ab" * m).tolist() == want
+
+
+def test_nul_bytes():
+    assert oracle.sa(b"a\0\0").tolist() == [2, 1, 0]
+    assert oracle.sa(b"\0\0\0\0").tolist() == [3, 2, 1, 0]
+    t = b"\0a\0a\0"
+    assert oracle.sa(t).tolist() == py_brute_sa(t)
+
+
+# --------------------------------------------------------------------------
+# Checker.
+
+def test_checker_rejects():
+    rng = np.random.default_rng(9)
+    for _ in range(300):
+        n = int(rng.integers(2, 200))
+        t = rng.integers(0, int(rng.choice([2, 4, 256])), n).astype(np.uint8)
+        good = np.array(py_brute_sa(t.tobytes()), dtype=np.uint32)
+        assert oracle.check_sa(t, good) == (0, 0)
+        bad = good.copy()
+        j = int(rng.integers(0, n - 1))
+        bad[j], bad[j + 1] = bad[j + 1], bad[j]
+        assert oracle.check_sa(t, bad)[0] == 2
+        dup = good.copy()
+        dup[j] = dup[j + 1]
+        assert oracle.check_sa(t, dup)[0] == 1
+        rng_perm = rng.permutation(n).astype(np.uint32)
+        if not np.array_equal(rng_perm, good):
+            assert oracle.check_sa(t, rng_perm)[0] == 2
+
+
+# --------------------------------------------------------------------------
+# Planted mistakes: each mutant of the oracle source must fail some pin above.
+
+MUTANTS = {
+    "sentinel_largest": ("uint64_t r1 = (i + h < n) ? name[i + h] : 0;",
+                         "uint64_t r1 = (i + h < n) ? name[i + h] : 0xFFFFFFFFull;"),
+    "unshifted_next": ("? uint64_t(T[i + 1]) + 1 : 0;", "? uint64_t(T[i + 1]) : 0;"),
+    "zero_based_names": ("name[S[p].i] = static_cast<uint32_t>(last_head + 1);",
+                         "name[S[p].i] = static_cast<uint32_t>(last_head);"),
+    "offset_off_by_one": ("(i + h < n) ? name[i + h] : 0;", "(i + h < n) ? name[i + h - 1] : 0;"),
+    "dropped_second_rank": ("S[i] = Triple{(r0 << 32) | r1, static_cast<uint32_t>(i)};",
+                            "S[i] = Triple{(r0 << 32), static_cast<uint32_t>(i)};"),
+    "early_stop": ("if (distinct == n) break;", "if (distinct + 1 >= n) break;"),
+    "no_doubling": ("h *= 2;", "h += 1;"),
+    "prefix_longer_first": ("return li < lj ? -1 : 1;", "return li < lj ? 1 : -1;"),
+    "checker_loose": ("bool ok = (T[a] < T[b]) ||", "bool ok = (T[a] <= T[b]) ||"),
+    "brute_signed": ("return std::lexicographical_compare(T + a, T + n, T + b, T + n);",
+                     "return std::lexicographical_compare((const signed char*)T + a, "
+                     "(const signed char*)T + n, (const signed char*)T + b, "
+                     "(const signed char*)T + n);"),
+}
+
+
+def _run_pins(so_path=None, timeout=120):
+    """Run the compact pin set in a fresh interpreter (a mutant may not
+    terminate; a time-out counts as caught)."""
+    cmd = [sys.executable, PINS]
+    if so_path:
+        cmd.append(str(so_path))
+    try:
+        r = subprocess.run(cmd, timeout=timeout, capture_output=True, text=True)
+    except subprocess.TimeoutExpired:
+        return False
+    return r.returncode == 0
+
+
+def test_unmutated_pins_pass():
+    assert _run_pins()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, tmp_path):
+    old, new = MUTANTS[name]
+    src = open(oracle._SRC).read()
+    assert src.count(old) == 1, f"mutation site for {name} not found"
+    mpath = tmp_path / "mutant.cpp"
+    mpath.write_text(src.replace(old, new))
+    so = tmp_path / "libmutant.so"
+    subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-o", str(so), str(mpath)],
+                   check=True)
+    assert not _run_pins(so, timeout=15), f"mutant {name} survived the pins"
