@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark: suffix-array construction throughput on one MI355X.
+
+One step = one complete sa_build (every doubling round: key packing, radix
+sort, re-rank / ISA scatter / discard) of the 256 MiB order-3 Markov text over
+96 printable bytes, with the text already resident in HBM. Prints one JSON line
+with Msuffixes/s, the HBM roofline of the dominant kernel (the radix-sort
+sweep) measured with HIP events inside the timed steps, and the CPU oracle
+timed on a bounded sample on the host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+WORKLOADS = {
+    "markov_256m": "order-3 Markov text, 96 printable bytes, Dirichlet(0.1) rows, n=2^28",
+    "dna_1m": "uniform ACGT text, seed 0, n=2^20",
+    "repetitive_1g": "256 KiB base x 4096 copies, 1e-4 substitutions, n=2^30",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_03007_amd", "csrc", "sa_kernels.hip")
+
+
+def make_text(name: str):
+    import workloads as W
+    if name == "markov_256m":
+        return W.markov3(1 << 28, chain_seed=2)
+    if name == "dna_1m":
+        return W.dna(1 << 20, seed=0)
+    if name == "repetitive_1g":
+        return W.repetitive()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per sort-sweep launch from committed rocprofv3 counter runs,
+    or None when absent or taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(text, sample: int):
+    import oracle
+    s = text[:sample].copy()
+    t0 = time.perf_counter()
+    oracle.sa(s, parallel=True)
+    dt = time.perf_counter() - t0
+    return {
+        "value": round(s.size / dt / 1e6, 3),
+        "unit": "Msuffixes/s",
+        "cores": oracle.num_threads(parallel=True),
+        "kind": "oracle",
+        "sample": f"first {s.size} bytes of the same text, plain prefix doubling "
+                  f"(GNU parallel std::sort), {dt:.2f} s",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="markov_256m", choices=sorted(WORKLOADS))
+    ap.add_argument("--cpu-sample", type=int, default=1 << 24,
+                    help="bytes of the text the CPU oracle is timed on (0 = skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="MiB of a plain device copy to run after the steps (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(a single text does not shard without an all-to-all exchange step).",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1610_03007_amd import SuffixArrayBuilder
+
+    t_gen = time.perf_counter()
+    text = make_text(args.workload)
+    n = int(text.size)
+    print(f"[bench] workload {args.workload} n={n} generated in "
+          f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda", 0)
+    d_text = torch.from_numpy(text).to(dev)
+    d_sa = torch.empty(n, dtype=torch.int32, device=dev)
+    b = SuffixArrayBuilder(0)
+
+    for _ in range(args.warmup):
+        b.build(d_text, out=d_sa)
+    torch.cuda.synchronize()
+    print(f"[bench] warmup done: {b.last_info()}", file=sys.stderr, flush=True)
+
+    b.reset_stats()
+    b.set_trace(True)
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        b.build(d_text, out=d_sa)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.set_trace(False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    info = b.last_info()
+    stats = b.kernel_stats()
+
+    ms_per_step = gpu_ms / args.steps
+    value = n * args.steps / (gpu_ms / 1e3) / 1e6
+
+    sweep = stats["sort_pass"]
+    achieved = sweep["bytes"] / (sweep["ms"] / 1e3) / 1e9 if sweep["ms"] > 0 else 0.0
+    per_launch = sweep["bytes"] / max(1, sweep["launches"])
+    traffic = measured_traffic(args.workload)
+
+    result = {
+        "metric": "Msuffixes/s on 1 GPU + HBM roofline %; batched vs per-text; p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "Msuffixes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "description": WORKLOADS[args.workload],
+            "n": n,
+            "rounds": info["rounds"],
+            "active_per_round": info["active"],
+            "sigma": info["sigma"],
+            "chars_round0": info["chars0"],
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "onesweep_pass_kernel",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "algorithmic_bytes_per_launch": round(per_launch),
+            "launches": sweep["launches"],
+            "avg_launch_us": round(sweep["ms"] * 1e3 / max(1, sweep["launches"]), 2),
+        },
+        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in stats.items()},
+        "wall_s": round(wall, 3),
+    }
+    if args.cpu_sample > 0:
+        result["cpu_baseline"] = cpu_baseline(text, min(args.cpu_sample, n))
+    else:
+        result["cpu_baseline"] = None
+
+    if args.calibrate_copy > 0:
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["calibrate_copy_bytes"] = nbytes
+
+    b.close()
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,135 @@
+/*
+ * sa.h -- C ABI of the MI355X (gfx950) suffix-array library.
+ *
+ * The library builds suffix arrays by prefix doubling with discarding
+ * (Bingmann, Gog, Kurpicz, "Scalable Construction of Text Indexes",
+ * arXiv 1610.03007, Section 2.1, Alg. 5 and 6, with the inverse-suffix-array
+ * pairing of Alg. 4) entirely on one GPU with hand-written HIP kernels.
+ *
+ * Problem statement (Section 2): for a text T of length n over an alphabet,
+ * suffix i is T[i, n); the suffix array SA is the permutation of [0, n) that
+ * lists the suffixes in lexicographic order, and the inverse suffix array ISA
+ * is its inverse. Here characters are bytes compared as unsigned values, and a
+ * proper prefix is smaller than every extension of it (the end of the text
+ * acts as a sentinel below every byte). The result is unique and bit-exact.
+ *
+ * Conventions for every entry point:
+ *   - All functions return sa_status; nothing throws across the ABI.
+ *   - Pointers named d_* are device pointers (hipMalloc or a PyTorch CUDA
+ *     tensor) on the context's device; h_* are host pointers. The caller owns
+ *     every buffer it passes; the context owns its workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work
+ *     is enqueued on it; the call returns after the result is complete on that
+ *     stream (the call synchronizes with the stream once per doubling round).
+ *   - On an error, outputs are undefined and the context stays usable.
+ *   - A context must be used by one host thread at a time.
+ */
+#ifndef SA_MI355X_H
+#define SA_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SA_OK = 0,
+  SA_EINVAL = 1,   /* null pointer, bad size or flag, sigma outside [1, 256] */
+  SA_ENOMEM = 2,   /* a workspace allocation failed */
+  SA_ETOOBIG = 3,  /* n >= 2^32 (ranks and SA entries are 32-bit) */
+  SA_EDEVICE = 4,  /* a HIP call failed or a kernel reported an error */
+  SA_EBUSY = 5     /* the resource is in use */
+} sa_status;
+
+typedef struct sa_ctx sa_ctx;
+
+/* Creates a context on HIP device `device`. The workspace grows on demand and
+ * is kept for later calls. tune_cache_json: optional path of a tuning cache
+ * (may be NULL). */
+sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json);
+
+/* Frees the context and its device workspace. NULL is accepted. */
+sa_status sa_ctx_destroy(sa_ctx* ctx);
+
+/* Suffix array of one text (Section 2 problem statement; method of Section
+ * 2.1, Alg. 5).
+ *   d_text: device u8[n], the text.
+ *   n:      text length; n = 0 is a no-op; n >= 2^32 gives SA_ETOOBIG.
+ *   sigma:  alphabet-size hint in [1, 256]; the result never depends on it
+ *           (the library measures the alphabet itself).
+ *   d_sa:   device u32[n], receives the suffix array (may be read through an
+ *           int32 view; every value is < n).
+ * Needs about 37 bytes of device workspace per text byte. */
+sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
+                   uint32_t* d_sa, void* stream);
+
+/* Per-build diagnostics of the last sa_build / sa_build_rounds call. */
+#define SA_MAX_ROUNDS 64
+typedef struct {
+  uint64_t n;
+  uint32_t rounds;        /* doubling rounds run, round 0 included */
+  uint32_t sigma;         /* distinct byte values in the text */
+  uint32_t code_bits;     /* bits per character in a round-0 key */
+  uint32_t chars0;        /* characters per round-0 key: the first prefix length */
+  uint64_t prefix_len;    /* prefix length the ranks resolve after the last round */
+  uint64_t active[SA_MAX_ROUNDS];       /* suffixes sorted in round k */
+  uint32_t passes_run[SA_MAX_ROUNDS];   /* radix passes executed in round k */
+  uint32_t key_bits[SA_MAX_ROUNDS];     /* key bits sorted in round k */
+} sa_build_info;
+
+sa_status sa_last_build_info(const sa_ctx* ctx, sa_build_info* out);
+
+/* Runs at most `max_rounds` doubling rounds (0 = until done) and exposes the
+ * intermediate state, for checking the method round by round.
+ *   d_sa:  device u32[n]; positions finalised so far hold their suffix.
+ *   d_isa: device u32[n] (may be NULL); receives the names after the last round
+ *          run: ISA[i] = 1 + the number of suffixes whose prefix of length
+ *          info.prefix_len is smaller than that of suffix i (Section 2.1,
+ *          lexicographic names, here 1-based with 0 kept for the sentinel).
+ * Other arguments as sa_build. Results are in sa_last_build_info. */
+sa_status sa_build_rounds(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t max_rounds,
+                          uint32_t* d_sa, uint32_t* d_isa, void* stream);
+
+/* The sorting step on its own (the Sort of Alg. 1 and 5): stable LSD radix
+ * sort of `count` (key, value) pairs in place, ordered by the low `key_bits`
+ * bits of the key (1..64; higher bits must be zero). d_keys: device u64[count],
+ * d_vals: device u32[count]. */
+sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, uint64_t count,
+                              uint32_t key_bits, void* stream);
+
+/* Device workspace a context needs for a text of n bytes. */
+size_t sa_workspace_bytes(uint64_t n);
+
+/* Per-kernel timing. With tracing on, every kernel launch of a build is
+ * bracketed by HIP events on the build's stream; the totals accumulate until
+ * reset. `kind` selects the kernel (SA_KERNEL_*). bytes are the algorithmic
+ * bytes of those launches (what the step must read and write, random 4-byte
+ * accesses counted at 4 bytes). */
+enum {
+  SA_KERNEL_SORT_PASS = 0,   /* one radix-sort sweep */
+  SA_KERNEL_HISTOGRAM = 1,   /* up-front digit histograms */
+  SA_KERNEL_RERANK = 2,      /* re-rank, ISA scatter, finalise, compact */
+  SA_KERNEL_PACK_TEXT = 3,   /* round-0 keys from the text */
+  SA_KERNEL_PACK_PAIRS = 4,  /* round >= 1 keys (ISA gather) */
+  SA_KERNEL_OTHER = 5,       /* alphabet, plan, fills */
+  SA_KERNEL_KINDS = 6
+};
+typedef struct {
+  uint64_t launches;
+  double ms;
+  double bytes;
+} sa_kernel_stats;
+
+sa_status sa_ctx_set_trace(sa_ctx* ctx, int on);
+sa_status sa_ctx_reset_stats(sa_ctx* ctx);
+sa_status sa_ctx_get_kernel_stats(const sa_ctx* ctx, int kind, sa_kernel_stats* out);
+
+const char* sa_strerror(sa_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SA_MI355X_H */

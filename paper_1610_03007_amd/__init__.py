@@ -1,0 +1,136 @@
+"""Suffix-array construction on MI355X (gfx950) by prefix doubling with discarding.
+
+Python face of the HIP library ``libsa_mi355x.so`` (C ABI in include/sa.h).
+Texts and suffix arrays are PyTorch CUDA tensors; every step runs in the
+library's kernels on the tensor's device and the current stream.
+
+    >>> from paper_1610_03007_amd import SuffixArrayBuilder
+    >>> b = SuffixArrayBuilder()
+    >>> sa = b.build(torch.frombuffer(bytearray(b"banana"), dtype=torch.uint8).cuda())
+    >>> sa.tolist()
+    [5, 3, 1, 0, 4, 2]
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _native
+from ._native import SAError, check
+
+__all__ = ["SuffixArrayBuilder", "SAError", "workspace_bytes"]
+
+
+def _stream_handle(device: torch.device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace_bytes(n: int) -> int:
+    """Device workspace (bytes) a build of an n-byte text needs."""
+    return int(_native.lib().sa_workspace_bytes(n))
+
+
+class SuffixArrayBuilder:
+    """Owns a library context (device workspace, kernel statistics) on one GPU."""
+
+    def __init__(self, device: int | torch.device | None = None, tune_cache: str | None = None):
+        if device is None:
+            device = torch.cuda.current_device()
+        self.device = torch.device("cuda", device if isinstance(device, int) else device.index)
+        self._lib = _native.lib()
+        self._ctx = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_ctx_create(ctypes.byref(self._ctx), self.device.index,
+                                          tune_cache.encode() if tune_cache else None),
+                  "sa_ctx_create")
+
+    def close(self) -> None:
+        if self._ctx:
+            self._lib.sa_ctx_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order varies
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _text(self, text: torch.Tensor) -> torch.Tensor:
+        if not isinstance(text, torch.Tensor) or text.dtype != torch.uint8:
+            raise TypeError("text must be a torch.uint8 tensor")
+        if text.device != self.device:
+            raise ValueError(f"text is on {text.device}, builder on {self.device}")
+        return text.contiguous().view(-1)
+
+    def _out(self, out: torch.Tensor | None, n: int, name: str) -> torch.Tensor:
+        if out is None:
+            return torch.empty(n, dtype=torch.int32, device=self.device)
+        if out.dtype != torch.int32 or out.numel() != n or not out.is_contiguous() \
+                or out.device != self.device:
+            raise ValueError(f"{name} must be a contiguous int32 tensor of {n} elements on "
+                             f"{self.device}")
+        return out
+
+    def build(self, text: torch.Tensor, out: torch.Tensor | None = None,
+              sigma: int = 256) -> torch.Tensor:
+        """Suffix array of ``text`` as int32 (values < n, bit pattern of the u32 SA)."""
+        t = self._text(text)
+        n = t.numel()
+        sa = self._out(out, n, "out")
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_build(self._ctx, ctypes.c_void_p(t.data_ptr()), n, sigma,
+                                     ctypes.c_void_p(sa.data_ptr()), _stream_handle(self.device)),
+                  "sa_build")
+        return sa
+
+    def build_rounds(self, text: torch.Tensor, max_rounds: int):
+        """Run at most ``max_rounds`` doubling rounds. Returns (sa, isa, info):
+        the partially finalised SA, the names after the last round run, and the
+        build diagnostics (``info['prefix_len']`` is the prefix length the names
+        resolve)."""
+        t = self._text(text)
+        n = t.numel()
+        sa = torch.zeros(n, dtype=torch.int32, device=self.device)
+        isa = torch.zeros(n, dtype=torch.int32, device=self.device)
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_build_rounds(self._ctx, ctypes.c_void_p(t.data_ptr()), n,
+                                            max_rounds, ctypes.c_void_p(sa.data_ptr()),
+                                            ctypes.c_void_p(isa.data_ptr()),
+                                            _stream_handle(self.device)), "sa_build_rounds")
+        return sa, isa, self.last_info()
+
+    def radix_sort_pairs(self, keys: torch.Tensor, vals: torch.Tensor, key_bits: int = 64):
+        """Stable sort of (int64 key bits as u64, int32 value bits as u32) pairs
+        in place by the low ``key_bits`` bits of the key."""
+        if keys.dtype != torch.int64 or vals.dtype != torch.int32:
+            raise TypeError("keys must be int64 and vals int32 tensors")
+        if keys.numel() != vals.numel() or not keys.is_contiguous() or not vals.is_contiguous():
+            raise ValueError("keys and vals must be contiguous and of equal length")
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_radix_sort_pairs(self._ctx, ctypes.c_void_p(keys.data_ptr()),
+                                                ctypes.c_void_p(vals.data_ptr()), keys.numel(),
+                                                key_bits, _stream_handle(self.device)),
+                  "sa_radix_sort_pairs")
+        return keys, vals
+
+    def last_info(self) -> dict:
+        info = _native.BuildInfo()
+        check(self._lib.sa_last_build_info(self._ctx, ctypes.byref(info)), "sa_last_build_info")
+        return info.as_dict()
+
+    def set_trace(self, on: bool = True) -> None:
+        check(self._lib.sa_ctx_set_trace(self._ctx, 1 if on else 0), "sa_ctx_set_trace")
+
+    def reset_stats(self) -> None:
+        check(self._lib.sa_ctx_reset_stats(self._ctx), "sa_ctx_reset_stats")
+
+    def kernel_stats(self) -> dict:
+        out = {}
+        for name, kind in _native.KERNEL_KINDS.items():
+            st = _native.KernelStats()
+            check(self._lib.sa_ctx_get_kernel_stats(self._ctx, kind, ctypes.byref(st)),
+                  "sa_ctx_get_kernel_stats")
+            out[name] = {"launches": int(st.launches), "ms": float(st.ms), "bytes": float(st.bytes)}
+        return out

@@ -1,0 +1,117 @@
+"""ctypes binding of ``libsa_mi355x.so`` (the C ABI declared in include/sa.h).
+
+Argument marshalling only: every step of the suffix-array build runs in the HIP
+library. PyTorch supplies device memory (CUDA tensors on ROCm) and the current
+stream. There is no CPU fallback: if the library is missing or cannot be
+loaded, importing it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+from . import build_ext
+
+SA_OK, SA_EINVAL, SA_ENOMEM, SA_ETOOBIG, SA_EDEVICE, SA_EBUSY = range(6)
+SA_MAX_ROUNDS = 64
+KERNEL_KINDS = {
+    "sort_pass": 0,
+    "histogram": 1,
+    "rerank": 2,
+    "pack_text": 3,
+    "pack_pairs": 4,
+    "other": 5,
+}
+
+EXPORTED = [
+    "sa_ctx_create", "sa_ctx_destroy", "sa_build", "sa_last_build_info", "sa_build_rounds",
+    "sa_radix_sort_pairs", "sa_workspace_bytes", "sa_ctx_set_trace", "sa_ctx_reset_stats",
+    "sa_ctx_get_kernel_stats", "sa_strerror",
+]
+
+
+class BuildInfo(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_uint64),
+        ("rounds", ctypes.c_uint32),
+        ("sigma", ctypes.c_uint32),
+        ("code_bits", ctypes.c_uint32),
+        ("chars0", ctypes.c_uint32),
+        ("prefix_len", ctypes.c_uint64),
+        ("active", ctypes.c_uint64 * SA_MAX_ROUNDS),
+        ("passes_run", ctypes.c_uint32 * SA_MAX_ROUNDS),
+        ("key_bits", ctypes.c_uint32 * SA_MAX_ROUNDS),
+    ]
+
+    def as_dict(self) -> dict:
+        r = int(self.rounds)
+        return {
+            "n": int(self.n), "rounds": r, "sigma": int(self.sigma),
+            "code_bits": int(self.code_bits), "chars0": int(self.chars0),
+            "prefix_len": int(self.prefix_len),
+            "active": [int(x) for x in self.active[:r]],
+            "passes_run": [int(x) for x in self.passes_run[:r]],
+            "key_bits": [int(x) for x in self.key_bits[:r]],
+        }
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+class SAError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {_strerror(status)} (status {status})")
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def _declare(lib: ctypes.CDLL) -> None:
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    sig = {
+        "sa_ctx_create": ([ctypes.POINTER(vp), i32, ctypes.c_char_p], i32),
+        "sa_ctx_destroy": ([vp], i32),
+        "sa_build": ([vp, vp, u64, u32, vp, vp], i32),
+        "sa_last_build_info": ([vp, ctypes.POINTER(BuildInfo)], i32),
+        "sa_build_rounds": ([vp, vp, u64, u32, vp, vp, vp], i32),
+        "sa_radix_sort_pairs": ([vp, vp, vp, u64, u32, vp], i32),
+        "sa_workspace_bytes": ([u64], ctypes.c_size_t),
+        "sa_ctx_set_trace": ([vp, i32], i32),
+        "sa_ctx_reset_stats": ([vp], i32),
+        "sa_ctx_get_kernel_stats": ([vp, i32, ctypes.POINTER(KernelStats)], i32),
+        "sa_strerror": ([i32], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+
+
+def lib() -> ctypes.CDLL:
+    """Load the HIP library, building it first only if no build exists."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(build_ext.LIB):
+                build_ext.build()
+            handle = ctypes.CDLL(build_ext.LIB)
+            _declare(handle)
+            _lib = handle
+        return _lib
+
+
+def _strerror(status: int) -> str:
+    try:
+        return lib().sa_strerror(status).decode()
+    except Exception:  # pragma: no cover - only when the library itself is broken
+        return "unknown"
+
+
+def check(status: int, what: str) -> None:
+    if status != SA_OK:
+        raise SAError(status, what)

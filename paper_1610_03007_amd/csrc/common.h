@@ -1,0 +1,87 @@
+// Shared definitions for the gfx950 suffix-array kernels and their host driver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sa {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef uint16_t u16;
+typedef uint8_t u8;
+
+constexpr int kWave = 64;  // CDNA wavefront width
+
+// ---------------------------------------------------------------------------
+// Decoupled look-back status words (single-pass scans across workgroups).
+//
+// A 64-bit word holds [generation:22 | flag:2 | value:40]. The generation is a
+// launch counter kept by the host, so a status array never has to be cleared
+// between launches: a word written by an older launch reads as "not ready".
+// flag 1 = aggregate of this tile only, flag 2 = inclusive prefix.
+constexpr u64 kStatusValueBits = 40;
+constexpr u64 kStatusValueMask = (u64(1) << kStatusValueBits) - 1;
+constexpr u32 kFlagAggregate = 1;
+constexpr u32 kFlagPrefix = 2;
+constexpr u32 kGenMask = (1u << 22) - 1;
+
+__host__ __device__ inline u64 status_pack(u32 gen, u32 flag, u64 value) {
+  return (u64(gen & kGenMask) << 42) | (u64(flag) << 40) | (value & kStatusValueMask);
+}
+__host__ __device__ inline u32 status_gen(u64 s) { return u32(s >> 42) & kGenMask; }
+__host__ __device__ inline u32 status_flag(u64 s) { return u32(s >> 40) & 3u; }
+__host__ __device__ inline u64 status_value(u64 s) { return s & kStatusValueMask; }
+
+// Bounded wait: a look-back that does not see its predecessor within this many
+// polls raises the error flag and gives up, so a kernel always terminates.
+constexpr u32 kSpinLimit = 1u << 24;
+
+// Error flag bits reported back to the host.
+constexpr u32 kErrLookbackTimeout = 1u;
+constexpr u32 kErrBounds = 2u;  // an index fell outside its array; the write was dropped
+
+__device__ inline u64 load_status(const u64* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void store_status(u64* p, u64 v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---------------------------------------------------------------------------
+// Radix sort plan, computed on the device from the up-front digit histograms.
+constexpr int kRadixBits = 8;
+constexpr int kRadix = 1 << kRadixBits;
+constexpr int kMaxPasses = 64 / kRadixBits;
+
+struct SortPlan {
+  u64 offsets[kMaxPasses][kRadix];  // exclusive global start of each digit
+  u32 skip[kMaxPasses];             // pass p is skipped (its digit is constant)
+  u32 src[kMaxPasses];              // buffer pass p reads (0 = A, 1 = B)
+  u32 iota[kMaxPasses];             // pass p generates values = input index
+  u32 final_buf;                    // buffer that holds the sorted output
+  u32 pad;
+};
+
+// Workgroup and tile shapes.
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 elements
+constexpr int kHistBlock = 256;
+constexpr int kRerankBlock = 256;
+constexpr int kRerankItems = 8;
+constexpr int kRerankTile = kRerankBlock * kRerankItems;  // 2048 elements
+
+// Device-side 64-bit counters shared by one build (slot indices).
+enum CounterSlot : int {
+  kCtrSortTiles = 0,                 // kMaxPasses slots: tile tickets per pass
+  kCtrRerankTiles = kMaxPasses,      // tile tickets of the re-rank kernel
+  kCtrActive = kMaxPasses + 1,       // survivors written by the last re-rank
+  kCtrError = kMaxPasses + 2,        // error bits (kErr*)
+  kCtrSigma = kMaxPasses + 3,        // distinct bytes in the text
+  kCtrCodeBits = kMaxPasses + 4,     // w: bits per character code
+  kCtrChars = kMaxPasses + 5,        // c: characters packed in a round-0 key
+  kCtrCount = kMaxPasses + 8,
+};
+
+}  // namespace sa

@@ -1,0 +1,490 @@
+// Context, round driver and C ABI of the gfx950 suffix-array library.
+//
+// The driver runs the loop of prefix doubling with discarding (Section 2.1,
+// Alg. 5): round 0 sorts keys of c packed characters; each later round sorts
+// only the suffixes whose name is not yet unique, by the name pair (own name,
+// name of the suffix h positions on), with h doubling every round, until no
+// suffix is left. One 8-byte readback per round tells the host how many
+// suffixes remain.
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sa.h"
+#include "kernels.h"
+
+using namespace sa;
+
+struct TraceRec {
+  hipEvent_t start, stop;
+  int kind;
+  double bytes;      // algorithmic bytes, if known at launch
+  int sort_slot;     // >= 0: bytes depend on the plan of this sort (pass `pass`)
+  int pass;
+  u64 count;
+};
+
+struct sa_ctx {
+  int device = 0;
+  u64 cap = 0;  // element capacity of the workspace
+  u64* keysA = nullptr;
+  u64* keysB = nullptr;
+  u32* valsA = nullptr;
+  u32* valsB = nullptr;
+  u32* isa = nullptr;
+  u32* act_idx = nullptr;
+  u32* act_rank = nullptr;
+  u64* status = nullptr;  // sort look-back: [tiles][kRadix]
+  u64* st3 = nullptr;     // re-rank look-back: 3 x [tiles]
+  u64 rr_tiles_cap = 0;
+  // Small control block: hist | counters | plan | present | code.
+  void* small = nullptr;
+  u64* hist = nullptr;
+  u64* counters = nullptr;
+  SortPlan* plan = nullptr;
+  u32* present = nullptr;
+  u16* code = nullptr;
+  // Pinned readback area: counters copy + per-sort plan flags.
+  u64* h_counters = nullptr;
+  u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][3 * kMaxPasses]
+  u32 gen = 0;
+  bool trace = false;
+  std::vector<TraceRec> recs;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_used = 0;
+  sa_kernel_stats stats[SA_KERNEL_KINDS];
+  sa_build_info info;
+};
+
+namespace {
+
+constexpr size_t kSmallHist = size_t(kMaxPasses) * kRadix * sizeof(u64);
+constexpr size_t kSmallCounters = size_t(kCtrCount) * sizeof(u64);
+constexpr size_t kSmallPlan = (sizeof(SortPlan) + 255) / 256 * 256;
+constexpr size_t kSmallPresent = 256 * sizeof(u32);
+constexpr size_t kSmallCode = 256 * sizeof(u16);
+constexpr size_t kSmallBytes = kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent + kSmallCode;
+constexpr int kPlanFlagWords = 3 * kMaxPasses + 1;  // skip, src, iota, final_buf
+
+u64 sort_status_words(u64 cap) { return ceil_div(cap, kSortTile) * kRadix; }
+u64 rerank_tiles(u64 cap) { return ceil_div(cap, kRerankTile); }
+
+int bits_of(u64 v) { return v == 0 ? 0 : 64 - __builtin_clzll(v); }
+
+void free_workspace(sa_ctx* c) {
+  (void)hipFree(c->keysA);
+  (void)hipFree(c->keysB);
+  (void)hipFree(c->valsA);
+  (void)hipFree(c->valsB);
+  (void)hipFree(c->isa);
+  (void)hipFree(c->act_idx);
+  (void)hipFree(c->act_rank);
+  (void)hipFree(c->status);
+  (void)hipFree(c->st3);
+  c->keysA = c->keysB = nullptr;
+  c->valsA = c->valsB = c->isa = c->act_idx = c->act_rank = nullptr;
+  c->status = c->st3 = nullptr;
+  c->cap = 0;
+  c->rr_tiles_cap = 0;
+}
+
+template <typename T>
+bool dev_alloc(T** p, u64 count) {
+  if (hipMalloc(reinterpret_cast<void**>(p), std::max<u64>(count, 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+sa_status ensure_workspace(sa_ctx* c, u64 n) {
+  if (n <= c->cap) return SA_OK;
+  free_workspace(c);
+  u64 cap = std::max<u64>(n, 1 << 16);
+  bool ok = dev_alloc(&c->keysA, cap) && dev_alloc(&c->keysB, cap) && dev_alloc(&c->valsA, cap) &&
+            dev_alloc(&c->valsB, cap) && dev_alloc(&c->isa, cap) && dev_alloc(&c->act_idx, cap) &&
+            dev_alloc(&c->act_rank, cap) && dev_alloc(&c->status, sort_status_words(cap)) &&
+            dev_alloc(&c->st3, 3 * rerank_tiles(cap));
+  if (!ok) {
+    free_workspace(c);
+    return SA_ENOMEM;
+  }
+  // Status arrays start cleared; generations then keep them valid without
+  // further clearing.
+  if (hipMemset(c->status, 0, sort_status_words(cap) * sizeof(u64)) != hipSuccess ||
+      hipMemset(c->st3, 0, 3 * rerank_tiles(cap) * sizeof(u64)) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    free_workspace(c);
+    return SA_EDEVICE;
+  }
+  c->cap = cap;
+  c->rr_tiles_cap = rerank_tiles(cap);
+  c->gen = 0;
+  return SA_OK;
+}
+
+// Next look-back generation; clears the status arrays when the 22-bit counter
+// wraps.
+u32 next_gen(sa_ctx* c, hipStream_t s) {
+  if (c->gen + 1 >= kGenMask) {
+    launch_fill_u64(c->status, sort_status_words(c->cap), 0, s);
+    launch_fill_u64(c->st3, 3 * c->rr_tiles_cap, 0, s);
+    c->gen = 0;
+  }
+  return ++c->gen;
+}
+
+hipEvent_t take_event(sa_ctx* c) {
+  if (c->event_used == c->event_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    c->event_pool.push_back(e);
+  }
+  return c->event_pool[c->event_used++];
+}
+
+// Brackets one launch with events when tracing.
+struct Tracer {
+  sa_ctx* c;
+  hipStream_t s;
+  TraceRec rec{};
+  bool on;
+  Tracer(sa_ctx* ctx, hipStream_t st, int kind, double bytes, int sort_slot = -1, int pass = 0,
+         u64 count = 0)
+      : c(ctx), s(st), on(ctx->trace) {
+    if (!on) return;
+    rec.kind = kind;
+    rec.bytes = bytes;
+    rec.sort_slot = sort_slot;
+    rec.pass = pass;
+    rec.count = count;
+    rec.start = take_event(c);
+    rec.stop = take_event(c);
+    if (!rec.start || !rec.stop) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(rec.start, s);
+  }
+  ~Tracer() {
+    if (!on) return;
+    (void)hipEventRecord(rec.stop, s);
+    c->recs.push_back(rec);
+  }
+};
+
+void collect_trace(sa_ctx* c) {
+  for (const TraceRec& r : c->recs) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+      (void)hipGetLastError();
+      continue;
+    }
+    double bytes = r.bytes;
+    if (r.sort_slot >= 0) {
+      const u32* f = c->h_plans + size_t(r.sort_slot) * kPlanFlagWords;
+      const bool skip = f[r.pass] != 0;
+      const bool iota = f[2 * kMaxPasses + r.pass] != 0;
+      if (skip) continue;  // the launch returned at once; not a sweep
+      bytes = double(r.count) * (iota ? 20.0 : 24.0);
+    }
+    sa_kernel_stats& st = c->stats[r.kind];
+    st.launches += 1;
+    st.ms += ms;
+    st.bytes += bytes;
+  }
+  c->recs.clear();
+  c->event_used = 0;
+}
+
+// Sorts (keysA, valsA or generated values) by the low 8*npass bits. The sorted
+// pairs end in the buffer named by plan->final_buf. The plan flags are copied to
+// h_plans slot `slot` on the stream.
+void run_sort(sa_ctx* c, u64 count, int npass, int vals_present, int slot, hipStream_t s) {
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, 0);
+    // Clear the histograms and the ticket counters (slots 0 .. kCtrRerankTiles).
+    launch_fill_u64(c->hist, kMaxPasses * kRadix + kCtrRerankTiles + 1, 0, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_HISTOGRAM, double(count) * 8.0);
+    launch_radix_histogram(c->keysA, count, npass, c->hist, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, 0);
+    launch_radix_plan(c->hist, count, npass, vals_present, c->plan, s);
+  }
+  (void)hipMemcpyAsync(c->h_plans + size_t(slot) * kPlanFlagWords, c->plan->skip,
+                 kPlanFlagWords * sizeof(u32), hipMemcpyDeviceToHost, s);
+  for (int p = 0; p < npass; ++p) {
+    u32 gen = next_gen(c, s);
+    Tracer t(c, s, SA_KERNEL_SORT_PASS, 0, slot, p, count);
+    launch_onesweep_pass(c->keysA, c->keysB, c->valsA, c->valsB, count, p, c->plan, c->status,
+                         c->counters, gen, s);
+  }
+}
+
+void run_rerank(sa_ctx* c, u64 count, u64 n, int b, u32* d_sa, hipStream_t s) {
+  u32 gen = next_gen(c, s);
+  Tracer t(c, s, SA_KERNEL_RERANK, double(count) * 16.0);
+  const u64 rt = c->rr_tiles_cap;
+  launch_rerank_compact(c->keysA, c->keysB, c->valsA, c->valsB, c->plan, count, n, b, c->isa, d_sa,
+                        c->act_idx, c->act_rank, c->st3, c->st3 + rt, c->st3 + 2 * rt,
+                        c->counters, gen, s);
+}
+
+sa_status readback(sa_ctx* c, hipStream_t s) {
+  if (hipMemcpyAsync(c->h_counters, c->counters, kCtrCount * sizeof(u64), hipMemcpyDeviceToHost,
+                     s) != hipSuccess)
+    return SA_EDEVICE;
+  if (hipStreamSynchronize(s) != hipSuccess) return SA_EDEVICE;
+  if (hipGetLastError() != hipSuccess) return SA_EDEVICE;
+  if (c->h_counters[kCtrError] != 0) return SA_EDEVICE;
+  return SA_OK;
+}
+
+u32 passes_run(const sa_ctx* c, int slot, int npass) {
+  const u32* f = c->h_plans + size_t(slot) * kPlanFlagWords;
+  u32 r = 0;
+  for (int p = 0; p < npass; ++p) r += f[p] == 0;
+  return r;
+}
+
+sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_sa, u32* d_isa,
+                       hipStream_t s) {
+  std::memset(&c->info, 0, sizeof(c->info));
+  c->info.n = n;
+  if (n == 0) return SA_OK;
+  if (!text || !d_sa) return SA_EINVAL;
+  if (n >= (u64(1) << 32)) return SA_ETOOBIG;
+  if (hipSetDevice(c->device) != hipSuccess) return SA_EDEVICE;
+  sa_status st = ensure_workspace(c, n);
+  if (st != SA_OK) return st;
+
+  // Round 0: alphabet, packed keys, full sort, names, discard.
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, 0);
+    launch_fill_u64(c->hist, kMaxPasses * kRadix + kCtrCount, 0, s);
+    launch_fill_u64(reinterpret_cast<u64*>(c->present), 256 / 2, 0, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, double(n));
+    launch_byte_presence(text, n, c->present, s);
+    launch_alphabet_codes(c->present, c->code, c->counters, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_PACK_TEXT, double(n) * 9.0);
+    launch_pack_text(text, n, c->code, c->counters, c->keysA, s);
+  }
+  run_sort(c, n, kMaxPasses, 0, 0, s);
+  run_rerank(c, n, n, 0, d_sa, s);
+  st = readback(c, s);
+  if (st != SA_OK) return st;
+
+  sa_build_info& info = c->info;
+  info.sigma = u32(c->h_counters[kCtrSigma]);
+  info.code_bits = u32(c->h_counters[kCtrCodeBits]);
+  info.chars0 = u32(c->h_counters[kCtrChars]);
+  info.rounds = 1;
+  info.active[0] = n;
+  info.key_bits[0] = info.code_bits * info.chars0;
+  info.passes_run[0] = passes_run(c, 0, kMaxPasses);
+  u64 h = info.chars0;
+  info.prefix_len = h;
+  u64 active = c->h_counters[kCtrActive];
+
+  // Later rounds: only suffixes whose name is still shared.
+  const int b = bits_of(n);  // ranks and second ranks are <= n
+  const int key_bits = 2 * b;
+  const int npass = int(ceil_div(u64(key_bits), kRadixBits));
+  while (active > 0 && (max_rounds == 0 || info.rounds < max_rounds)) {
+    if (info.rounds >= SA_MAX_ROUNDS) return SA_EDEVICE;  // cannot happen for n < 2^32
+    const int slot = int(info.rounds);
+    {
+      Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
+      launch_pack_pairs(c->act_idx, c->act_rank, active, n, h, b, c->isa, c->keysA, c->valsA, s);
+    }
+    run_sort(c, active, npass, 1, slot, s);
+    run_rerank(c, active, n, b, d_sa, s);
+    st = readback(c, s);
+    if (st != SA_OK) return st;
+    info.active[slot] = active;
+    info.key_bits[slot] = u32(key_bits);
+    info.passes_run[slot] = passes_run(c, slot, npass);
+    info.rounds += 1;
+    h *= 2;
+    info.prefix_len = h;
+    active = c->h_counters[kCtrActive];
+  }
+  if (d_isa) {
+    if (hipMemcpyAsync(d_isa, c->isa, n * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return SA_EDEVICE;
+    if (hipStreamSynchronize(s) != hipSuccess) return SA_EDEVICE;
+  }
+  return SA_OK;
+}
+
+// Runs a build and settles the trace records: collected on success, dropped on
+// error (their events may not have completed).
+sa_status build_impl(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_sa, u32* d_isa,
+                     hipStream_t s) {
+  if (!c) return SA_EINVAL;
+  sa_status st = build_rounds(c, text, n, max_rounds, d_sa, d_isa, s);
+  if (st == SA_OK && c->trace) {
+    collect_trace(c);
+  } else {
+    c->recs.clear();
+    c->event_used = 0;
+  }
+  return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
+  (void)tune_cache_json;
+  if (!out) return SA_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+    (void)hipGetLastError();
+    return ndev == 0 ? SA_EDEVICE : SA_EINVAL;
+  }
+  if (hipSetDevice(device) != hipSuccess) return SA_EDEVICE;
+  sa_ctx* c = new (std::nothrow) sa_ctx();
+  if (!c) return SA_ENOMEM;
+  c->device = device;
+  std::memset(c->stats, 0, sizeof(c->stats));
+  std::memset(&c->info, 0, sizeof(c->info));
+  if (hipMalloc(&c->small, kSmallBytes) != hipSuccess) {
+    delete c;
+    return SA_ENOMEM;
+  }
+  char* p = static_cast<char*>(c->small);
+  c->hist = reinterpret_cast<u64*>(p);
+  c->counters = reinterpret_cast<u64*>(p + kSmallHist);
+  c->plan = reinterpret_cast<SortPlan*>(p + kSmallHist + kSmallCounters);
+  c->present = reinterpret_cast<u32*>(p + kSmallHist + kSmallCounters + kSmallPlan);
+  c->code = reinterpret_cast<u16*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent);
+  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_counters), kCtrCount * sizeof(u64)) !=
+          hipSuccess ||
+      hipHostMalloc(reinterpret_cast<void**>(&c->h_plans),
+                    size_t(SA_MAX_ROUNDS + 1) * kPlanFlagWords * sizeof(u32)) != hipSuccess) {
+    sa_ctx_destroy(c);
+    return SA_ENOMEM;
+  }
+  *out = c;
+  return SA_OK;
+}
+
+sa_status sa_ctx_destroy(sa_ctx* ctx) {
+  if (!ctx) return SA_OK;
+  (void)hipSetDevice(ctx->device);
+  free_workspace(ctx);
+  (void)hipFree(ctx->small);
+  if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
+  if (ctx->h_plans) (void)hipHostFree(ctx->h_plans);
+  for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return SA_OK;
+}
+
+sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma, uint32_t* d_sa,
+                   void* stream) {
+  if (!ctx) return SA_EINVAL;
+  if (sigma == 0 || sigma > 256) return SA_EINVAL;
+  return build_impl(ctx, d_text, n, 0, d_sa, nullptr, static_cast<hipStream_t>(stream));
+}
+
+sa_status sa_build_rounds(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t max_rounds,
+                          uint32_t* d_sa, uint32_t* d_isa, void* stream) {
+  return build_impl(ctx, d_text, n, max_rounds, d_sa, d_isa, static_cast<hipStream_t>(stream));
+}
+
+sa_status sa_last_build_info(const sa_ctx* ctx, sa_build_info* out) {
+  if (!ctx || !out) return SA_EINVAL;
+  *out = ctx->info;
+  return SA_OK;
+}
+
+sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, uint64_t count,
+                              uint32_t key_bits, void* stream) {
+  if (!ctx) return SA_EINVAL;
+  if (count == 0) return SA_OK;
+  if (!d_keys || !d_vals || key_bits == 0 || key_bits > 64) return SA_EINVAL;
+  if (count >= (u64(1) << 32)) return SA_ETOOBIG;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipSetDevice(ctx->device) != hipSuccess) return SA_EDEVICE;
+  sa_status st = ensure_workspace(ctx, count);
+  if (st != SA_OK) return st;
+  {
+    Tracer t(ctx, s, SA_KERNEL_OTHER, 0);
+    launch_fill_u64(ctx->counters, kCtrCount, 0, s);
+  }
+  if (hipMemcpyAsync(ctx->keysA, d_keys, count * sizeof(u64), hipMemcpyDeviceToDevice, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(ctx->valsA, d_vals, count * sizeof(u32), hipMemcpyDeviceToDevice, s) !=
+          hipSuccess)
+    return SA_EDEVICE;
+  const int npass = int(ceil_div(key_bits, kRadixBits));
+  run_sort(ctx, count, npass, 1, 0, s);
+  st = readback(ctx, s);  // also waits for the plan flags
+  if (st != SA_OK) {
+    ctx->recs.clear();
+    ctx->event_used = 0;
+    return st;
+  }
+  const u32 final_buf = ctx->h_plans[3 * kMaxPasses];
+  const u64* ksrc = final_buf ? ctx->keysB : ctx->keysA;
+  const u32* vsrc = final_buf ? ctx->valsB : ctx->valsA;
+  if (hipMemcpyAsync(d_keys, ksrc, count * sizeof(u64), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(d_vals, vsrc, count * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return SA_EDEVICE;
+  if (ctx->trace) collect_trace(ctx);
+  return SA_OK;
+}
+
+size_t sa_workspace_bytes(uint64_t n) {
+  u64 cap = std::max<u64>(n, 1 << 16);
+  return size_t(cap) * (2 * 8 + 5 * 4) + sort_status_words(cap) * 8 + 3 * rerank_tiles(cap) * 8 +
+         kSmallBytes;
+}
+
+sa_status sa_ctx_set_trace(sa_ctx* ctx, int on) {
+  if (!ctx) return SA_EINVAL;
+  ctx->trace = on != 0;
+  return SA_OK;
+}
+
+sa_status sa_ctx_reset_stats(sa_ctx* ctx) {
+  if (!ctx) return SA_EINVAL;
+  std::memset(ctx->stats, 0, sizeof(ctx->stats));
+  return SA_OK;
+}
+
+sa_status sa_ctx_get_kernel_stats(const sa_ctx* ctx, int kind, sa_kernel_stats* out) {
+  if (!ctx || !out || kind < 0 || kind >= SA_KERNEL_KINDS) return SA_EINVAL;
+  *out = ctx->stats[kind];
+  return SA_OK;
+}
+
+const char* sa_strerror(sa_status s) {
+  switch (s) {
+    case SA_OK: return "ok";
+    case SA_EINVAL: return "invalid argument";
+    case SA_ENOMEM: return "out of device memory";
+    case SA_ETOOBIG: return "input too large (n must be < 2^32)";
+    case SA_EDEVICE: return "device error";
+    case SA_EBUSY: return "busy";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,218 @@
+"""GPU parity: the HIP suffix-array path against the CPU oracle.
+
+Bit-exact comparison (the suffix array is unique and all arithmetic is
+integer). Small and medium texts are compared element by element with
+``oracle.sa``; per-round names with the oracle's closed form; the full-size
+256 MiB and 1 GiB texts with the oracle's linear-time suffix-array check plus
+sampled direct suffix comparisons.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def builder():
+    from paper_1610_03007_amd import SuffixArrayBuilder
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    b = SuffixArrayBuilder(0)
+    yield b
+    b.close()
+
+
+def dev(a) -> torch.Tensor:
+    if isinstance(a, (bytes, bytearray)):
+        a = np.frombuffer(bytes(a), dtype=np.uint8)
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def gpu_sa(builder, text) -> np.ndarray:
+    sa = builder.build(dev(text))
+    torch.cuda.synchronize()
+    return sa.cpu().numpy().view(np.uint32)
+
+
+def assert_same(builder, text):
+    t = np.frombuffer(bytes(text), dtype=np.uint8) if isinstance(text, (bytes, bytearray)) else text
+    want = oracle.sa(t)
+    got = gpu_sa(builder, t)
+    if not np.array_equal(got, want):
+        bad = np.nonzero(got != want)[0]
+        raise AssertionError(f"n={t.size}: {bad.size} mismatches, first at {bad[:5].tolist()}; "
+                             f"info={builder.last_info()}")
+
+
+@pytest.mark.parametrize("fixture", ["paper_example1_bdacbdacb.json",
+                                     "paper_example3_dbacbacbd.json", "banana.json"])
+def test_golden(builder, fixture):
+    g = json.load(open(os.path.join(GOLDEN, fixture)))
+    assert gpu_sa(builder, g["text"].encode()).tolist() == g["sa"]
+
+
+def test_empty(builder):
+    sa = builder.build(torch.empty(0, dtype=torch.uint8, device="cuda:0"))
+    assert sa.numel() == 0
+
+
+@pytest.mark.parametrize("text", [b"x", b"ab", b"ba", b"aa", b"a\0\0", b"\0\0\0\0",
+                                  b"\0a\0a\0", bytes(range(256)), bytes(range(255, -1, -1)),
+                                  bytes(range(256)) * 3])
+def test_small_edge_texts(builder, text):
+    assert_same(builder, text)
+
+
+@pytest.mark.parametrize("n", [2, 63, 64, 65, 2047, 2048, 2049, 4095, 4096, 4097, 70000])
+def test_unary(builder, n):
+    assert gpu_sa(builder, b"a" * n).tolist() == list(range(n - 1, -1, -1))
+
+
+@pytest.mark.parametrize("m", [1, 7, 1000, 5000])
+def test_ab_repeats(builder, m):
+    want = list(range(2 * m - 2, -1, -2)) + list(range(2 * m - 1, 0, -2))
+    assert gpu_sa(builder, b"ab" * m).tolist() == want
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 3, 4, 96, 255, 256])
+def test_random_small(builder, sigma):
+    rng = np.random.default_rng(1000 + sigma)
+    for _ in range(40):
+        n = int(rng.integers(1, 600))
+        t = rng.integers(0, sigma, n).astype(np.uint8)
+        assert_same(builder, t)
+
+
+@pytest.mark.parametrize("n", [4095, 4096, 4097, 8191, 12289, 65537, 200003])
+@pytest.mark.parametrize("kind", ["dna", "binary", "bytes", "markov"])
+def test_random_tiles(builder, n, kind):
+    rng = np.random.default_rng(n)
+    if kind == "dna":
+        t = W.dna(n, seed=n)
+    elif kind == "binary":
+        t = rng.integers(0, 2, n).astype(np.uint8)
+    elif kind == "bytes":
+        t = rng.integers(0, 256, n).astype(np.uint8)
+    else:
+        t = W.markov3(n, chain_seed=n)
+    assert_same(builder, t)
+
+
+def test_periodic_texts(builder):
+    rng = np.random.default_rng(5)
+    for period in (3, 17, 1000):
+        unit = rng.integers(0, 4, period).astype(np.uint8)
+        t = np.tile(unit, 50000 // period + 1)[:50000]
+        assert_same(builder, t)
+
+
+def test_repetitive_small(builder):
+    assert_same(builder, W.repetitive(copies=64, base_len=4096))
+
+
+@pytest.mark.parametrize("kind", ["dna", "markov", "repetitive", "binary"])
+def test_round_names_closed_form(builder, kind):
+    """After every round k, ISA equals 1 + #{j : pad_h(j) < pad_h(i)} for the
+    prefix length h that round resolves (discarded suffixes included)."""
+    n = 20000
+    if kind == "dna":
+        t = W.dna(n, seed=3)
+    elif kind == "markov":
+        t = W.markov3(n, chain_seed=3)
+    elif kind == "repetitive":
+        t = W.repetitive(copies=10, base_len=2000)
+    else:
+        t = np.random.default_rng(3).integers(0, 2, n).astype(np.uint8)
+    _, _, full = builder.build_rounds(dev(t), 0)
+    for k in range(1, full["rounds"] + 1):
+        _, isa, info = builder.build_rounds(dev(t), k)
+        assert info["rounds"] == k
+        want = oracle.prefix_ranks(t, info["prefix_len"])
+        got = isa.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got, want), (kind, k, info)
+
+
+def test_dna1m(builder):
+    """n = 2^20 ACGT text (seed 0): bit-exact against the oracle."""
+    t = W.dna(1 << 20, seed=0)
+    assert_same(builder, t)
+    info = builder.last_info()
+    assert info["sigma"] == 4 and info["chars0"] == 21
+
+
+@pytest.mark.parametrize("bits", [1, 7, 8, 9, 20, 33, 42, 58, 64])
+@pytest.mark.parametrize("count", [1, 100, 4095, 4096, 4097, 100000])
+def test_radix_sort_pairs(builder, bits, count):
+    rng = np.random.default_rng(bits * 1000 + count)
+    hi = np.uint64(1) << np.uint64(bits) if bits < 64 else None
+    keys = rng.integers(0, 2**63, count, dtype=np.uint64) * np.uint64(2) + \
+        rng.integers(0, 2, count, dtype=np.uint64)
+    if hi is not None:
+        keys = keys % hi
+    if count > 10:
+        keys[: count // 10] = keys[0]  # many equal keys: stability matters
+    vals = np.arange(count, dtype=np.uint32)[::-1].copy()
+    order = np.argsort(keys, kind="stable")
+    k_t = dev(keys.view(np.int64))
+    v_t = dev(vals.view(np.int32))
+    builder.radix_sort_pairs(k_t, v_t, bits)
+    torch.cuda.synchronize()
+    assert np.array_equal(k_t.cpu().numpy().view(np.uint64), keys[order])
+    assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals[order])
+
+
+def test_radix_sort_all_equal(builder):
+    keys = np.full(50000, 12345, dtype=np.uint64)
+    vals = np.arange(50000, dtype=np.uint32)
+    k_t, v_t = dev(keys.view(np.int64)), dev(vals.view(np.int32))
+    builder.radix_sort_pairs(k_t, v_t, 64)
+    torch.cuda.synchronize()
+    assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals)
+
+
+def test_errors(builder):
+    from paper_1610_03007_amd import SAError
+    with pytest.raises(SAError):
+        builder.build(dev(b"abc"), sigma=0)
+    with pytest.raises(TypeError):
+        builder.build(torch.zeros(3, dtype=torch.int32, device="cuda:0"))
+
+
+def sampled_direct_check(t: np.ndarray, sa: np.ndarray, samples: int = 2000, seed: int = 0):
+    """Compare SA[j] and SA[j+1] suffixes byte by byte at random j."""
+    rng = np.random.default_rng(seed)
+    n = t.size
+    tb = t.tobytes()
+    for j in rng.integers(0, n - 1, samples):
+        a, b = int(sa[j]), int(sa[j + 1])
+        L = 64
+        while True:
+            sa_, sb_ = tb[a:a + L], tb[b:b + L]
+            if sa_ != sb_ or a + L >= n or b + L >= n:
+                break
+            L *= 4
+        assert tb[a:a + L] < tb[b:b + L] or (tb[a:a + L] == tb[b:b + L] and n - a < n - b), j
+
+
+@pytest.mark.parametrize("kind", ["markov_256m", "repetitive_1g"])
+def test_full_size(builder, kind):
+    """Full-size texts in the benchmark's configuration: linear-time check of
+    the whole SA plus sampled direct suffix comparisons."""
+    if kind == "markov_256m":
+        t = W.markov3(1 << 28, chain_seed=2)
+    else:
+        t = W.repetitive()
+    sa = gpu_sa(builder, t)
+    info = builder.last_info()
+    status, where = oracle.check_sa(t, sa)
+    assert status == 0, (kind, status, where, info)
+    sampled_direct_check(t, sa)
