@@ -84,7 +84,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="markov_256m", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=1 << 24,
+    ap.add_argument("--cpu-sample", type=int, default=1 << 28,
                     help="bytes of the text the CPU oracle is timed on (0 = skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy to run after the steps (counter calibration)")
