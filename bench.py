@@ -86,6 +86,8 @@ def main() -> int:
     ap.add_argument("--workload", default="markov_256m", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=1 << 28,
                     help="bytes of the text the CPU oracle is timed on (0 = skip)")
+    ap.add_argument("--sort-items", type=int, default=0,
+                    help="radix-sort items per thread (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy to run after the steps (counter calibration)")
     args = ap.parse_args()
@@ -111,6 +113,8 @@ def main() -> int:
     d_text = torch.from_numpy(text).to(dev)
     d_sa = torch.empty(n, dtype=torch.int32, device=dev)
     b = SuffixArrayBuilder(0)
+    if args.sort_items:
+        b.set_tuning(sort_items=args.sort_items)
 
     for _ in range(args.warmup):
         b.build(d_text, out=d_sa)
@@ -165,6 +169,7 @@ def main() -> int:
             "sigma": info["sigma"],
             "chars_round0": info["chars0"],
             "parallelism": "single GPU",
+            "tuning": b.tuning(),
         },
         "roofline": {
             "bound": "hbm",

@@ -74,6 +74,8 @@ typedef struct {
   uint32_t code_bits;     /* bits per character in a round-0 key */
   uint32_t chars0;        /* characters per round-0 key: the first prefix length */
   uint64_t prefix_len;    /* prefix length the ranks resolve after the last round */
+  uint32_t lazy_isa;      /* 1 if the ISA was resolved lazily after round 0 */
+  uint32_t reserved;
   uint64_t active[SA_MAX_ROUNDS];       /* suffixes sorted in round k */
   uint32_t passes_run[SA_MAX_ROUNDS];   /* radix passes executed in round k */
   uint32_t key_bits[SA_MAX_ROUNDS];     /* key bits sorted in round k */
@@ -99,6 +101,30 @@ sa_status sa_build_rounds(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32
 sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, uint64_t count,
                               uint32_t key_bits, void* stream);
 
+/* How the inverse suffix array is formed after round 0 (a tuning choice; the
+ * result is the same). Eager: one random 4-byte write per suffix. Lazy: only
+ * the suffixes that survive round 0 are written, and a later round that needs
+ * the round-0 name of another suffix recomputes it by binary search in the
+ * round-0 sorted keys. Auto picks lazy when at most 1/8 of the suffixes
+ * survive. Lazy needs the survivors to fit in spare workspace (at most n/3);
+ * otherwise eager is used. */
+enum { SA_ISA_AUTO = 0, SA_ISA_EAGER = 1, SA_ISA_LAZY = 2 };
+sa_status sa_ctx_set_isa_mode(sa_ctx* ctx, int mode);
+
+/* Tuning knobs (none changes a result). Unknown or unsupported values give
+ * SA_EINVAL and leave the context unchanged. */
+typedef struct {
+  uint32_t sort_items;   /* radix-sort items per thread: 8, 12, 16, 20 or 24 (tile = 256x) */
+  uint32_t lazy_ratio;   /* auto ISA mode is lazy when survivors <= n / lazy_ratio (>= 3) */
+  uint32_t round0_full;  /* 1: pack floor(64 / code bits) characters in round 0; 0 (default):
+                            drop the characters that only half-fill a last 8-bit digit */
+  uint32_t sort_wgs_per_cu; /* persistent radix-sweep workgroups per compute unit
+                               (0 = what one CU holds for the tile shape; at most 16) */
+  uint32_t reserved[4];  /* must be zero */
+} sa_tuning;
+sa_status sa_ctx_set_tuning(sa_ctx* ctx, const sa_tuning* t);
+sa_status sa_ctx_get_tuning(const sa_ctx* ctx, sa_tuning* out);
+
 /* Device workspace a context needs for a text of n bytes. */
 size_t sa_workspace_bytes(uint64_t n);
 
@@ -114,7 +140,8 @@ enum {
   SA_KERNEL_PACK_TEXT = 3,   /* round-0 keys from the text */
   SA_KERNEL_PACK_PAIRS = 4,  /* round >= 1 keys (ISA gather) */
   SA_KERNEL_OTHER = 5,       /* alphabet, plan, fills */
-  SA_KERNEL_KINDS = 6
+  SA_KERNEL_ISA_SCATTER = 6, /* eager ISA after round 0 */
+  SA_KERNEL_KINDS = 7
 };
 typedef struct {
   uint64_t launches;

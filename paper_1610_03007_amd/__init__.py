@@ -120,6 +120,29 @@ class SuffixArrayBuilder:
         check(self._lib.sa_last_build_info(self._ctx, ctypes.byref(info)), "sa_last_build_info")
         return info.as_dict()
 
+    def set_isa_mode(self, mode: str = "auto") -> None:
+        """'auto', 'eager' or 'lazy' inverse-suffix-array formation after round 0."""
+        check(self._lib.sa_ctx_set_isa_mode(self._ctx, _native.ISA_MODES[mode]),
+              "sa_ctx_set_isa_mode")
+
+    def tuning(self) -> dict:
+        t = _native.Tuning()
+        check(self._lib.sa_ctx_get_tuning(self._ctx, ctypes.byref(t)), "sa_ctx_get_tuning")
+        return {"sort_items": int(t.sort_items), "lazy_ratio": int(t.lazy_ratio),
+                "round0_full": int(t.round0_full), "sort_wgs_per_cu": int(t.sort_wgs_per_cu)}
+
+    def set_tuning(self, **kw) -> None:
+        """Set tuning knobs (sort_items, lazy_ratio, round0_full, sort_wgs_per_cu);
+        results never change."""
+        cur = self.tuning()
+        unknown = set(kw) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown tuning knobs {sorted(unknown)}")
+        cur.update(kw)
+        t = _native.Tuning(sort_items=cur["sort_items"], lazy_ratio=cur["lazy_ratio"],
+                           round0_full=cur["round0_full"], sort_wgs_per_cu=cur["sort_wgs_per_cu"])
+        check(self._lib.sa_ctx_set_tuning(self._ctx, ctypes.byref(t)), "sa_ctx_set_tuning")
+
     def set_trace(self, on: bool = True) -> None:
         check(self._lib.sa_ctx_set_trace(self._ctx, 1 if on else 0), "sa_ctx_set_trace")
 

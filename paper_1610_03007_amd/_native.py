@@ -23,11 +23,14 @@ KERNEL_KINDS = {
     "pack_text": 3,
     "pack_pairs": 4,
     "other": 5,
+    "isa_scatter": 6,
 }
+ISA_MODES = {"auto": 0, "eager": 1, "lazy": 2}
 
 EXPORTED = [
     "sa_ctx_create", "sa_ctx_destroy", "sa_build", "sa_last_build_info", "sa_build_rounds",
     "sa_radix_sort_pairs", "sa_workspace_bytes", "sa_ctx_set_trace", "sa_ctx_reset_stats",
+    "sa_ctx_set_isa_mode", "sa_ctx_set_tuning", "sa_ctx_get_tuning",
     "sa_ctx_get_kernel_stats", "sa_strerror",
 ]
 
@@ -40,6 +43,8 @@ class BuildInfo(ctypes.Structure):
         ("code_bits", ctypes.c_uint32),
         ("chars0", ctypes.c_uint32),
         ("prefix_len", ctypes.c_uint64),
+        ("lazy_isa", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
         ("active", ctypes.c_uint64 * SA_MAX_ROUNDS),
         ("passes_run", ctypes.c_uint32 * SA_MAX_ROUNDS),
         ("key_bits", ctypes.c_uint32 * SA_MAX_ROUNDS),
@@ -51,10 +56,17 @@ class BuildInfo(ctypes.Structure):
             "n": int(self.n), "rounds": r, "sigma": int(self.sigma),
             "code_bits": int(self.code_bits), "chars0": int(self.chars0),
             "prefix_len": int(self.prefix_len),
+            "lazy_isa": bool(self.lazy_isa),
             "active": [int(x) for x in self.active[:r]],
             "passes_run": [int(x) for x in self.passes_run[:r]],
             "key_bits": [int(x) for x in self.key_bits[:r]],
         }
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("sort_items", ctypes.c_uint32), ("lazy_ratio", ctypes.c_uint32),
+                ("round0_full", ctypes.c_uint32), ("sort_wgs_per_cu", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 4)]
 
 
 class KernelStats(ctypes.Structure):
@@ -82,6 +94,9 @@ def _declare(lib: ctypes.CDLL) -> None:
         "sa_radix_sort_pairs": ([vp, vp, vp, u64, u32, vp], i32),
         "sa_workspace_bytes": ([u64], ctypes.c_size_t),
         "sa_ctx_set_trace": ([vp, i32], i32),
+        "sa_ctx_set_isa_mode": ([vp, i32], i32),
+        "sa_ctx_set_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
+        "sa_ctx_get_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
         "sa_ctx_reset_stats": ([vp], i32),
         "sa_ctx_get_kernel_stats": ([vp, i32, ctypes.POINTER(KernelStats)], i32),
         "sa_strerror": ([i32], ctypes.c_char_p),

@@ -60,13 +60,22 @@ struct SortPlan {
   u32 src[kMaxPasses];              // buffer pass p reads (0 = A, 1 = B)
   u32 iota[kMaxPasses];             // pass p generates values = input index
   u32 final_buf;                    // buffer that holds the sorted output
-  u32 pad;
+  u32 first_run;                    // first pass that runs
+  int next_run[kMaxPasses];         // next pass that runs after p, or -1
 };
+
+// Each sweep splits its tiles into up to kChunks contiguous chunks with
+// independent look-back chains. The digit counts of every chunk are known
+// before the sweep starts (for the first sweep from the up-front histogram,
+// for later ones accumulated by the sweep before), so a chunk's first tile
+// never waits on another chunk.
+constexpr int kChunks = 8;
 
 // Workgroup and tile shapes.
 constexpr int kSortBlock = 256;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortBlock * kSortItems;  // 4096 elements
+constexpr int kSortItemsDefault = 16;
+constexpr int kSortItemsMin = 8;
+constexpr int kSortTileMin = kSortBlock * kSortItemsMin;  // status arrays are sized for this
 constexpr int kHistBlock = 256;
 constexpr int kRerankBlock = 256;
 constexpr int kRerankItems = 8;

@@ -12,9 +12,11 @@ void launch_set_zero_u32(u32* p, hipStream_t s);
 
 // Alphabet reduction: present[256] must be zero on entry. Afterwards code[b] is
 // 1 + (number of present bytes below b) for every present byte b, and the
-// counters hold sigma, the code width w = bits(sigma) and c = floor(64 / w).
+// counters hold sigma, the code width w = bits(sigma) and c <= floor(64 / w).
 void launch_byte_presence(const u8* text, u64 n, u32* present, hipStream_t s);
-void launch_alphabet_codes(const u32* present, u16* code, u64* counters, hipStream_t s);
+// With trim != 0, c is lowered so that c * w fills whole 8-bit radix digits.
+void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int trim,
+                           hipStream_t s);
 
 // Round-0 keys: key[i] = c codes of T[i, i+c) (0 past the end), w bits each,
 // first character most significant.
@@ -27,24 +29,61 @@ void launch_pack_pairs(const u32* act_idx, const u32* act_rank, u64 count, u64 n
                        const u32* isa, u64* keys, u32* vals, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs held in buffer A, 8-bit digits over
-// the low `npass` digits. hist must hold kMaxPasses * kRadix zeroed words and the
-// pass ticket counters must be zero. Which buffer ends up sorted is recorded in
-// plan->final_buf. With vals_present == 0 the values are generated (input index).
-void launch_radix_histogram(const u64* keys, u64 count, int npass, u64* hist, hipStream_t s);
-void launch_radix_plan(const u64* hist, u64 count, int npass, int vals_present, SortPlan* plan,
-                       hipStream_t s);
-void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, u64 count, int pass,
-                          const SortPlan* plan, u64* status, u64* counters, u32 gen,
-                          hipStream_t s);
+// the low `npass` digits. Geometry: tiles of `tile` pairs grouped into chunks of
+// 2^ct_log2 tiles, nchunks = number of non-empty chunks (<= kChunks).
+struct SortGeom {
+  u64 count;
+  u32 tile;
+  u32 ct_log2;
+  u32 nchunks;
+};
+// hist_in [kMaxPasses][kChunks][kRadix] must be zero on entry; it receives the
+// digit counts of every pass per chunk of the input.
+void launch_radix_histogram(const u64* keys, const SortGeom& geo, int npass, u32* hist_in,
+                            hipStream_t s);
+// Offsets, skipped passes and the buffer schedule. With vals_present == 0 the
+// first sweep generates the values (input index).
+void launch_radix_plan(const u32* hist_in, const SortGeom& geo, int npass, int vals_present,
+                       SortPlan* plan, hipStream_t s);
+// One sweep. hist_run [kMaxPasses][kChunks][kRadix] and tickets
+// [kMaxPasses][kChunks] must be zero before the first sweep of a sort. `items`
+// per thread (8, 12, 16, 20 or 24) must match geo.tile = kSortBlock * items.
+// `grid` persistent workgroups (a multiple of geo.nchunks).
+void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
+                          int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
+                          u32* tickets, u64* status, u64* counters, u32 gen, int items,
+                          u32 grid, hipStream_t s);
 
 // Re-rank the sorted active set, scatter the ISA, finalize unique suffixes into
 // the SA and compact the survivors. b = bits of the second rank (0 in round 0,
 // where every element starts with rank 1).
+// mode: kRerankScatterIsa writes ISA[text position] = new rank for every element;
+// kRerankWriteRanks writes the new rank of sorted position p into the value
+// buffer the sort did not end in.
+constexpr int kRerankScatterIsa = 1;
+constexpr int kRerankWriteRanks = 2;
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            const u32* valsB, const SortPlan* plan, u64 count, u64 n, int b,
-                           u32* isa, u32* sa_out, u32* act_idx, u32* act_rank, u64* st_head,
-                           u64* st_grp, u64* st_surv, u64* counters, u32 gen, hipStream_t s);
+                           int mode, u32* isa, u32* sa_out, u32* act_idx, u32* act_rank,
+                           u64* st_head, u64* st_grp, u64* st_surv, u64* counters, u32 gen,
+                           hipStream_t s);
 
-inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
+// ISA after round 0. Eager: ISA[vals[p]] = ranks[p] over the sorted pairs (the
+// ranks written by the re-rank with kRerankWriteRanks). Lazy: ISA cleared,
+// survivors scattered from the active list, and zero entries resolved on
+// demand by a binary search in the round-0 sorted keys `keys0`.
+void launch_isa_scatter_sorted(const u32* valsA, const u32* valsB, const SortPlan* plan, u64 n,
+                               u32* isa, hipStream_t s);
+void launch_isa_scatter_list(const u32* idx, const u32* rank, u64 count, u64 n, u32* isa,
+                             hipStream_t s);
+void launch_pack_pairs_lazy(const u32* act_idx, const u32* act_rank, u64 count, u64 n, u64 h,
+                            int b, const u32* isa, const u8* text, const u16* code,
+                            const u64* counters, const u64* keys0, u64* keys, u32* vals,
+                            hipStream_t s);
+void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const u64* counters,
+                         const u64* keys0, hipStream_t s);
+void launch_fill_u32(u32* p, u64 count, u32 value, hipStream_t s);
+
+__host__ __device__ inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
 }  // namespace sa

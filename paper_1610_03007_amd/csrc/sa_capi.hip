@@ -18,6 +18,11 @@
 
 using namespace sa;
 
+// Automatic ISA mode: lazy when at most 1/kLazyRatio of the suffixes survive
+// round 0 (each later gather may then cost a binary search instead of every
+// suffix costing a random 4-byte write).
+constexpr u64 kLazyRatioDefault = 8;
+
 struct TraceRec {
   hipEvent_t start, stop;
   int kind;
@@ -40,9 +45,11 @@ struct sa_ctx {
   u64* status = nullptr;  // sort look-back: [tiles][kRadix]
   u64* st3 = nullptr;     // re-rank look-back: 3 x [tiles]
   u64 rr_tiles_cap = 0;
-  // Small control block: hist | counters | plan | present | code.
+  // Small control block: hist_in | hist_run | tickets | counters | plan | present | code.
   void* small = nullptr;
-  u64* hist = nullptr;
+  u32* hist_in = nullptr;   // [kMaxPasses][kChunks][kRadix] input-order chunk histograms
+  u32* hist_run = nullptr;  // [kMaxPasses][kChunks][kRadix] histograms fed forward by sweeps
+  u32* tickets = nullptr;   // [kMaxPasses][kChunks] tile tickets
   u64* counters = nullptr;
   SortPlan* plan = nullptr;
   u32* present = nullptr;
@@ -51,6 +58,12 @@ struct sa_ctx {
   u64* h_counters = nullptr;
   u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][3 * kMaxPasses]
   u32 gen = 0;
+  int isa_mode = SA_ISA_AUTO;
+  int sort_items = kSortItemsDefault;  // radix-sort items per thread (tile size)
+  int sort_wgs_per_cu = 0;             // persistent sweep workgroups per CU (0 = by tile size)
+  int num_cus = 256;
+  u64 lazy_ratio = kLazyRatioDefault;
+  int round0_trim = 1;  // round-0 keys fill whole radix digits
   bool trace = false;
   std::vector<TraceRec> recs;
   std::vector<hipEvent_t> event_pool;
@@ -61,7 +74,9 @@ struct sa_ctx {
 
 namespace {
 
-constexpr size_t kSmallHist = size_t(kMaxPasses) * kRadix * sizeof(u64);
+constexpr size_t kChunkHistWords = size_t(kMaxPasses) * kChunks * kRadix;
+constexpr size_t kTicketWords = size_t(kMaxPasses) * kChunks;
+constexpr size_t kSmallHist = (2 * kChunkHistWords + kTicketWords) * sizeof(u32);
 constexpr size_t kSmallCounters = size_t(kCtrCount) * sizeof(u64);
 constexpr size_t kSmallPlan = (sizeof(SortPlan) + 255) / 256 * 256;
 constexpr size_t kSmallPresent = 256 * sizeof(u32);
@@ -69,7 +84,8 @@ constexpr size_t kSmallCode = 256 * sizeof(u16);
 constexpr size_t kSmallBytes = kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent + kSmallCode;
 constexpr int kPlanFlagWords = 3 * kMaxPasses + 1;  // skip, src, iota, final_buf
 
-u64 sort_status_words(u64 cap) { return ceil_div(cap, kSortTile) * kRadix; }
+
+u64 sort_status_words(u64 cap) { return ceil_div(cap, kSortTileMin) * kRadix; }
 u64 rerank_tiles(u64 cap) { return ceil_div(cap, kRerankTile); }
 
 int bits_of(u64 v) { return v == 0 ? 0 : 64 - __builtin_clzll(v); }
@@ -189,8 +205,8 @@ void collect_trace(sa_ctx* c) {
       const u32* f = c->h_plans + size_t(r.sort_slot) * kPlanFlagWords;
       const bool skip = f[r.pass] != 0;
       const bool iota = f[2 * kMaxPasses + r.pass] != 0;
-      if (skip) continue;  // the launch returned at once; not a sweep
-      bytes = double(r.count) * (iota ? 20.0 : 24.0);
+      // A skipped pass returns at once: counted as a launch that moved nothing.
+      bytes = skip ? 0.0 : double(r.count) * (iota ? 20.0 : 24.0);
     }
     sa_kernel_stats& st = c->stats[r.kind];
     st.launches += 1;
@@ -201,38 +217,84 @@ void collect_trace(sa_ctx* c) {
   c->event_used = 0;
 }
 
-// Sorts (keysA, valsA or generated values) by the low 8*npass bits. The sorted
-// pairs end in the buffer named by plan->final_buf. The plan flags are copied to
-// h_plans slot `slot` on the stream.
-void run_sort(sa_ctx* c, u64 count, int npass, int vals_present, int slot, hipStream_t s) {
-  {
-    Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    // Clear the histograms and the ticket counters (slots 0 .. kCtrRerankTiles).
-    launch_fill_u64(c->hist, kMaxPasses * kRadix + kCtrRerankTiles + 1, 0, s);
-  }
-  {
-    Tracer t(c, s, SA_KERNEL_HISTOGRAM, double(count) * 8.0);
-    launch_radix_histogram(c->keysA, count, npass, c->hist, s);
-  }
-  {
-    Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    launch_radix_plan(c->hist, count, npass, vals_present, c->plan, s);
-  }
-  (void)hipMemcpyAsync(c->h_plans + size_t(slot) * kPlanFlagWords, c->plan->skip,
-                 kPlanFlagWords * sizeof(u32), hipMemcpyDeviceToHost, s);
-  for (int p = 0; p < npass; ++p) {
-    u32 gen = next_gen(c, s);
-    Tracer t(c, s, SA_KERNEL_SORT_PASS, 0, slot, p, count);
-    launch_onesweep_pass(c->keysA, c->keysB, c->valsA, c->valsB, count, p, c->plan, c->status,
-                         c->counters, gen, s);
+// Ping-pong buffers of one sort: input in (kA, vA), output in A or B.
+struct Bufs {
+  u64* kA;
+  u64* kB;
+  u32* vA;
+  u32* vB;
+};
+
+Bufs full_bufs(sa_ctx* c) { return Bufs{c->keysA, c->keysB, c->valsA, c->valsB}; }
+
+// Sweep geometry: tiles of kSortBlock * items pairs, chunks of a power-of-two
+// number of tiles so that at most kChunks chunks cover the input.
+SortGeom make_geom(u64 count, int items) {
+  SortGeom g;
+  g.count = count;
+  g.tile = u32(kSortBlock * items);
+  const u64 tiles = std::max<u64>(1, ceil_div(count, g.tile));
+  const u64 per = ceil_div(tiles, kChunks);
+  u32 lg = 0;
+  while ((u64(1) << lg) < per) ++lg;
+  g.ct_log2 = lg;
+  g.nchunks = u32(ceil_div(tiles, u64(1) << lg));
+  return g;
+}
+
+// Sweep workgroups one CU holds at once for each tile shape (register and LDS
+// limits of the kernel instances).
+int default_wgs_per_cu(int items) {
+  switch (items) {
+    case 8: return 4;
+    case 12: return 3;
+    case 24: return 1;
+    default: return 2;
   }
 }
 
-void run_rerank(sa_ctx* c, u64 count, u64 n, int b, u32* d_sa, hipStream_t s) {
+// Sorts (kA, vA or generated values) by the low 8*npass bits. The sorted pairs
+// end in the buffer named by plan->final_buf. The plan flags are copied to
+// h_plans slot `slot` on the stream.
+void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
+              hipStream_t s) {
+  const SortGeom geo = make_geom(count, c->sort_items);
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, 0);
+    // Chunk histograms and tickets; the re-rank ticket counter.
+    launch_fill_u32(c->hist_in, 2 * kChunkHistWords + kTicketWords, 0, s);
+    launch_fill_u64(c->counters, kCtrRerankTiles + 1, 0, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_HISTOGRAM, double(count) * 8.0);
+    launch_radix_histogram(bf.kA, geo, npass, c->hist_in, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, 0);
+    launch_radix_plan(c->hist_in, geo, npass, vals_present, c->plan, s);
+  }
+  (void)hipMemcpyAsync(c->h_plans + size_t(slot) * kPlanFlagWords, c->plan->skip,
+                       kPlanFlagWords * sizeof(u32), hipMemcpyDeviceToHost, s);
+  const u64 tiles = ceil_div(count, geo.tile);
+  const int per_cu = c->sort_wgs_per_cu > 0 ? c->sort_wgs_per_cu : default_wgs_per_cu(c->sort_items);
+  const u64 want = std::min<u64>(tiles, u64(c->num_cus) * u64(per_cu));
+  const u32 grid = u32(std::max<u64>(1, want / geo.nchunks) * geo.nchunks);
+  for (int p = 0; p < npass; ++p) {
+    u32 gen = next_gen(c, s);
+    Tracer t(c, s, SA_KERNEL_SORT_PASS, 0, slot, p, count);
+    launch_onesweep_pass(bf.kA, bf.kB, bf.vA, bf.vB, geo, p, c->plan, c->hist_in, c->hist_run,
+                         c->tickets, c->status, c->counters, gen, c->sort_items, grid, s);
+  }
+}
+
+void run_rerank(sa_ctx* c, const Bufs& bf, u64 count, u64 n, int b, int mode, u32* d_sa,
+                hipStream_t s) {
   u32 gen = next_gen(c, s);
-  Tracer t(c, s, SA_KERNEL_RERANK, double(count) * 16.0);
+  double bytes = double(count) * 16.0 + ((mode & kRerankWriteRanks) ? 4.0 * double(count) : 0.0) -
+                 ((mode & kRerankScatterIsa) ? 0.0 : 4.0 * double(count));
+  Tracer t(c, s, SA_KERNEL_RERANK, bytes);
   const u64 rt = c->rr_tiles_cap;
-  launch_rerank_compact(c->keysA, c->keysB, c->valsA, c->valsB, c->plan, count, n, b, c->isa, d_sa,
+  launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, count, n, b, mode, c->isa, d_sa,
                         c->act_idx, c->act_rank, c->st3, c->st3 + rt, c->st3 + 2 * rt,
                         c->counters, gen, s);
 }
@@ -254,6 +316,10 @@ u32 passes_run(const sa_ctx* c, int slot, int npass) {
   return r;
 }
 
+u32 final_buf_of(const sa_ctx* c, int slot) {
+  return c->h_plans[size_t(slot) * kPlanFlagWords + 3 * kMaxPasses];
+}
+
 sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_sa, u32* d_isa,
                        hipStream_t s) {
   std::memset(&c->info, 0, sizeof(c->info));
@@ -265,23 +331,25 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   sa_status st = ensure_workspace(c, n);
   if (st != SA_OK) return st;
 
-  // Round 0: alphabet, packed keys, full sort, names, discard.
+  // Round 0: alphabet, packed keys, full sort, names, discard. The ISA is not
+  // written yet; every sorted position's rank goes to the spare value buffer.
+  const Bufs full = full_bufs(c);
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    launch_fill_u64(c->hist, kMaxPasses * kRadix + kCtrCount, 0, s);
+    launch_fill_u64(c->counters, kCtrCount, 0, s);
     launch_fill_u64(reinterpret_cast<u64*>(c->present), 256 / 2, 0, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_OTHER, double(n));
     launch_byte_presence(text, n, c->present, s);
-    launch_alphabet_codes(c->present, c->code, c->counters, s);
+    launch_alphabet_codes(c->present, c->code, c->counters, c->round0_trim, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_PACK_TEXT, double(n) * 9.0);
     launch_pack_text(text, n, c->code, c->counters, c->keysA, s);
   }
-  run_sort(c, n, kMaxPasses, 0, 0, s);
-  run_rerank(c, n, n, 0, d_sa, s);
+  run_sort(c, full, n, kMaxPasses, 0, 0, s);
+  run_rerank(c, full, n, n, 0, kRerankWriteRanks, d_sa, s);
   st = readback(c, s);
   if (st != SA_OK) return st;
 
@@ -297,6 +365,39 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   info.prefix_len = h;
   u64 active = c->h_counters[kCtrActive];
 
+  // ISA after round 0: eager scatter, or lazy (survivors only) when few
+  // suffixes survive and the later rounds' buffers fit in the spare keys.
+  const u32 f0 = final_buf_of(c, 0);
+  const u64* keys0 = f0 ? c->keysB : c->keysA;
+  u64* spare = f0 ? c->keysA : c->keysB;
+  const bool fits = active * 24 <= n * 8;
+  bool lazy = false;
+  if (c->isa_mode == SA_ISA_LAZY)
+    lazy = fits;
+  else if (c->isa_mode == SA_ISA_AUTO)
+    lazy = fits && active * c->lazy_ratio <= n;
+  info.lazy_isa = lazy ? 1u : 0u;
+  if (active > 0 || d_isa) {
+    if (lazy) {
+      Tracer t(c, s, SA_KERNEL_OTHER, double(n) * 4.0 + double(active) * 12.0);
+      launch_fill_u32(c->isa, n, 0, s);
+      launch_isa_scatter_list(c->act_idx, c->act_rank, active, n, c->isa, s);
+    } else {
+      Tracer t(c, s, SA_KERNEL_ISA_SCATTER, double(n) * 12.0);
+      launch_isa_scatter_sorted(c->valsA, c->valsB, c->plan, n, c->isa, s);
+    }
+  }
+  // Later rounds sort at most `active` pairs; in lazy mode their buffers are
+  // carved out of the spare keys so that the round-0 sorted keys stay intact.
+  Bufs later = full;
+  if (lazy) {
+    const u64 a1 = std::max<u64>(active, 1);
+    later.kA = spare;
+    later.kB = spare + a1;
+    later.vA = reinterpret_cast<u32*>(spare + 2 * a1);
+    later.vB = later.vA + a1;
+  }
+
   // Later rounds: only suffixes whose name is still shared.
   const int b = bits_of(n);  // ranks and second ranks are <= n
   const int key_bits = 2 * b;
@@ -306,10 +407,15 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
     const int slot = int(info.rounds);
     {
       Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
-      launch_pack_pairs(c->act_idx, c->act_rank, active, n, h, b, c->isa, c->keysA, c->valsA, s);
+      if (lazy)
+        launch_pack_pairs_lazy(c->act_idx, c->act_rank, active, n, h, b, c->isa, text, c->code,
+                               c->counters, keys0, later.kA, later.vA, s);
+      else
+        launch_pack_pairs(c->act_idx, c->act_rank, active, n, h, b, c->isa, later.kA, later.vA,
+                          s);
     }
-    run_sort(c, active, npass, 1, slot, s);
-    run_rerank(c, active, n, b, d_sa, s);
+    run_sort(c, later, active, npass, 1, slot, s);
+    run_rerank(c, later, active, n, b, kRerankScatterIsa, d_sa, s);
     st = readback(c, s);
     if (st != SA_OK) return st;
     info.active[slot] = active;
@@ -321,9 +427,11 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
     active = c->h_counters[kCtrActive];
   }
   if (d_isa) {
+    if (lazy) launch_isa_complete(c->isa, n, text, c->code, c->counters, keys0, s);
     if (hipMemcpyAsync(d_isa, c->isa, n * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess)
       return SA_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return SA_EDEVICE;
+    if (hipGetLastError() != hipSuccess) return SA_EDEVICE;
   }
   return SA_OK;
 }
@@ -360,6 +468,10 @@ sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
   sa_ctx* c = new (std::nothrow) sa_ctx();
   if (!c) return SA_ENOMEM;
   c->device = device;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cus > 0)
+    c->num_cus = cus;
   std::memset(c->stats, 0, sizeof(c->stats));
   std::memset(&c->info, 0, sizeof(c->info));
   if (hipMalloc(&c->small, kSmallBytes) != hipSuccess) {
@@ -367,7 +479,9 @@ sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
     return SA_ENOMEM;
   }
   char* p = static_cast<char*>(c->small);
-  c->hist = reinterpret_cast<u64*>(p);
+  c->hist_in = reinterpret_cast<u32*>(p);
+  c->hist_run = c->hist_in + kChunkHistWords;
+  c->tickets = c->hist_run + kChunkHistWords;
   c->counters = reinterpret_cast<u64*>(p + kSmallHist);
   c->plan = reinterpret_cast<SortPlan*>(p + kSmallHist + kSmallCounters);
   c->present = reinterpret_cast<u32*>(p + kSmallHist + kSmallCounters + kSmallPlan);
@@ -433,7 +547,7 @@ sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, u
           hipSuccess)
     return SA_EDEVICE;
   const int npass = int(ceil_div(key_bits, kRadixBits));
-  run_sort(ctx, count, npass, 1, 0, s);
+  run_sort(ctx, full_bufs(ctx), count, npass, 1, 0, s);
   st = readback(ctx, s);  // also waits for the plan flags
   if (st != SA_OK) {
     ctx->recs.clear();
@@ -460,6 +574,38 @@ size_t sa_workspace_bytes(uint64_t n) {
 sa_status sa_ctx_set_trace(sa_ctx* ctx, int on) {
   if (!ctx) return SA_EINVAL;
   ctx->trace = on != 0;
+  return SA_OK;
+}
+
+sa_status sa_ctx_set_isa_mode(sa_ctx* ctx, int mode) {
+  if (!ctx || mode < SA_ISA_AUTO || mode > SA_ISA_LAZY) return SA_EINVAL;
+  ctx->isa_mode = mode;
+  return SA_OK;
+}
+
+sa_status sa_ctx_set_tuning(sa_ctx* ctx, const sa_tuning* t) {
+  if (!ctx || !t) return SA_EINVAL;
+  const u32 it = t->sort_items;
+  if (it != 8 && it != 12 && it != 16 && it != 20 && it != 24) return SA_EINVAL;
+  if (t->lazy_ratio < 3) return SA_EINVAL;
+  if (t->round0_full > 1) return SA_EINVAL;
+  if (t->sort_wgs_per_cu > 16) return SA_EINVAL;
+  for (u32 r : t->reserved)
+    if (r != 0) return SA_EINVAL;
+  ctx->sort_items = int(it);
+  ctx->lazy_ratio = t->lazy_ratio;
+  ctx->round0_trim = t->round0_full ? 0 : 1;
+  ctx->sort_wgs_per_cu = int(t->sort_wgs_per_cu);
+  return SA_OK;
+}
+
+sa_status sa_ctx_get_tuning(const sa_ctx* ctx, sa_tuning* out) {
+  if (!ctx || !out) return SA_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->sort_items = u32(ctx->sort_items);
+  out->lazy_ratio = u32(ctx->lazy_ratio);
+  out->round0_full = ctx->round0_trim ? 0u : 1u;
+  out->sort_wgs_per_cu = u32(ctx->sort_wgs_per_cu);
   return SA_OK;
 }
 

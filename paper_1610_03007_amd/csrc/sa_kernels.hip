@@ -19,6 +19,9 @@ namespace {
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// LDS index with one pad slot after every 8 entries.
+__device__ inline int pad8(int i) { return i + (i >> 3); }
+
 __device__ inline u32 wave_inclusive_sum(u32 v) {
   const int lane = lane_id();
 #pragma unroll
@@ -81,6 +84,62 @@ __device__ u64 lookback(u64* status, u64 stride, u64 tile, u64 agg, u32 gen, boo
   return excl;
 }
 
+// Look-back by one whole wave over a window of 64 earlier tiles per round trip:
+// lane l reads the status of tile hi - l; the wave combines the aggregates up
+// to the nearest inclusive prefix, or up to the nearest tile not yet published
+// and then waits on that one. Must be called by all 64 lanes with tile > 0.
+// Publishes the inclusive prefix from lane 0 and returns the exclusive one.
+__device__ u64 lookback_wave(u64* status, u64 tile, u64 agg, u32 gen, bool op_max, u64* counters,
+                             u32* timed_out) {
+  const int lane = lane_id();
+  u64 excl = 0;
+  long long hi = (long long)tile - 1;
+  u32 spins = 0;
+  for (;;) {
+    const long long t = hi - lane;
+    bool ready = true, pre = true;
+    u64 v = 0;
+    if (t >= 0) {
+      const u64 s = load_status(status + t);
+      const u32 f = status_flag(s);
+      ready = status_gen(s) == (gen & kGenMask) && f != 0;
+      pre = ready && f == kFlagPrefix;
+      v = ready ? status_value(s) : 0;
+    }
+    const u64 stop = __ballot(!ready || pre);
+    const u64 pres = __ballot(pre);
+    const int first = stop ? __ffsll((long long)stop) - 1 : kWave;
+    const bool first_pre = first < kWave && ((pres >> first) & 1u);
+    u64 x = (lane < first || (lane == first && first_pre)) ? v : 0;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const u64 y = __shfl_xor(x, off, kWave);
+      x = op_max ? (y > x ? y : x) : x + y;
+    }
+    excl = op_max ? (x > excl ? x : excl) : excl + x;
+    if (first_pre) break;
+    if (first == kWave) {
+      hi -= kWave;
+      continue;
+    }
+    hi -= first;  // wait for the nearest unpublished tile
+    if (++spins > kSpinLimit) {
+      if (lane == 0) {
+        atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+                 (unsigned long long)kErrLookbackTimeout);
+        *timed_out = 1;
+      }
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+  if (lane == 0) {
+    const u64 inc = op_max ? (agg > excl ? agg : excl) : excl + agg;
+    store_status(status + tile, status_pack(gen, kFlagPrefix, inc));
+  }
+  return excl;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -96,6 +155,18 @@ void launch_fill_u64(u64* p, u64 count, u64 value, hipStream_t s) {
   u64 blocks = ceil_div(count, 256);
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(u32(blocks)), dim3(256), 0, s, p, count, value);
+}
+
+__global__ void fill_u32_kernel(u32* p, u64 count, u32 value) {
+  u64 stride = u64(gridDim.x) * blockDim.x;
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = value;
+}
+
+void launch_fill_u32(u32* p, u64 count, u32 value, hipStream_t s) {
+  if (count == 0) return;
+  u64 blocks = ceil_div(count, 256);
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(u32(blocks)), dim3(256), 0, s, p, count, value);
 }
 
 __global__ void set_zero_u32_kernel(u32* p) { p[0] = 0; }
@@ -144,7 +215,8 @@ void launch_byte_presence(const u8* text, u64 n, u32* present, hipStream_t s) {
 
 __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restrict__ present,
                                                              u16* __restrict__ code,
-                                                             u64* __restrict__ counters) {
+                                                             u64* __restrict__ counters,
+                                                             int trim) {
   __shared__ u32 wsum[4];
   const int t = threadIdx.x;
   u32 p = present[t] ? 1u : 0u;
@@ -162,14 +234,24 @@ __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restri
     u32 sigma = total;
     u32 w = 32 - __clz(sigma);  // bits of sigma: codes 1..sigma, 0 = sentinel
     if (w == 0) w = 1;
+    // As many characters as fit in 64 bits; with `trim`, drop the characters
+    // that would only half-fill a last 8-bit radix digit, saving one sort pass
+    // over every suffix for a slightly shorter first prefix.
+    u32 c = 64 / w;
+    if (trim && (c * w) % kRadixBits != 0) {
+      const u32 ct = ((c * w) / kRadixBits) * kRadixBits / w;
+      if (ct >= 1) c = ct;
+    }
     counters[kCtrSigma] = sigma;
     counters[kCtrCodeBits] = w;
-    counters[kCtrChars] = 64 / w;
+    counters[kCtrChars] = c;
   }
 }
 
-void launch_alphabet_codes(const u32* present, u16* code, u64* counters, hipStream_t s) {
-  hipLaunchKernelGGL(alphabet_codes_kernel, dim3(1), dim3(256), 0, s, present, code, counters);
+void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int trim,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(alphabet_codes_kernel, dim3(1), dim3(256), 0, s, present, code, counters,
+                     trim);
 }
 
 // ---------------------------------------------------------------------------
@@ -256,21 +338,29 @@ void launch_pack_pairs(const u32* act_idx, const u32* act_rank, u64 count, u64 n
 
 constexpr int kHistItems = 8;
 
-__global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(const u64* __restrict__ keys,
-                                                                     u64 count, int npass,
-                                                                     u64* __restrict__ hist) {
+// Up-front digit histograms of every planned pass, per chunk of the input
+// (chunk c = tiles [c << ct_log2, (c + 1) << ct_log2)). Block b counts a
+// contiguous share of chunk b / per_chunk.
+__global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
+    const u64* __restrict__ keys, u64 count, int npass, u64 chunk_elems, u32 nchunks,
+    u32 per_chunk, u32* __restrict__ hist_in) {
   __shared__ u32 lh[kMaxPasses * kRadix];
   for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kHistBlock) lh[i] = 0;
   __syncthreads();
+  const u32 c = blockIdx.x / per_chunk;
+  const u32 g = blockIdx.x % per_chunk;
+  const u64 cs = u64(c) * chunk_elems;
+  u64 ce = cs + chunk_elems;
+  if (ce > count) ce = count;
   const int lane = lane_id();
-  const u64 chunk = u64(kHistBlock) * kHistItems;
-  for (u64 base = u64(blockIdx.x) * chunk; base < count; base += u64(gridDim.x) * chunk) {
+  const u64 step = u64(kHistBlock) * kHistItems;
+  for (u64 base = cs + u64(g) * step; base < ce; base += u64(per_chunk) * step) {
     u64 key[kHistItems];
     bool valid[kHistItems];
 #pragma unroll
     for (int j = 0; j < kHistItems; ++j) {
-      u64 e = base + u64(j) * kHistBlock + threadIdx.x;
-      valid[j] = e < count;
+      const u64 e = base + u64(j) * kHistBlock + threadIdx.x;
+      valid[j] = e < ce;
       key[j] = valid[j] ? keys[e] : 0;
     }
 #pragma unroll
@@ -278,9 +368,9 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(const u64* 
       const u64 vmask = __ballot(valid[j]);
       if (vmask == 0) continue;  // wave-uniform
       for (int p = 0; p < npass; ++p) {
-        u32 d = u32(key[j] >> (p * kRadixBits)) & (kRadix - 1);
+        const u32 d = u32(key[j] >> (p * kRadixBits)) & (kRadix - 1);
         // Valid lanes form a prefix of the wave, so lane 0 is valid here.
-        u32 d0 = __shfl(d, 0, kWave);
+        const u32 d0 = __shfl(d, 0, kWave);
         const u64 same = __ballot(valid[j] && d == d0);
         if (same == vmask) {
           if (lane == 0) atomicAdd(&lh[p * kRadix + d0], u32(__popcll(vmask)));
@@ -291,27 +381,32 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(const u64* 
     }
   }
   __syncthreads();
+  if (c >= nchunks) return;
   for (int i = threadIdx.x; i < npass * kRadix; i += kHistBlock) {
-    u32 v = lh[i];
-    if (v) atomicAdd(reinterpret_cast<unsigned long long*>(hist + i), (unsigned long long)v);
+    const u32 v = lh[i];
+    const int p = i / kRadix, d = i % kRadix;
+    if (v) atomicAdd(&hist_in[(size_t(p) * kChunks + c) * kRadix + d], v);
   }
 }
 
-void launch_radix_histogram(const u64* keys, u64 count, int npass, u64* hist, hipStream_t s) {
-  if (count == 0) return;
-  u64 blocks = ceil_div(count, u64(kHistBlock) * kHistItems * 4);
-  if (blocks > 2048) blocks = 2048;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(radix_histogram_kernel, dim3(u32(blocks)), dim3(kHistBlock), 0, s, keys,
-                     count, npass, hist);
+void launch_radix_histogram(const u64* keys, const SortGeom& geo, int npass, u32* hist_in,
+                            hipStream_t s) {
+  if (geo.count == 0) return;
+  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
+  u64 per = ceil_div(chunk_elems, u64(kHistBlock) * kHistItems * 4);
+  const u64 cap = ceil_div(2048, geo.nchunks);
+  if (per > cap) per = cap;
+  if (per < 1) per = 1;
+  hipLaunchKernelGGL(radix_histogram_kernel, dim3(u32(per * geo.nchunks)), dim3(kHistBlock), 0, s,
+                     keys, geo.count, npass, chunk_elems, geo.nchunks, u32(per), hist_in);
 }
 
-
-// Exclusive digit offsets per pass, constant-digit passes marked skipped, and
-// the ping-pong schedule of the passes that run. One workgroup, one thread per
-// digit value.
-__global__ __launch_bounds__(kRadix) void radix_plan_kernel(const u64* __restrict__ hist,
-                                                            u64 count, int npass, int vals_present,
+// Global digit offsets per pass (sums of the chunk histograms), constant-digit
+// passes marked skipped, and the ping-pong schedule of the passes that run.
+// One workgroup, one thread per digit value.
+__global__ __launch_bounds__(kRadix) void radix_plan_kernel(const u32* __restrict__ hist_in,
+                                                            u32 nchunks, u64 count, int npass,
+                                                            int vals_present,
                                                             SortPlan* __restrict__ plan) {
   __shared__ u64 sc[kMaxPasses][kRadix];
   __shared__ u32 s_skip[kMaxPasses];
@@ -321,9 +416,12 @@ __global__ __launch_bounds__(kRadix) void radix_plan_kernel(const u64* __restric
   u64 own[kMaxPasses];
 #pragma unroll
   for (int p = 0; p < kMaxPasses; ++p) {
-    own[p] = (p < npass) ? hist[p * kRadix + d] : 0;
-    sc[p][d] = own[p];
-    if (p < npass && own[p] == count) s_skip[p] = 1;  // one digit holds every key
+    u64 h = 0;
+    if (p < npass)
+      for (u32 c = 0; c < nchunks; ++c) h += hist_in[(size_t(p) * kChunks + c) * kRadix + d];
+    own[p] = h;
+    sc[p][d] = h;
+    if (p < npass && h == count) s_skip[p] = 1;  // one digit holds every key
   }
   __syncthreads();
   // Hillis-Steele inclusive scans over the digits of every pass at once.
@@ -339,57 +437,70 @@ __global__ __launch_bounds__(kRadix) void radix_plan_kernel(const u64* __restric
 #pragma unroll
   for (int p = 0; p < kMaxPasses; ++p) plan->offsets[p][d] = sc[p][d] - own[p];
   if (d == 0) {
+    u32 run[kMaxPasses];
+    u32 nrun = 0;
+    for (int p = 0; p < kMaxPasses; ++p) {
+      run[p] = (p < npass && !s_skip[p]) ? 1u : 0u;
+      nrun += run[p];
+    }
+    if (nrun == 0) run[npass - 1] = 1;  // all keys equal: one stable copy pass
     u32 cur = 0;
     bool first = true;
+    int prev = -1;
     for (int p = 0; p < kMaxPasses; ++p) {
-      bool run = (p < npass) && !s_skip[p];
-      plan->skip[p] = run ? 0u : 1u;
+      plan->skip[p] = run[p] ? 0u : 1u;
       plan->src[p] = cur;
       plan->iota[p] = 0;
-      if (run) {
+      plan->next_run[p] = -1;
+      if (run[p]) {
         plan->iota[p] = (!vals_present && first) ? 1u : 0u;
+        if (first) plan->first_run = u32(p);
+        if (prev >= 0) plan->next_run[prev] = p;
         first = false;
+        prev = p;
         cur ^= 1u;
       }
-    }
-    if (first) {
-      // Every digit is constant (all keys equal): run the top pass anyway; it
-      // is a stable copy that also materialises generated values.
-      int p = npass - 1;
-      plan->skip[p] = 0;
-      plan->src[p] = 0;
-      plan->iota[p] = vals_present ? 0u : 1u;
-      cur = 1;
     }
     plan->final_buf = cur;
   }
 }
 
-void launch_radix_plan(const u64* hist, u64 count, int npass, int vals_present, SortPlan* plan,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(radix_plan_kernel, dim3(1), dim3(kRadix), 0, s, hist, count, npass,
-                     vals_present, plan);
+void launch_radix_plan(const u32* hist_in, const SortGeom& geo, int npass, int vals_present,
+                       SortPlan* plan, hipStream_t s) {
+  hipLaunchKernelGGL(radix_plan_kernel, dim3(1), dim3(kRadix), 0, s, hist_in, geo.nchunks,
+                     geo.count, npass, vals_present, plan);
 }
 
-// One stable counting pass over digit `pass`. Per tile: load 16 items per
-// thread in wave-striped order, rank every item among equal digits of its wave
-// with eight ballots (the match mask) and a per-wave LDS counter, combine the
-// waves, publish the tile's digit counts, look back for the counts of earlier
-// tiles, reorder the tile by digit in LDS and write each digit's run out
-// contiguously.
+// One stable counting sweep over digit `pass`, persistent: workgroup b works on
+// chunk b % nchunks and takes that chunk's tiles in order from a ticket. Per
+// tile of kSortBlock * ITEMS pairs: load ITEMS items per thread in
+// wave-striped order; rank every item among the equal digits of its wave (an
+// eight-ballot match mask, and one LDS fetch-add per match group issued back
+// to back for all items, which a wave executes in program order); combine the
+// waves; publish the tile's digit counts and look back (inside the chunk) for
+// the counts of earlier tiles; reorder the keys by digit in LDS and write each
+// digit's run out contiguously, then the values through the same LDS buffer.
+// While writing keys it counts, per output chunk, the digit of the next sweep
+// that runs, so that sweep starts with exact chunk bases as well.
+template <int ITEMS>
 __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
     u64* __restrict__ keysA, u64* __restrict__ keysB, u32* __restrict__ valsA,
-    u32* __restrict__ valsB, u64 count, int pass, const SortPlan* __restrict__ plan,
-    u64* __restrict__ status, u64* __restrict__ counters, u32 gen) {
+    u32* __restrict__ valsB, u64 count, int pass, u32 ct_log2, u32 nchunks,
+    const SortPlan* __restrict__ plan, const u32* __restrict__ hist_in,
+    u32* __restrict__ hist_run, u32* __restrict__ tickets, u64* __restrict__ status,
+    u64* __restrict__ counters, u32 gen) {
   static_assert(kSortBlock == kRadix, "one thread per digit value");
   constexpr int NW = kSortBlock / kWave;
-  __shared__ u64 s_keys[kSortTile];
-  __shared__ u32 s_vals[kSortTile];
+  constexpr int TILE = kSortBlock * ITEMS;
+  __shared__ u64 s_buf[TILE];  // keys, then values (as u32)
+  __shared__ u8 s_dig[TILE];   // digit of each reordered position
   __shared__ u32 s_cnt[NW][kRadix];
+  __shared__ u32 s_next[kChunks * kRadix];
   __shared__ u32 s_start[kRadix];
   __shared__ u64 s_base[kRadix];
+  __shared__ u64 s_cbase[kRadix];
   __shared__ u32 s_wsum[NW];
-  __shared__ u64 s_tile;
+  __shared__ u32 s_ticket;
   __shared__ u32 s_abort;
 
   if (plan->skip[pass]) return;
@@ -400,123 +511,191 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
   const u32* vin = src ? valsB : valsA;
   u32* vout = src ? valsA : valsB;
   const int shift = pass * kRadixBits;
+  const int next = plan->next_run[pass];
+  const int nshift = next >= 0 ? next * kRadixBits : 0;
 
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
-  if (tid == 0) {
-    s_tile = atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrSortTiles + pass),
-                       1ull);
-    s_abort = 0;
-  }
-#pragma unroll
-  for (int w = 0; w < NW; ++w) s_cnt[w][tid] = 0;
-  __syncthreads();
-  const u64 tile = s_tile;
-  const u64 tile_base = tile * kSortTile;
-  const u64 wave_base = tile_base + u64(wave) * (kSortItems * kWave);
+  const u32 chunk = blockIdx.x % nchunks;
+  const u64 tiles = ceil_div(count, u64(TILE));
+  const u64 c_first = u64(chunk) << ct_log2;
+  u64 c_end = c_first + (u64(1) << ct_log2);
+  if (c_end > tiles) c_end = tiles;
 
-  u64 key[kSortItems];
-  u32 val[kSortItems];
-  u32 rank[kSortItems];
-#pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    u64 e = wave_base + u64(j) * kWave + lane;
-    if (e < count) {
-      key[j] = kin[e];
-      val[j] = iota ? u32(e) : vin[e];
-    } else {
-      key[j] = ~u64(0);  // digit 255: lands after every valid item of the tile
-      val[j] = 0;
+  // Start of each digit's output range for this chunk: global digit offset
+  // plus that digit's count in the earlier chunks.
+  {
+    const u32* h = (u32(pass) == plan->first_run ? hist_in : hist_run) +
+                   size_t(pass) * kChunks * kRadix;
+    u64 b = plan->offsets[pass][tid];
+    for (u32 c = 0; c < chunk; ++c) b += h[c * kRadix + tid];
+    s_cbase[tid] = b;
+  }
+  for (int i = tid; i < kChunks * kRadix; i += kSortBlock) s_next[i] = 0;
+
+  for (;;) {
+    if (tid == 0) {
+      s_ticket = atomicAdd(tickets + pass * kChunks + chunk, 1u);
+      s_abort = 0;
     }
-  }
+#pragma unroll
+    for (int w = 0; w < NW; ++w) s_cnt[w][tid] = 0;
+    __syncthreads();
+    const u64 tile = c_first + s_ticket;
+    if (tile >= c_end) break;  // uniform
+    const u64 tile_base = tile * TILE;
+    const u64 wave_base = tile_base + u64(wave) * (ITEMS * kWave);
+    // Items of this wave that exist (all of them except in the last tile).
+    const u64 wleft = count > wave_base ? count - wave_base : 0;
+    const u32 wvalid = wleft < u64(ITEMS * kWave) ? u32(wleft) : u32(ITEMS * kWave);
+    const u64* kin_w = kin + wave_base;
 
-  // Rank within the wave, items taken in (j, lane) order == input order. The
-  // counters are read by every lane and bumped by the lowest lane of each
-  // digit's match set; volatile keeps every access a real LDS access, which a
-  // wave issues in program order.
-  volatile u32* cnt = &s_cnt[wave][0];
-  const u64 lt_mask = (u64(1) << lane) - 1;
+    // Keys and values are both requested up front: a value load issued after
+    // the key stores would wait behind them.
+    u64 key[ITEMS];
+    u32 val[ITEMS];
+    const u32* vin_w = vin + wave_base;
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const u32 d = u32(key[j] >> shift) & (kRadix - 1);
-    u64 peers = ~u64(0);
-#pragma unroll
-    for (int b = 0; b < kRadixBits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const u64 bal = __ballot(bit);
-      peers &= bit ? bal : ~bal;
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 e = u32(j * kWave + lane);
+      key[j] = (e < wvalid) ? kin_w[e] : ~u64(0);  // digit 255: after every valid item
     }
-    const u32 below = __popcll(peers & lt_mask);
-    const u32 old = cnt[d];
-    if (below == 0) cnt[d] = old + u32(__popcll(peers));
-    rank[j] = old + below;
-  }
-  __syncthreads();
-
-  // Per digit (one per thread): exclusive prefix over waves, tile total.
-  u32 tot = 0;
 #pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    u32 c = s_cnt[w][tid];
-    s_cnt[w][tid] = tot;
-    tot += c;
-  }
-  u64* my_status = status + tile * kRadix + tid;
-  if (tile == 0)
-    store_status(my_status, status_pack(gen, kFlagPrefix, tot));
-  else
-    store_status(my_status, status_pack(gen, kFlagAggregate, tot));
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 e = u32(j * kWave + lane);
+      val[j] = (e < wvalid) ? (iota ? u32(wave_base + e) : vin_w[e]) : 0u;
+    }
 
-  // Exclusive scan of the tile totals over digits: tile-local run starts.
-  const u32 inc = wave_inclusive_sum(tot);
-  if (lane == kWave - 1) s_wsum[wave] = inc;
-  __syncthreads();
-  u32 woff = 0;
+    // Rank within the wave, items in (j, lane) order == input order.
+    u32* cnt = &s_cnt[wave][0];
+    const u64 lt_mask = (u64(1) << lane) - 1;
+    u32 rank[ITEMS];
+    u32 packed[ITEMS];  // below | leader << 8
 #pragma unroll
-  for (int w = 0; w < NW; ++w)
-    if (w < wave) woff += s_wsum[w];
-  const u32 start = woff + inc - tot;
-  s_start[tid] = start;
-
-  u64 excl = 0;
-  if (tile > 0) excl = lookback(status + tid, kRadix, tile, tot, gen, false, counters, &s_abort);
-  s_base[tid] = plan->offsets[pass][tid] + excl - u64(start);
-  __syncthreads();
-
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 d = u32(key[j] >> shift) & (kRadix - 1);
+      u64 peers = ~u64(0);
 #pragma unroll
-  for (int j = 0; j < kSortItems; ++j) {
-    const u32 d = u32(key[j] >> shift) & (kRadix - 1);
-    const u32 q = s_start[d] + s_cnt[wave][d] + rank[j];
-    s_keys[q] = key[j];
-    s_vals[q] = val[j];
-  }
-  __syncthreads();
+      for (int b = 0; b < kRadixBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const u64 bal = __ballot(bit);
+        peers &= bit ? bal : ~bal;
+      }
+      const u32 leader = u32(__ffsll((long long)peers) - 1);
+      packed[j] = u32(__popcll(peers & lt_mask)) | (leader << 8);
+      u32 old = 0;
+      if (u32(lane) == leader)
+        old = __hip_atomic_fetch_add(cnt + d, u32(__popcll(peers)), __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+      rank[j] = old;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+      rank[j] = __shfl(rank[j], int(packed[j] >> 8), kWave) + (packed[j] & 0xFFu);
+    __syncthreads();
 
-  if (s_abort) return;
-  const u64 left = count - tile_base;
-  const u32 valid = left < u64(kSortTile) ? u32(left) : u32(kSortTile);
-  for (u32 q = tid; q < valid; q += kSortBlock) {
-    const u64 k = s_keys[q];
-    const u32 d = u32(k >> shift) & (kRadix - 1);
-    const u64 o = s_base[d] + q;
-    if (o < count) {
-      kout[o] = k;
-      vout[o] = s_vals[q];
-    } else {
-      atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
-               (unsigned long long)kErrBounds);
+    // Per digit (one per thread): exclusive prefix over waves, tile total.
+    u32 tot = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const u32 c = s_cnt[w][tid];
+      s_cnt[w][tid] = tot;
+      tot += c;
+    }
+    u64* my_status = status + tile * kRadix + tid;
+    store_status(my_status,
+                 status_pack(gen, tile == c_first ? kFlagPrefix : kFlagAggregate, tot));
+
+    // Exclusive scan of the tile totals over digits: tile-local run starts.
+    const u32 inc = wave_inclusive_sum(tot);
+    if (lane == kWave - 1) s_wsum[wave] = inc;
+    __syncthreads();
+    u32 woff = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w)
+      if (w < wave) woff += s_wsum[w];
+    const u32 start = woff + inc - tot;
+    s_start[tid] = start;
+
+    // The chunk's first tile publishes a prefix, so the look-back never
+    // leaves the chunk.
+    u64 excl = 0;
+    if (tile > c_first)
+      excl = lookback(status + tid, kRadix, tile, tot, gen, false, counters, &s_abort);
+    s_base[tid] = s_cbase[tid] + excl - u64(start);
+    __syncthreads();
+
+    // Tile-local position of each item: its digit's run start, the wave's
+    // offset in that run, its rank in the wave.
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 d = u32(key[j] >> shift) & (kRadix - 1);
+      rank[j] += s_start[d] + s_cnt[wave][d];
+      s_buf[rank[j]] = key[j];
+      s_dig[rank[j]] = u8(d);
+    }
+    __syncthreads();
+    if (s_abort) return;
+
+    const u64 left = count - tile_base;
+    const u32 valid = left < u64(TILE) ? u32(left) : u32(TILE);
+    for (u32 q = tid; q < valid; q += kSortBlock) {
+      const u64 k = s_buf[q];
+      const u64 o = s_base[s_dig[q]] + q;
+      if (o < count) {
+        kout[o] = k;
+        if (next >= 0) {
+          const u32 oc = u32((o / u64(TILE)) >> ct_log2);
+          atomicAdd(&s_next[oc * kRadix + (u32(k >> nshift) & (kRadix - 1))], 1u);
+        }
+      }
+    }
+    __syncthreads();
+    u32* s_vals = reinterpret_cast<u32*>(s_buf);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+      const u32 e = u32(j * kWave + lane);
+      if (e < wvalid) s_vals[rank[j]] = val[j];
+    }
+    __syncthreads();
+    for (u32 q = tid; q < valid; q += kSortBlock) {
+      const u64 o = s_base[s_dig[q]] + q;
+      if (o < count) {
+        vout[o] = s_vals[q];
+      } else {
+        atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+                 (unsigned long long)kErrBounds);
+      }
+    }
+    __syncthreads();
+  }
+  if (next >= 0) {
+    u32* h = hist_run + size_t(next) * kChunks * kRadix;
+    for (int i = tid; i < kChunks * kRadix; i += kSortBlock) {
+      const u32 v = s_next[i];
+      if (v) atomicAdd(h + i, v);
     }
   }
 }
 
-void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, u64 count, int pass,
-                          const SortPlan* plan, u64* status, u64* counters, u32 gen,
-                          hipStream_t s) {
-  if (count == 0) return;
-  const u64 tiles = ceil_div(count, kSortTile);
-  hipLaunchKernelGGL(onesweep_pass_kernel, dim3(u32(tiles)), dim3(kSortBlock), 0, s, keysA, keysB,
-                     valsA, valsB, count, pass, plan, status, counters, gen);
+void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
+                          int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
+                          u32* tickets, u64* status, u64* counters, u32 gen, int items,
+                          u32 grid, hipStream_t s) {
+  if (geo.count == 0) return;
+#define SA_ONESWEEP(IT)                                                                          \
+  hipLaunchKernelGGL(onesweep_pass_kernel<IT>, dim3(grid), dim3(kSortBlock), 0, s, keysA, keysB, \
+                     valsA, valsB, geo.count, pass, geo.ct_log2, geo.nchunks, plan, hist_in,     \
+                     hist_run, tickets, status, counters, gen)
+  switch (items) {
+    case 8: SA_ONESWEEP(8); break;
+    case 12: SA_ONESWEEP(12); break;
+    case 20: SA_ONESWEEP(20); break;
+    case 24: SA_ONESWEEP(24); break;
+    default: SA_ONESWEEP(16); break;
+  }
+#undef SA_ONESWEEP
 }
 
 // ---------------------------------------------------------------------------
@@ -534,21 +713,23 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, u64 co
 // In round 0 every element starts in one group with r0 = 1.
 // An element is unique when it is a head and the next element is a head too
 // (Alg. 6 `Unique`); its rank is final, so SA[newrank - 1] = its position and it
-// is discarded. All others survive, in sorted order. Every element's new rank
-// goes to ISA[text position] because any suffix may be gathered later.
+// is discarded. All others survive, in sorted order.
+//
+// Layout: each wave owns kRerankItems * 64 consecutive elements, lane l of item
+// j holding element j * 64 + l, so every load and store is coalesced; the scans
+// run per item across the wave with a carry from the previous item, then
+// across the waves of the block, then across tiles by decoupled look-back.
 __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
-    const SortPlan* __restrict__ plan, u64 count, u64 n, int b, u32* __restrict__ isa,
-    u32* __restrict__ sa_out, u32* __restrict__ act_idx, u32* __restrict__ act_rank,
-    u64* __restrict__ st_head, u64* __restrict__ st_grp, u64* __restrict__ st_surv,
-    u64* __restrict__ counters, u32 gen) {
+    const SortPlan* __restrict__ plan, u64 count, u64 n, int b, int mode,
+    u32* __restrict__ isa, u32* __restrict__ sa_out, u32* __restrict__ act_idx,
+    u32* __restrict__ act_rank, u64* __restrict__ st_head, u64* __restrict__ st_grp,
+    u64* __restrict__ st_surv, u64* __restrict__ counters, u32 gen) {
   constexpr int NW = kRerankBlock / kWave;
-  constexpr int T = kRerankTile;
   constexpr int I = kRerankItems;
-  __shared__ u64 s_k[T + 2];
-  __shared__ u32 s_v[T];
-  __shared__ u64 s_wh[NW], s_wg[NW], s_ws[NW];
+  constexpr int T = kRerankTile;
+  __shared__ u32 s_wh[NW], s_wg[NW], s_ws[NW];
   __shared__ u64 s_prefix[3];
   __shared__ u64 s_tile;
   __shared__ u32 s_abort;
@@ -556,6 +737,11 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const u32 fb = plan->final_buf;
   const u64* keys = fb ? keysB : keysA;
   const u32* vals = fb ? valsB : valsA;
+  // The other value buffer is free after the sort: it receives the new rank
+  // of every sorted position when kRerankWriteRanks is set.
+  u32* ranks_out = const_cast<u32*>(fb ? valsA : valsB);
+  const bool scatter = (mode & kRerankScatterIsa) != 0;
+  const bool write_ranks = (mode & kRerankWriteRanks) != 0;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
@@ -566,133 +752,278 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   __syncthreads();
   const u64 tile = s_tile;
   const u64 base = tile * T;
+  const u32 wofs = u32(wave) * (I * kWave);  // wave start within the tile
+  const u64 wbase = base + wofs;
 
-  for (int i = tid; i < T; i += kRerankBlock) {
-    u64 p = base + u64(i);
-    s_k[i + 1] = (p < count) ? keys[p] : 0;
-    s_v[i] = (p < count) ? vals[p] : 0;
-  }
-  if (tid == 0) s_k[0] = (base > 0) ? keys[base - 1] : 0;
-  if (tid == 1) s_k[T + 1] = (base + T < count) ? keys[base + T] : 0;
-  __syncthreads();
-
-  // Thread-local flags over I consecutive elements.
-  const int first = tid * I;
-  u64 th_head = 0, th_grp = 0, th_surv = 0;  // max head pos, max group pos, survivors
-  u32 flags = 0;                             // bit j: head, bit 8+j: grp, bit 16+j: unique
+  u64 k[I];
+  u32 v[I];
 #pragma unroll
   for (int j = 0; j < I; ++j) {
-    const u64 p = base + u64(first + j);
-    if (p >= count) break;
-    const u64 k = s_k[first + j + 1];
-    const u64 kp = s_k[first + j];
-    const u64 kn = s_k[first + j + 2];
-    const bool head = (p == 0) || (k != kp);
-    const bool grp = (p == 0) || (b > 0 && (k >> b) != (kp >> b));
-    const bool next_head = (p + 1 == count) || (kn != k);
-    const bool uniq = head && next_head;
-    if (head) {
-      th_head = p;
-      flags |= 1u << j;
-    }
-    if (grp) {
-      th_grp = p;
-      flags |= 1u << (8 + j);
-    }
-    if (uniq) flags |= 1u << (16 + j);
-    else th_surv += 1;
+    const u64 p = wbase + u64(j * kWave + lane);
+    k[j] = (p < count) ? keys[p] : 0;
+    v[j] = (p < count) ? vals[p] : 0;
   }
+  const u64 k_before = (wbase > 0 && wbase - 1 < count) ? keys[wbase - 1] : 0;
+  const u64 k_after = (wbase + I * kWave < count) ? keys[wbase + I * kWave] : 0;
 
-  // Block-wide scans: inclusive max for heads and groups, inclusive sum for survivors.
-  const u64 ih = wave_inclusive_max64(th_head);
-  const u64 ig = wave_inclusive_max64(th_grp);
-  const u64 is = wave_inclusive_sum64(th_surv);
-  if (lane == kWave - 1) {
-    s_wh[wave] = ih;
-    s_wg[wave] = ig;
-    s_ws[wave] = is;
+  // Flags and wave-level scans with a carry across items. Positions inside the
+  // tile are stored + 1 so that 0 means "none yet".
+  u32 hin[I], gin[I], sin[I];
+  u32 flags = 0;  // bit j: head, bit 8+j: group start, bit 16+j: unique
+  u32 ch = 0, cg = 0, cs = 0;
+#pragma unroll
+  for (int j = 0; j < I; ++j) {
+    const u32 lp = wofs + u32(j * kWave + lane);
+    const u64 p = base + lp;
+    // Neighbour keys; every lane takes part in each shuffle (a lane reading
+    // from an inactive lane would get no data).
+    u64 kp = __shfl_up(k[j], 1, kWave);
+    const u64 kp_edge = (j > 0) ? __shfl(k[j > 0 ? j - 1 : 0], kWave - 1, kWave) : k_before;
+    if (lane == 0) kp = kp_edge;
+    u64 kn = __shfl_down(k[j], 1, kWave);
+    const u64 kn_edge = (j + 1 < I) ? __shfl(k[j + 1 < I ? j + 1 : j], 0, kWave) : k_after;
+    if (lane == kWave - 1) kn = kn_edge;
+    const bool valid = p < count;
+    const bool head = valid && ((p == 0) || (k[j] != kp));
+    const bool grp = valid && ((p == 0) || (b > 0 && (k[j] >> b) != (kp >> b)));
+    const bool uniq = head && ((p + 1 == count) || (kn != k[j]));
+    if (head) flags |= 1u << j;
+    if (grp) flags |= 1u << (8 + j);
+    if (uniq) flags |= 1u << (16 + j);
+    const u32 hv = head ? lp + 1 : 0;
+    const u32 gv = grp ? lp + 1 : 0;
+    const u32 sv = (valid && !uniq) ? 1u : 0u;
+    u32 ih = hv, ig = gv, is = sv;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+      const u32 th = __shfl_up(ih, off, kWave);
+      const u32 tg = __shfl_up(ig, off, kWave);
+      const u32 ts = __shfl_up(is, off, kWave);
+      if (lane >= off) {
+        ih = th > ih ? th : ih;
+        ig = tg > ig ? tg : ig;
+        is += ts;
+      }
+    }
+    hin[j] = ih > ch ? ih : ch;
+    gin[j] = ig > cg ? ig : cg;
+    sin[j] = is + cs;
+    ch = __shfl(hin[j], kWave - 1, kWave);
+    cg = __shfl(gin[j], kWave - 1, kWave);
+    cs = __shfl(sin[j], kWave - 1, kWave);
+  }
+  if (lane == 0) {
+    s_wh[wave] = ch;
+    s_wg[wave] = cg;
+    s_ws[wave] = cs;
   }
   __syncthreads();
-  u64 bh = 0, bg = 0, bs = 0;        // exclusive over earlier waves
-  u64 tot_h = 0, tot_g = 0, tot_s = 0;
+  u32 eh = 0, eg = 0, es = 0, th = 0, tg = 0, ts = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
+    const u32 a = s_wh[w], g = s_wg[w], c = s_ws[w];
     if (w < wave) {
-      bh = s_wh[w] > bh ? s_wh[w] : bh;
-      bg = s_wg[w] > bg ? s_wg[w] : bg;
-      bs += s_ws[w];
+      eh = a > eh ? a : eh;
+      eg = g > eg ? g : eg;
+      es += c;
     }
-    tot_h = s_wh[w] > tot_h ? s_wh[w] : tot_h;
-    tot_g = s_wg[w] > tot_g ? s_wg[w] : tot_g;
-    tot_s += s_ws[w];
+    th = a > th ? a : th;
+    tg = g > tg ? g : tg;
+    ts += c;
   }
-  // Exclusive within the block for this thread.
-  u64 eh = __shfl_up(ih, 1, kWave);
-  u64 eg = __shfl_up(ig, 1, kWave);
-  u64 es = is - th_surv;
-  if (lane == 0) {
-    eh = 0;
-    eg = 0;
-  }
-  eh = eh > bh ? eh : bh;
-  eg = eg > bg ? eg : bg;
-  es += bs;
 
-  // Tile prefixes from earlier tiles (threads 0..2 of wave 0 look back).
-  if (tid < 3) {
-    u64* st = tid == 0 ? st_head : (tid == 1 ? st_grp : st_surv);
-    const u64 agg = tid == 0 ? tot_h : (tid == 1 ? tot_g : tot_s);
+  // Tile prefixes from earlier tiles: waves 0, 1, 2 look back for the head,
+  // group and survivor scans. Head and group are max-scans of global positions
+  // (0 is the identity: position 0 is always a head and a group start); the
+  // survivor scan is a sum.
+  if (wave < 3) {
+    u64* st = wave == 0 ? st_head : (wave == 1 ? st_grp : st_surv);
+    const u32 loc = wave == 0 ? th : (wave == 1 ? tg : 0);
+    const u64 agg = wave == 2 ? u64(ts) : (loc ? base + loc - 1 : 0);
     u64 pre = 0;
-    if (tile == 0)
-      store_status(st, status_pack(gen, kFlagPrefix, agg));
-    else {
-      store_status(st + tile, status_pack(gen, kFlagAggregate, agg));
-      pre = lookback(st, 1, tile, agg, gen, tid != 2, counters, &s_abort);
+    if (tile == 0) {
+      if (lane == 0) store_status(st, status_pack(gen, kFlagPrefix, agg));
+    } else {
+      if (lane == 0) store_status(st + tile, status_pack(gen, kFlagAggregate, agg));
+      pre = lookback_wave(st, tile, agg, gen, wave != 2, counters, &s_abort);
     }
-    s_prefix[tid] = pre;
-    if (tid == 2 && base + T >= count) counters[kCtrActive] = pre + agg;  // last tile
+    if (lane == 0) {
+      s_prefix[wave] = pre;
+      if (wave == 2 && base + T >= count) counters[kCtrActive] = pre + agg;  // last tile
+    }
   }
   __syncthreads();
   if (s_abort) return;
-  u64 ss = s_prefix[0] > eh ? s_prefix[0] : eh;
-  u64 gs = s_prefix[1] > eg ? s_prefix[1] : eg;
-  u64 out = s_prefix[2] + es;
 
 #pragma unroll
   for (int j = 0; j < I; ++j) {
-    const u64 p = base + u64(first + j);
+    const u32 lp = wofs + u32(j * kWave + lane);
+    const u64 p = base + lp;
     if (p >= count) break;
-    if (flags & (1u << j)) ss = p;
-    if (flags & (1u << (8 + j))) gs = p;
-    const u64 k = s_k[first + j + 1];
-    const u32 v = s_v[first + j];
-    const u64 r0 = b > 0 ? (k >> b) : 1;
+    const u32 h = hin[j] > eh ? hin[j] : eh;
+    const u32 g = gin[j] > eg ? gin[j] : eg;
+    const u64 ss = h ? base + h - 1 : s_prefix[0];
+    const u64 gs = g ? base + g - 1 : s_prefix[1];
+    const u64 r0 = b > 0 ? (k[j] >> b) : 1;
     const u64 nr = r0 + ss - gs;
-    if (v >= n || nr == 0 || nr > n || out >= count) {
+    const bool uniq = (flags >> (16 + j)) & 1u;
+    const u64 out = s_prefix[2] + es + sin[j] - (uniq ? 0u : 1u);
+    if (v[j] >= n || nr == 0 || nr > n || (!uniq && out >= count)) {
       atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
                (unsigned long long)kErrBounds);
       break;
     }
-    isa[v] = u32(nr);
-    if (flags & (1u << (16 + j))) {
-      sa_out[nr - 1] = v;
+    if (scatter) isa[v[j]] = u32(nr);
+    if (write_ranks) ranks_out[p] = u32(nr);
+    if (uniq) {
+      sa_out[nr - 1] = v[j];
     } else {
-      act_idx[out] = v;
+      act_idx[out] = v[j];
       act_rank[out] = u32(nr);
-      ++out;
     }
   }
 }
 
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            const u32* valsB, const SortPlan* plan, u64 count, u64 n, int b,
-                           u32* isa, u32* sa_out, u32* act_idx, u32* act_rank, u64* st_head,
-                           u64* st_grp, u64* st_surv, u64* counters, u32 gen, hipStream_t s) {
+                           int mode, u32* isa, u32* sa_out, u32* act_idx, u32* act_rank,
+                           u64* st_head, u64* st_grp, u64* st_surv, u64* counters, u32 gen,
+                           hipStream_t s) {
   if (count == 0) return;
   const u64 tiles = ceil_div(count, kRerankTile);
   hipLaunchKernelGGL(rerank_compact_kernel, dim3(u32(tiles)), dim3(kRerankBlock), 0, s, keysA,
-                     keysB, valsA, valsB, plan, count, n, b, isa, sa_out, act_idx, act_rank, st_head,
+                     keysB, valsA, valsB, plan, count, n, b, mode, isa, sa_out, act_idx, act_rank,
+                     st_head,
                      st_grp, st_surv, counters, gen);
+}
+
+// ---------------------------------------------------------------------------
+// Inverse suffix array after round 0.
+//
+// Eager form: ISA[text position] = rank for every sorted position (one random
+// 4-byte write per suffix). Lazy form, used when few suffixes survive round 0:
+// ISA is cleared, only the survivors' ranks are written, and a later gather
+// that finds 0 recomputes the round-0 rank of position j as 1 + the number of
+// round-0 keys below key(j), by binary search in the round-0 sorted keys (the
+// name is the head rank of j's run of equal keys).
+
+__global__ __launch_bounds__(256) void isa_scatter_sorted_kernel(const u32* __restrict__ valsA,
+                                                                 const u32* __restrict__ valsB,
+                                                                 const SortPlan* __restrict__ plan,
+                                                                 u64 n, u32* __restrict__ isa) {
+  const u32 fb = plan->final_buf;
+  const u32* vals = fb ? valsB : valsA;
+  const u32* ranks = fb ? valsA : valsB;
+  u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const u32 v = vals[p];
+  if (v < n) isa[v] = ranks[p];
+}
+
+void launch_isa_scatter_sorted(const u32* valsA, const u32* valsB, const SortPlan* plan, u64 n,
+                               u32* isa, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(isa_scatter_sorted_kernel, dim3(u32(ceil_div(n, 256))), dim3(256), 0, s,
+                     valsA, valsB, plan, n, isa);
+}
+
+__global__ __launch_bounds__(256) void isa_scatter_list_kernel(const u32* __restrict__ idx,
+                                                               const u32* __restrict__ rank,
+                                                               u64 count, u64 n,
+                                                               u32* __restrict__ isa) {
+  u64 q = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= count) return;
+  const u32 v = idx[q];
+  if (v < n) isa[v] = rank[q];
+}
+
+void launch_isa_scatter_list(const u32* idx, const u32* rank, u64 count, u64 n, u32* isa,
+                             hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(isa_scatter_list_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
+                     idx, rank, count, n, isa);
+}
+
+namespace {
+
+// Round-0 name of suffix j: its packed key and a lower-bound search in the
+// round-0 sorted keys.
+__device__ inline u32 round0_rank(u64 j, const u8* __restrict__ text, u64 n,
+                                  const u16* __restrict__ code, u32 w, u32 c,
+                                  const u64* __restrict__ keys0) {
+  u64 k = 0;
+  for (u32 q = 0; q < c; ++q) {
+    const u64 p = j + q;
+    k = (k << w) | u64(p < n ? code[text[p]] : u16(0));
+  }
+  u64 lo = 0, hi = n;
+  while (lo < hi) {
+    const u64 mid = (lo + hi) >> 1;
+    if (keys0[mid] < k)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return u32(lo + 1);
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
+    const u32* __restrict__ act_idx, const u32* __restrict__ act_rank, u64 count, u64 n, u64 h,
+    int b, const u32* __restrict__ isa, const u8* __restrict__ text, const u16* __restrict__ code,
+    const u64* __restrict__ counters, const u64* __restrict__ keys0, u64* __restrict__ keys,
+    u32* __restrict__ vals) {
+  __shared__ u16 s_code[256];
+  s_code[threadIdx.x] = code[threadIdx.x];
+  __syncthreads();
+  u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const u32 w = u32(counters[kCtrCodeBits]);
+  const u32 c = u32(counters[kCtrChars]);
+  const u32 i = act_idx[p];
+  const u32 r = act_rank[p];
+  const u64 j = u64(i) + h;
+  u32 r1 = 0;
+  if (j < n) {
+    r1 = isa[j];
+    if (r1 == 0) r1 = round0_rank(j, text, n, s_code, w, c, keys0);
+  }
+  keys[p] = (u64(r) << b) | u64(r1);
+  vals[p] = i;
+}
+
+void launch_pack_pairs_lazy(const u32* act_idx, const u32* act_rank, u64 count, u64 n, u64 h,
+                            int b, const u32* isa, const u8* text, const u16* code,
+                            const u64* counters, const u64* keys0, u64* keys, u32* vals,
+                            hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(pack_pairs_lazy_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
+                     act_idx, act_rank, count, n, h, b, isa, text, code, counters, keys0, keys,
+                     vals);
+}
+
+__global__ __launch_bounds__(256) void isa_complete_kernel(u32* __restrict__ isa, u64 n,
+                                                           const u8* __restrict__ text,
+                                                           const u16* __restrict__ code,
+                                                           const u64* __restrict__ counters,
+                                                           const u64* __restrict__ keys0) {
+  __shared__ u16 s_code[256];
+  s_code[threadIdx.x] = code[threadIdx.x];
+  __syncthreads();
+  u64 j = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  if (isa[j] != 0) return;
+  const u32 w = u32(counters[kCtrCodeBits]);
+  const u32 c = u32(counters[kCtrChars]);
+  isa[j] = round0_rank(j, text, n, s_code, w, c, keys0);
+}
+
+void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const u64* counters,
+                         const u64* keys0, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(isa_complete_kernel, dim3(u32(ceil_div(n, 256))), dim3(256), 0, s, isa, n,
+                     text, code, counters, keys0);
 }
 
 }  // namespace sa

@@ -141,12 +141,53 @@ def test_round_names_closed_form(builder, kind):
         assert np.array_equal(got, want), (kind, k, info)
 
 
+def two_copy_text(n_rand: int, block: int, seed: int) -> np.ndarray:
+    """Random Markov text followed by two copies of one block: about 2*block of
+    the suffixes survive round 0."""
+    rng = np.random.default_rng(seed)
+    base = W.markov3(n_rand, chain_seed=seed)
+    blk = W.SYMBOLS96[rng.integers(0, 96, block)]
+    return np.concatenate([base, blk, blk])
+
+
+@pytest.mark.parametrize("mode", ["eager", "lazy", "auto"])
+def test_isa_modes(builder, mode):
+    """Eager and lazy inverse-suffix-array formation after round 0 give the same
+    bit-exact SA, and lazily resolved names match the closed form."""
+    builder.set_isa_mode(mode)
+    try:
+        for text in (two_copy_text(30000, 2500, 1), two_copy_text(9000, 5000, 2),
+                     W.markov3(70001, chain_seed=4), W.dna(50000, seed=4),
+                     np.random.default_rng(0).integers(0, 2, 40000).astype(np.uint8)):
+            assert_same(builder, text)
+            info = builder.last_info()
+            survivors = info["active"][1] if info["rounds"] > 1 else 0
+            if mode == "eager":
+                assert not info["lazy_isa"]
+            elif mode == "lazy":
+                assert info["lazy_isa"] == (survivors * 3 <= text.size)
+        t = two_copy_text(30000, 2500, 3)
+        _, _, full = builder.build_rounds(dev(t), 0)
+        for k in range(1, full["rounds"] + 1):
+            _, isa, info = builder.build_rounds(dev(t), k)
+            want = oracle.prefix_ranks(t, info["prefix_len"])
+            assert np.array_equal(isa.cpu().numpy().view(np.uint32), want), (mode, k, info)
+    finally:
+        builder.set_isa_mode("auto")
+
+
 def test_dna1m(builder):
     """n = 2^20 ACGT text (seed 0): bit-exact against the oracle."""
     t = W.dna(1 << 20, seed=0)
     assert_same(builder, t)
     info = builder.last_info()
-    assert info["sigma"] == 4 and info["chars0"] == 21
+    assert info["sigma"] == 4 and info["chars0"] == 18  # 3-bit codes, 54 of 56 key bits
+    builder.set_tuning(round0_full=1)
+    try:
+        assert_same(builder, t)
+        assert builder.last_info()["chars0"] == 21  # 63 key bits
+    finally:
+        builder.set_tuning(round0_full=0)
 
 
 @pytest.mark.parametrize("bits", [1, 7, 8, 9, 20, 33, 42, 58, 64])
@@ -216,3 +257,35 @@ def test_full_size(builder, kind):
     status, where = oracle.check_sa(t, sa)
     assert status == 0, (kind, status, where, info)
     sampled_direct_check(t, sa)
+
+
+@pytest.mark.parametrize("items", [8, 12, 16, 20, 24])
+def test_sort_tile_variants(builder, items):
+    """Every radix-sort tile shape sorts stably and builds the same SA."""
+    default = builder.tuning()["sort_items"]
+    builder.set_tuning(sort_items=items)
+    try:
+        rng = np.random.default_rng(items)
+        count = 100003
+        keys = rng.integers(0, 2**62, count, dtype=np.uint64)
+        keys[::7] = keys[3]
+        vals = rng.integers(0, 2**31, count, dtype=np.uint32)
+        order = np.argsort(keys, kind="stable")
+        k_t, v_t = dev(keys.view(np.int64)), dev(vals.view(np.int32))
+        builder.radix_sort_pairs(k_t, v_t, 62)
+        torch.cuda.synchronize()
+        assert np.array_equal(k_t.cpu().numpy().view(np.uint64), keys[order])
+        assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals[order])
+        assert_same(builder, W.dna(200003, seed=items))
+        assert_same(builder, W.repetitive(copies=20, base_len=3001))
+    finally:
+        builder.set_tuning(sort_items=default)
+
+
+def test_tuning_rejects_bad_values(builder):
+    from paper_1610_03007_amd import SAError
+    with pytest.raises(SAError):
+        builder.set_tuning(sort_items=10)
+    with pytest.raises(SAError):
+        builder.set_tuning(lazy_ratio=1)
+    assert builder.tuning()["sort_items"] in (8, 12, 16, 20, 24)
