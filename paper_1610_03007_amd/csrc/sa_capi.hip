@@ -370,7 +370,9 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   const u32 f0 = final_buf_of(c, 0);
   const u64* keys0 = f0 ? c->keysB : c->keysA;
   u64* spare = f0 ? c->keysA : c->keysB;
-  const bool fits = active * 24 <= n * 8;
+  // Later-round buffers are carved at 256-byte boundaries (vector accesses).
+  const u64 a1 = (std::max<u64>(active, 1) + 63) / 64 * 64;
+  const bool fits = a1 * 24 <= n * 8;
   bool lazy = false;
   if (c->isa_mode == SA_ISA_LAZY)
     lazy = fits;
@@ -391,7 +393,6 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   // carved out of the spare keys so that the round-0 sorted keys stay intact.
   Bufs later = full;
   if (lazy) {
-    const u64 a1 = std::max<u64>(active, 1);
     later.kA = spare;
     later.kB = spare + a1;
     later.vA = reinterpret_cast<u32*>(spare + 2 * a1);

@@ -715,10 +715,10 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
 // (Alg. 6 `Unique`); its rank is final, so SA[newrank - 1] = its position and it
 // is discarded. All others survive, in sorted order.
 //
-// Layout: each wave owns kRerankItems * 64 consecutive elements, lane l of item
-// j holding element j * 64 + l, so every load and store is coalesced; the scans
-// run per item across the wave with a carry from the previous item, then
-// across the waves of the block, then across tiles by decoupled look-back.
+// Layout: thread t of the tile owns kRerankItems consecutive elements and
+// scans them sequentially; one wave-level scan per tile combines the threads,
+// then the waves of the block, then the tiles by decoupled look-back. Loads and
+// the rank store are 16-byte vector accesses.
 __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
@@ -729,6 +729,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   constexpr int NW = kRerankBlock / kWave;
   constexpr int I = kRerankItems;
   constexpr int T = kRerankTile;
+  static_assert(I % 4 == 0, "vector loads of four values");
   __shared__ u32 s_wh[NW], s_wg[NW], s_ws[NW];
   __shared__ u64 s_prefix[3];
   __shared__ u64 s_tile;
@@ -752,73 +753,95 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   __syncthreads();
   const u64 tile = s_tile;
   const u64 base = tile * T;
-  const u32 wofs = u32(wave) * (I * kWave);  // wave start within the tile
-  const u64 wbase = base + wofs;
+  const u32 lfirst = u32(tid) * I;  // first element of this thread inside the tile
+  const u64 first = base + lfirst;
+  const bool full = first + I <= count;
 
   u64 k[I];
   u32 v[I];
+  if (full) {
+    const uint4* kv = reinterpret_cast<const uint4*>(keys + first);
+    const uint4* vv = reinterpret_cast<const uint4*>(vals + first);
 #pragma unroll
-  for (int j = 0; j < I; ++j) {
-    const u64 p = wbase + u64(j * kWave + lane);
-    k[j] = (p < count) ? keys[p] : 0;
-    v[j] = (p < count) ? vals[p] : 0;
-  }
-  const u64 k_before = (wbase > 0 && wbase - 1 < count) ? keys[wbase - 1] : 0;
-  const u64 k_after = (wbase + I * kWave < count) ? keys[wbase + I * kWave] : 0;
-
-  // Flags and wave-level scans with a carry across items. Positions inside the
-  // tile are stored + 1 so that 0 means "none yet".
-  u32 hin[I], gin[I], sin[I];
-  u32 flags = 0;  // bit j: head, bit 8+j: group start, bit 16+j: unique
-  u32 ch = 0, cg = 0, cs = 0;
-#pragma unroll
-  for (int j = 0; j < I; ++j) {
-    const u32 lp = wofs + u32(j * kWave + lane);
-    const u64 p = base + lp;
-    // Neighbour keys; every lane takes part in each shuffle (a lane reading
-    // from an inactive lane would get no data).
-    u64 kp = __shfl_up(k[j], 1, kWave);
-    const u64 kp_edge = (j > 0) ? __shfl(k[j > 0 ? j - 1 : 0], kWave - 1, kWave) : k_before;
-    if (lane == 0) kp = kp_edge;
-    u64 kn = __shfl_down(k[j], 1, kWave);
-    const u64 kn_edge = (j + 1 < I) ? __shfl(k[j + 1 < I ? j + 1 : j], 0, kWave) : k_after;
-    if (lane == kWave - 1) kn = kn_edge;
-    const bool valid = p < count;
-    const bool head = valid && ((p == 0) || (k[j] != kp));
-    const bool grp = valid && ((p == 0) || (b > 0 && (k[j] >> b) != (kp >> b)));
-    const bool uniq = head && ((p + 1 == count) || (kn != k[j]));
-    if (head) flags |= 1u << j;
-    if (grp) flags |= 1u << (8 + j);
-    if (uniq) flags |= 1u << (16 + j);
-    const u32 hv = head ? lp + 1 : 0;
-    const u32 gv = grp ? lp + 1 : 0;
-    const u32 sv = (valid && !uniq) ? 1u : 0u;
-    u32 ih = hv, ig = gv, is = sv;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const u32 th = __shfl_up(ih, off, kWave);
-      const u32 tg = __shfl_up(ig, off, kWave);
-      const u32 ts = __shfl_up(is, off, kWave);
-      if (lane >= off) {
-        ih = th > ih ? th : ih;
-        ig = tg > ig ? tg : ig;
-        is += ts;
-      }
+    for (int q = 0; q < I / 2; ++q) {
+      const uint4 w = kv[q];
+      k[2 * q] = (u64(w.y) << 32) | w.x;
+      k[2 * q + 1] = (u64(w.w) << 32) | w.z;
     }
-    hin[j] = ih > ch ? ih : ch;
-    gin[j] = ig > cg ? ig : cg;
-    sin[j] = is + cs;
-    ch = __shfl(hin[j], kWave - 1, kWave);
-    cg = __shfl(gin[j], kWave - 1, kWave);
-    cs = __shfl(sin[j], kWave - 1, kWave);
+#pragma unroll
+    for (int q = 0; q < I / 4; ++q) {
+      const uint4 w = vv[q];
+      v[4 * q] = w.x;
+      v[4 * q + 1] = w.y;
+      v[4 * q + 2] = w.z;
+      v[4 * q + 3] = w.w;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < I; ++j) {
+      const u64 p = first + j;
+      k[j] = p < count ? keys[p] : 0;
+      v[j] = p < count ? vals[p] : 0;
+    }
   }
-  if (lane == 0) {
-    s_wh[wave] = ch;
-    s_wg[wave] = cg;
-    s_ws[wave] = cs;
+  // Neighbour keys across thread boundaries (all lanes shuffle; the wave edges
+  // come from memory).
+  u64 kprev = __shfl_up(k[I - 1], 1, kWave);
+  u64 knext = __shfl_down(k[0], 1, kWave);
+  if (lane == 0) kprev = (first > 0 && first - 1 < count) ? keys[first - 1] : 0;
+  if (lane == kWave - 1) knext = (first + I < count) ? keys[first + I] : 0;
+
+  // Thread-local flags and sequential scans. Positions inside the tile are
+  // stored + 1 so that 0 means "none yet".
+  u32 flags = 0;  // bit j: head, bit 16+j: unique (group starts recomputed below)
+  u32 gflags = 0;
+  u32 th = 0, tg = 0, ts = 0;
+#pragma unroll
+  for (int j = 0; j < I; ++j) {
+    const u64 p = first + j;
+    if (p >= count) break;
+    const u64 kp = j ? k[j - 1] : kprev;
+    const u64 kn = (j + 1 < I) ? k[j + 1] : knext;
+    const bool head = (p == 0) || (k[j] != kp);
+    const bool grp = (p == 0) || (b > 0 && (k[j] >> b) != (kp >> b));
+    const bool uniq = head && ((p + 1 == count) || (kn != k[j]));
+    if (head) {
+      flags |= 1u << j;
+      th = lfirst + j + 1;
+    }
+    if (grp) {
+      gflags |= 1u << j;
+      tg = lfirst + j + 1;
+    }
+    if (uniq)
+      flags |= 1u << (16 + j);
+    else
+      ++ts;
   }
+  // Wave scans of the thread aggregates (max, max, sum).
+  u32 ih = th, ig = tg, is = ts;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const u32 a = __shfl_up(ih, off, kWave);
+    const u32 g = __shfl_up(ig, off, kWave);
+    const u32 c = __shfl_up(is, off, kWave);
+    if (lane >= off) {
+      ih = a > ih ? a : ih;
+      ig = g > ig ? g : ig;
+      is += c;
+    }
+  }
+  if (lane == kWave - 1) {
+    s_wh[wave] = ih;
+    s_wg[wave] = ig;
+    s_ws[wave] = is;
+  }
+  u32 xh = __shfl_up(ih, 1, kWave);  // exclusive within the wave
+  u32 xg = __shfl_up(ig, 1, kWave);
+  if (lane == 0) xh = xg = 0;
+  u32 xs = is - ts;
   __syncthreads();
-  u32 eh = 0, eg = 0, es = 0, th = 0, tg = 0, ts = 0;
+  u32 eh = 0, eg = 0, es = 0, tth = 0, ttg = 0, tts = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     const u32 a = s_wh[w], g = s_wg[w], c = s_ws[w];
@@ -827,10 +850,13 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
       eg = g > eg ? g : eg;
       es += c;
     }
-    th = a > th ? a : th;
-    tg = g > tg ? g : tg;
-    ts += c;
+    tth = a > tth ? a : tth;
+    ttg = g > ttg ? g : ttg;
+    tts += c;
   }
+  xh = xh > eh ? xh : eh;
+  xg = xg > eg ? xg : eg;
+  xs += es;
 
   // Tile prefixes from earlier tiles: waves 0, 1, 2 look back for the head,
   // group and survivor scans. Head and group are max-scans of global positions
@@ -838,8 +864,8 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   // survivor scan is a sum.
   if (wave < 3) {
     u64* st = wave == 0 ? st_head : (wave == 1 ? st_grp : st_surv);
-    const u32 loc = wave == 0 ? th : (wave == 1 ? tg : 0);
-    const u64 agg = wave == 2 ? u64(ts) : (loc ? base + loc - 1 : 0);
+    const u32 loc = wave == 0 ? tth : (wave == 1 ? ttg : 0);
+    const u64 agg = wave == 2 ? u64(tts) : (loc ? base + loc - 1 : 0);
     u64 pre = 0;
     if (tile == 0) {
       if (lane == 0) store_status(st, status_pack(gen, kFlagPrefix, agg));
@@ -855,31 +881,50 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   __syncthreads();
   if (s_abort) return;
 
+  u64 ss = xh ? base + xh - 1 : s_prefix[0];
+  u64 gs = xg ? base + xg - 1 : s_prefix[1];
+  u64 out = s_prefix[2] + xs;
+  u32 nrs[I];
+  bool bad = false;
 #pragma unroll
   for (int j = 0; j < I; ++j) {
-    const u32 lp = wofs + u32(j * kWave + lane);
-    const u64 p = base + lp;
+    const u64 p = first + j;
+    nrs[j] = 0;
     if (p >= count) break;
-    const u32 h = hin[j] > eh ? hin[j] : eh;
-    const u32 g = gin[j] > eg ? gin[j] : eg;
-    const u64 ss = h ? base + h - 1 : s_prefix[0];
-    const u64 gs = g ? base + g - 1 : s_prefix[1];
+    if ((flags >> j) & 1u) ss = p;
+    if ((gflags >> j) & 1u) gs = p;
     const u64 r0 = b > 0 ? (k[j] >> b) : 1;
     const u64 nr = r0 + ss - gs;
     const bool uniq = (flags >> (16 + j)) & 1u;
-    const u64 out = s_prefix[2] + es + sin[j] - (uniq ? 0u : 1u);
     if (v[j] >= n || nr == 0 || nr > n || (!uniq && out >= count)) {
-      atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
-               (unsigned long long)kErrBounds);
+      bad = true;
       break;
     }
+    nrs[j] = u32(nr);
     if (scatter) isa[v[j]] = u32(nr);
-    if (write_ranks) ranks_out[p] = u32(nr);
     if (uniq) {
       sa_out[nr - 1] = v[j];
     } else {
       act_idx[out] = v[j];
       act_rank[out] = u32(nr);
+      ++out;
+    }
+  }
+  if (bad) {
+    atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+             (unsigned long long)kErrBounds);
+    return;
+  }
+  if (write_ranks) {
+    if (full) {
+      uint4* rv = reinterpret_cast<uint4*>(ranks_out + first);
+#pragma unroll
+      for (int q = 0; q < I / 4; ++q)
+        rv[q] = make_uint4(nrs[4 * q], nrs[4 * q + 1], nrs[4 * q + 2], nrs[4 * q + 3]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < I; ++j)
+        if (first + j < count) ranks_out[first + j] = nrs[j];
     }
   }
 }
