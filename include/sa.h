@@ -65,7 +65,22 @@ sa_status sa_ctx_destroy(sa_ctx* ctx);
 sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
                    uint32_t* d_sa, void* stream);
 
-/* Per-build diagnostics of the last sa_build / sa_build_rounds call. */
+/* Suffix arrays of many texts in one batched build: every doubling round runs
+ * one sort and one re-rank launch for all texts together (the text id sits in
+ * the high key bits), instead of one build per text.
+ *   d_texts:   device u8[offsets[num_texts]], the texts concatenated.
+ *   h_offsets: host u64[num_texts + 1], offsets[0] = 0, non-decreasing; text t is
+ *              d_texts[offsets[t], offsets[t+1]) (empty texts are allowed).
+ *   d_sas:     device u32[offsets[num_texts]]; text t's suffix array (local
+ *              positions, values < n_t) is written to d_sas[offsets[t] ..).
+ * Errors: SA_EINVAL for null pointers, num_texts = 0, offsets[0] != 0 or
+ * decreasing offsets; SA_ETOOBIG if a text has 2^32 or more bytes, or if
+ * bits(num_texts - 1) + 2 * bits(longest text) > 64 (the key layout).
+ * The total may exceed 2^32. Workspace: about 45 bytes per byte of all texts. */
+sa_status sa_build_batch(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets,
+                         uint32_t num_texts, uint32_t* d_sas, void* stream);
+
+/* Per-build diagnostics of the last sa_build / sa_build_batch / sa_build_rounds call. */
 #define SA_MAX_ROUNDS 64
 typedef struct {
   uint64_t n;

@@ -85,6 +85,28 @@ class SuffixArrayBuilder:
                   "sa_build")
         return sa
 
+    def build_batch(self, texts: torch.Tensor, offsets, out: torch.Tensor | None = None):
+        """Suffix arrays of many texts in one batched build.
+
+        ``texts``: uint8 CUDA tensor, the texts concatenated; ``offsets``: the
+        num_texts + 1 boundaries (any integer sequence or array, host side).
+        Returns an int32 tensor aligned with ``texts`` holding each text's
+        suffix array (local positions) at that text's slice."""
+        import numpy as np
+        t = self._text(texts)
+        off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        if off.ndim != 1 or off.size < 2:
+            raise ValueError("offsets must hold num_texts + 1 boundaries")
+        if int(off[-1]) != t.numel():
+            raise ValueError("offsets[-1] must equal the total text length")
+        sa = self._out(out, t.numel(), "out")
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_build_batch(self._ctx, ctypes.c_void_p(t.data_ptr()),
+                                           off.ctypes.data_as(ctypes.c_void_p), off.size - 1,
+                                           ctypes.c_void_p(sa.data_ptr()),
+                                           _stream_handle(self.device)), "sa_build_batch")
+        return sa
+
     def build_rounds(self, text: torch.Tensor, max_rounds: int):
         """Run at most ``max_rounds`` doubling rounds. Returns (sa, isa, info):
         the partially finalised SA, the names after the last round run, and the

@@ -14,8 +14,9 @@ void launch_set_zero_u32(u32* p, hipStream_t s);
 // 1 + (number of present bytes below b) for every present byte b, and the
 // counters hold sigma, the code width w = bits(sigma) and c <= floor(64 / w).
 void launch_byte_presence(const u8* text, u64 n, u32* present, hipStream_t s);
-// With trim != 0, c is lowered so that c * w fills whole 8-bit radix digits.
-void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int trim,
+// The key holds idbits + c * w bits (idbits = text-id bits of a batch, else 0).
+// With trim != 0, c is lowered so that the key fills whole 8-bit radix digits.
+void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int trim, int idbits,
                            hipStream_t s);
 
 // Round-0 keys: key[i] = c codes of T[i, i+c) (0 past the end), w bits each,
@@ -55,16 +56,32 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
                           u32 grid, hipStream_t s);
 
 // Re-rank the sorted active set, scatter the ISA, finalize unique suffixes into
-// the SA and compact the survivors. b = bits of the second rank (0 in round 0,
-// where every element starts with rank 1).
+// the SA and compact the survivors.
 // mode: kRerankScatterIsa writes ISA[text position] = new rank for every element;
 // kRerankWriteRanks writes the new rank of sorted position p into the value
 // buffer the sort did not end in.
 constexpr int kRerankScatterIsa = 1;
 constexpr int kRerankWriteRanks = 2;
+// Key layout of the sorted set:
+//   group     = key >> gshift (64: one group, round 0 of a single text)
+//   old rank  = (key >> rshift) & rmask (rmask 0: every element has rank 1)
+//   text id   = key >> idshift when toff (batch text offsets, T + 1) is set;
+//               ranks and positions are then local to that text, SA and ISA
+//               are addressed at toff[t] + local, survivors go to act_ti as
+//               (t << 32) | local instead of act_idx.
+struct RerankArgs {
+  u64 count;
+  u64 n;
+  int gshift;
+  int rshift;
+  u64 rmask;
+  int idshift;
+  int mode;
+  const u64* toff;
+};
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
-                           const u32* valsB, const SortPlan* plan, u64 count, u64 n, int b,
-                           int mode, u32* isa, u32* sa_out, u32* act_idx, u32* act_rank,
+                           const u32* valsB, const SortPlan* plan, const RerankArgs& args,
+                           u32* isa, u32* sa_out, u32* act_idx, u64* act_ti, u32* act_rank,
                            u64* st_head, u64* st_grp, u64* st_surv, u64* counters, u32 gen,
                            hipStream_t s);
 
@@ -85,5 +102,15 @@ void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const
 void launch_fill_u32(u32* p, u64 count, u32 value, hipStream_t s);
 
 __host__ __device__ inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
+
+// Batch (toff = device u64[num_texts + 1] text offsets, total = toff[num_texts]).
+// Round 0: keys (t << idshift | packed codes of text t), values = local position.
+void launch_pack_text_batch(const u8* text, u64 total, const u64* toff, u64 num_texts,
+                            int idshift, const u16* code, const u64* counters, u64* keys,
+                            u32* vals, hipStream_t s);
+// Later rounds: key = t << idshift | rank << b | ISA[toff[t] + i + h] (0 past text end).
+void launch_pack_pairs_batch(const u64* act_ti, const u32* act_rank, u64 count, const u64* toff,
+                             u64 h, int b, int idshift, const u32* isa, u64* keys, u32* vals,
+                             hipStream_t s);
 
 }  // namespace sa

@@ -42,6 +42,10 @@ struct sa_ctx {
   u32* isa = nullptr;
   u32* act_idx = nullptr;
   u32* act_rank = nullptr;
+  u64* act_ti = nullptr;  // batch survivors: (text << 32) | local position
+  u64 act_ti_cap = 0;
+  u64* toff = nullptr;    // batch text offsets on the device
+  u64 toff_cap = 0;
   u64* status = nullptr;  // sort look-back: [tiles][kRadix]
   u64* st3 = nullptr;     // re-rank look-back: 3 x [tiles]
   u64 rr_tiles_cap = 0;
@@ -100,6 +104,9 @@ void free_workspace(sa_ctx* c) {
   (void)hipFree(c->act_rank);
   (void)hipFree(c->status);
   (void)hipFree(c->st3);
+  (void)hipFree(c->act_ti);
+  c->act_ti = nullptr;
+  c->act_ti_cap = 0;
   c->keysA = c->keysB = nullptr;
   c->valsA = c->valsB = c->isa = c->act_idx = c->act_rank = nullptr;
   c->status = c->st3 = nullptr;
@@ -287,16 +294,31 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
   }
 }
 
-void run_rerank(sa_ctx* c, const Bufs& bf, u64 count, u64 n, int b, int mode, u32* d_sa,
-                hipStream_t s) {
+void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s) {
   u32 gen = next_gen(c, s);
-  double bytes = double(count) * 16.0 + ((mode & kRerankWriteRanks) ? 4.0 * double(count) : 0.0) -
-                 ((mode & kRerankScatterIsa) ? 0.0 : 4.0 * double(count));
+  const double count = double(args.count);
+  double bytes = count * 16.0 + ((args.mode & kRerankWriteRanks) ? 4.0 * count : 0.0) -
+                 ((args.mode & kRerankScatterIsa) ? 0.0 : 4.0 * count);
   Tracer t(c, s, SA_KERNEL_RERANK, bytes);
   const u64 rt = c->rr_tiles_cap;
-  launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, count, n, b, mode, c->isa, d_sa,
-                        c->act_idx, c->act_rank, c->st3, c->st3 + rt, c->st3 + 2 * rt,
-                        c->counters, gen, s);
+  launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->isa, d_sa,
+                        args.toff ? nullptr : c->act_idx, args.toff ? c->act_ti : nullptr,
+                        c->act_rank, c->st3, c->st3 + rt, c->st3 + 2 * rt, c->counters, gen, s);
+}
+
+// Re-rank arguments of a single text: round 0 (one group, every rank 1) or a
+// later round with (rank << b | next rank) keys.
+RerankArgs single_args(u64 count, u64 n, int b, int mode) {
+  RerankArgs a{};
+  a.count = count;
+  a.n = n;
+  a.gshift = b > 0 ? b : 64;
+  a.rshift = b;
+  a.rmask = b > 0 ? ~u64(0) : 0;
+  a.idshift = 0;
+  a.mode = mode;
+  a.toff = nullptr;
+  return a;
 }
 
 sa_status readback(sa_ctx* c, hipStream_t s) {
@@ -342,14 +364,14 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   {
     Tracer t(c, s, SA_KERNEL_OTHER, double(n));
     launch_byte_presence(text, n, c->present, s);
-    launch_alphabet_codes(c->present, c->code, c->counters, c->round0_trim, s);
+    launch_alphabet_codes(c->present, c->code, c->counters, c->round0_trim, 0, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_PACK_TEXT, double(n) * 9.0);
     launch_pack_text(text, n, c->code, c->counters, c->keysA, s);
   }
   run_sort(c, full, n, kMaxPasses, 0, 0, s);
-  run_rerank(c, full, n, n, 0, kRerankWriteRanks, d_sa, s);
+  run_rerank(c, full, single_args(n, n, 0, kRerankWriteRanks), d_sa, s);
   st = readback(c, s);
   if (st != SA_OK) return st;
 
@@ -416,7 +438,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
                           s);
     }
     run_sort(c, later, active, npass, 1, slot, s);
-    run_rerank(c, later, active, n, b, kRerankScatterIsa, d_sa, s);
+    run_rerank(c, later, single_args(active, n, b, kRerankScatterIsa), d_sa, s);
     st = readback(c, s);
     if (st != SA_OK) return st;
     info.active[slot] = active;
@@ -433,6 +455,123 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
       return SA_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return SA_EDEVICE;
     if (hipGetLastError() != hipSuccess) return SA_EDEVICE;
+  }
+  return SA_OK;
+}
+
+// Batch: T texts concatenated at device `text`, host offsets h_off[0..T]. One
+// sort and one re-rank per round for all texts: the text id sits in the high
+// key bits, ranks are local (Section 2.1 names per text), SA entries are local
+// positions written at h_off[t] + rank - 1.
+sa_status build_batch(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d_sa,
+                      hipStream_t s) {
+  std::memset(&c->info, 0, sizeof(c->info));
+  if (!h_off || T == 0) return SA_EINVAL;
+  if (h_off[0] != 0) return SA_EINVAL;
+  u64 max_n = 0;
+  for (u32 t = 0; t < T; ++t) {
+    if (h_off[t + 1] < h_off[t]) return SA_EINVAL;
+    max_n = std::max<u64>(max_n, h_off[t + 1] - h_off[t]);
+  }
+  const u64 N = h_off[T];
+  c->info.n = N;
+  if (max_n >= (u64(1) << 32)) return SA_ETOOBIG;
+  if (N == 0) return SA_OK;
+  if (!text || !d_sa) return SA_EINVAL;
+  if (T == 1) return build_rounds(c, text, N, 0, d_sa, nullptr, s);
+  const int idbits = bits_of(u64(T) - 1);
+  const int B = bits_of(max_n);
+  if (idbits + 2 * B > 64) return SA_ETOOBIG;
+  if (hipSetDevice(c->device) != hipSuccess) return SA_EDEVICE;
+  sa_status st = ensure_workspace(c, N);
+  if (st != SA_OK) return st;
+  if (c->act_ti_cap < c->cap) {
+    (void)hipFree(c->act_ti);
+    c->act_ti = nullptr;
+    c->act_ti_cap = 0;
+    if (!dev_alloc(&c->act_ti, c->cap)) return SA_ENOMEM;
+    c->act_ti_cap = c->cap;
+  }
+  if (c->toff_cap < u64(T) + 1) {
+    (void)hipFree(c->toff);
+    c->toff = nullptr;
+    c->toff_cap = 0;
+    if (!dev_alloc(&c->toff, u64(T) + 1)) return SA_ENOMEM;
+    c->toff_cap = u64(T) + 1;
+  }
+  if (hipMemcpyAsync(c->toff, h_off, (u64(T) + 1) * sizeof(u64), hipMemcpyHostToDevice, s) !=
+      hipSuccess)
+    return SA_EDEVICE;
+
+  const Bufs full = full_bufs(c);
+  const int idshift0 = 64 - idbits;
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, 0);
+    launch_fill_u64(c->counters, kCtrCount, 0, s);
+    launch_fill_u64(reinterpret_cast<u64*>(c->present), 256 / 2, 0, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_OTHER, double(N));
+    launch_byte_presence(text, N, c->present, s);
+    launch_alphabet_codes(c->present, c->code, c->counters, c->round0_trim, idbits, s);
+  }
+  {
+    Tracer t(c, s, SA_KERNEL_PACK_TEXT, double(N) * 13.0);
+    launch_pack_text_batch(text, N, c->toff, T, idshift0, c->code, c->counters, c->keysA,
+                           c->valsA, s);
+  }
+  run_sort(c, full, N, kMaxPasses, 1, 0, s);
+  RerankArgs a{};
+  a.count = N;
+  a.n = 0;
+  a.gshift = idshift0;  // round 0: one group per text, every rank 1
+  a.rshift = 0;
+  a.rmask = 0;
+  a.idshift = idshift0;
+  a.mode = kRerankScatterIsa;
+  a.toff = c->toff;
+  run_rerank(c, full, a, d_sa, s);
+  st = readback(c, s);
+  if (st != SA_OK) return st;
+
+  sa_build_info& info = c->info;
+  info.sigma = u32(c->h_counters[kCtrSigma]);
+  info.code_bits = u32(c->h_counters[kCtrCodeBits]);
+  info.chars0 = u32(c->h_counters[kCtrChars]);
+  info.rounds = 1;
+  info.active[0] = N;
+  info.key_bits[0] = u32(idbits) + info.code_bits * info.chars0;
+  info.passes_run[0] = passes_run(c, 0, kMaxPasses);
+  u64 h = info.chars0;
+  info.prefix_len = h;
+  u64 active = c->h_counters[kCtrActive];
+
+  const int key_bits = idbits + 2 * B;
+  const int npass = int(ceil_div(u64(key_bits), kRadixBits));
+  a.gshift = B;  // group = (text, rank)
+  a.rshift = B;
+  a.rmask = (u64(1) << B) - 1;
+  a.idshift = 2 * B;
+  while (active > 0) {
+    if (info.rounds >= SA_MAX_ROUNDS) return SA_EDEVICE;
+    const int slot = int(info.rounds);
+    {
+      Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
+      launch_pack_pairs_batch(c->act_ti, c->act_rank, active, c->toff, h, B, 2 * B, c->isa,
+                              c->keysA, c->valsA, s);
+    }
+    run_sort(c, full, active, npass, 1, slot, s);
+    a.count = active;
+    run_rerank(c, full, a, d_sa, s);
+    st = readback(c, s);
+    if (st != SA_OK) return st;
+    info.active[slot] = active;
+    info.key_bits[slot] = u32(key_bits);
+    info.passes_run[slot] = passes_run(c, slot, npass);
+    info.rounds += 1;
+    h *= 2;
+    info.prefix_len = h;
+    active = c->h_counters[kCtrActive];
   }
   return SA_OK;
 }
@@ -505,6 +644,7 @@ sa_status sa_ctx_destroy(sa_ctx* ctx) {
   (void)hipFree(ctx->small);
   if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
   if (ctx->h_plans) (void)hipHostFree(ctx->h_plans);
+  (void)hipFree(ctx->toff);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx;
   return SA_OK;
@@ -515,6 +655,20 @@ sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigm
   if (!ctx) return SA_EINVAL;
   if (sigma == 0 || sigma > 256) return SA_EINVAL;
   return build_impl(ctx, d_text, n, 0, d_sa, nullptr, static_cast<hipStream_t>(stream));
+}
+
+sa_status sa_build_batch(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets,
+                         uint32_t num_texts, uint32_t* d_sas, void* stream) {
+  if (!ctx) return SA_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  sa_status st = build_batch(ctx, d_texts, h_offsets, num_texts, d_sas, s);
+  if (st == SA_OK && ctx->trace) {
+    collect_trace(ctx);
+  } else {
+    ctx->recs.clear();
+    ctx->event_used = 0;
+  }
+  return st;
 }
 
 sa_status sa_build_rounds(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t max_rounds,

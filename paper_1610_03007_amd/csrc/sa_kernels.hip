@@ -216,7 +216,7 @@ void launch_byte_presence(const u8* text, u64 n, u32* present, hipStream_t s) {
 __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restrict__ present,
                                                              u16* __restrict__ code,
                                                              u64* __restrict__ counters,
-                                                             int trim) {
+                                                             int trim, int idbits) {
   __shared__ u32 wsum[4];
   const int t = threadIdx.x;
   u32 p = present[t] ? 1u : 0u;
@@ -237,10 +237,17 @@ __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restri
     // As many characters as fit in 64 bits; with `trim`, drop the characters
     // that would only half-fill a last 8-bit radix digit, saving one sort pass
     // over every suffix for a slightly shorter first prefix.
-    u32 c = 64 / w;
-    if (trim && (c * w) % kRadixBits != 0) {
-      const u32 ct = ((c * w) / kRadixBits) * kRadixBits / w;
-      if (ct >= 1) c = ct;
+    // `idbits` high key bits are taken by a text id (batches).
+    const u32 avail = 64u - u32(idbits);
+    u32 c = avail / w;
+    if (c < 1) c = 1;
+    const u32 used = u32(idbits) + c * w;
+    if (trim && used % kRadixBits != 0 && used > kRadixBits) {
+      const u32 full = (used / kRadixBits) * kRadixBits;
+      if (full > u32(idbits)) {
+        const u32 ct = (full - u32(idbits)) / w;
+        if (ct >= 1) c = ct;
+      }
     }
     counters[kCtrSigma] = sigma;
     counters[kCtrCodeBits] = w;
@@ -248,10 +255,10 @@ __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restri
   }
 }
 
-void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int trim,
+void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int trim, int idbits,
                            hipStream_t s) {
   hipLaunchKernelGGL(alphabet_codes_kernel, dim3(1), dim3(256), 0, s, present, code, counters,
-                     trim);
+                     trim, idbits);
 }
 
 // ---------------------------------------------------------------------------
@@ -722,13 +729,15 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
 __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
-    const SortPlan* __restrict__ plan, u64 count, u64 n, int b, int mode,
-    u32* __restrict__ isa, u32* __restrict__ sa_out, u32* __restrict__ act_idx,
+    const SortPlan* __restrict__ plan, const RerankArgs a, u32* __restrict__ isa,
+    u32* __restrict__ sa_out, u32* __restrict__ act_idx, u64* __restrict__ act_ti,
     u32* __restrict__ act_rank, u64* __restrict__ st_head, u64* __restrict__ st_grp,
     u64* __restrict__ st_surv, u64* __restrict__ counters, u32 gen) {
   constexpr int NW = kRerankBlock / kWave;
   constexpr int I = kRerankItems;
   constexpr int T = kRerankTile;
+  const u64 count = a.count;
+  const int mode = a.mode;
   static_assert(I % 4 == 0, "vector loads of four values");
   __shared__ u32 s_wh[NW], s_wg[NW], s_ws[NW];
   __shared__ u64 s_prefix[3];
@@ -803,7 +812,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64 kp = j ? k[j - 1] : kprev;
     const u64 kn = (j + 1 < I) ? k[j + 1] : knext;
     const bool head = (p == 0) || (k[j] != kp);
-    const bool grp = (p == 0) || (b > 0 && (k[j] >> b) != (kp >> b));
+    const bool grp = (p == 0) || (a.gshift < 64 && (k[j] >> a.gshift) != (kp >> a.gshift));
     const bool uniq = head && ((p + 1 == count) || (kn != k[j]));
     if (head) {
       flags |= 1u << j;
@@ -893,19 +902,30 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     if (p >= count) break;
     if ((flags >> j) & 1u) ss = p;
     if ((gflags >> j) & 1u) gs = p;
-    const u64 r0 = b > 0 ? (k[j] >> b) : 1;
+    const u64 r0 = a.rmask ? ((k[j] >> a.rshift) & a.rmask) : 1;
     const u64 nr = r0 + ss - gs;
     const bool uniq = (flags >> (16 + j)) & 1u;
-    if (v[j] >= n || nr == 0 || nr > n || (!uniq && out >= count)) {
+    // Text of the element: the whole text, or (batch) the one named by the
+    // key's high bits; ranks and positions are local to it.
+    u64 gb = 0, nt = a.n, t = 0;
+    if (a.toff) {
+      t = k[j] >> a.idshift;
+      gb = a.toff[t];
+      nt = a.toff[t + 1] - gb;
+    }
+    if (v[j] >= nt || nr == 0 || nr > nt || (!uniq && out >= count)) {
       bad = true;
       break;
     }
     nrs[j] = u32(nr);
-    if (scatter) isa[v[j]] = u32(nr);
+    if (scatter) isa[gb + v[j]] = u32(nr);
     if (uniq) {
-      sa_out[nr - 1] = v[j];
+      sa_out[gb + nr - 1] = v[j];
     } else {
-      act_idx[out] = v[j];
+      if (act_ti)
+        act_ti[out] = (t << 32) | v[j];
+      else
+        act_idx[out] = v[j];
       act_rank[out] = u32(nr);
       ++out;
     }
@@ -930,14 +950,14 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
 }
 
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
-                           const u32* valsB, const SortPlan* plan, u64 count, u64 n, int b,
-                           int mode, u32* isa, u32* sa_out, u32* act_idx, u32* act_rank,
+                           const u32* valsB, const SortPlan* plan, const RerankArgs& args,
+                           u32* isa, u32* sa_out, u32* act_idx, u64* act_ti, u32* act_rank,
                            u64* st_head, u64* st_grp, u64* st_surv, u64* counters, u32 gen,
                            hipStream_t s) {
-  if (count == 0) return;
-  const u64 tiles = ceil_div(count, kRerankTile);
+  if (args.count == 0) return;
+  const u64 tiles = ceil_div(args.count, kRerankTile);
   hipLaunchKernelGGL(rerank_compact_kernel, dim3(u32(tiles)), dim3(kRerankBlock), 0, s, keysA,
-                     keysB, valsA, valsB, plan, count, n, b, mode, isa, sa_out, act_idx, act_rank,
+                     keysB, valsA, valsB, plan, args, isa, sa_out, act_idx, act_ti, act_rank,
                      st_head,
                      st_grp, st_surv, counters, gen);
 }
@@ -1069,6 +1089,106 @@ void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const
   if (n == 0) return;
   hipLaunchKernelGGL(isa_complete_kernel, dim3(u32(ceil_div(n, 256))), dim3(256), 0, s, isa, n,
                      text, code, counters, keys0);
+}
+
+// ---------------------------------------------------------------------------
+// Batched rounds: many texts concatenated (CSR offsets toff[0..T]); keys carry
+// the text id in their high bits so that one sort and one re-rank per round
+// serve every text; ranks, values and SA entries are local to each text.
+
+namespace {
+
+// Text containing global position g: the last t with toff[t] <= g.
+__device__ inline u64 text_of(const u64* __restrict__ toff, u64 num_texts, u64 g) {
+  u64 lo = 0, hi = num_texts;  // toff[lo] <= g < toff[hi]
+  while (hi - lo > 1) {
+    const u64 mid = (lo + hi) >> 1;
+    if (toff[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace
+
+// Round-0 keys of a batch: key[g] = (t << idshift) | c character codes of text t
+// from local position i (0 past the end of text t); val[g] = i.
+__global__ __launch_bounds__(kPackBlock) void pack_text_batch_kernel(
+    const u8* __restrict__ text, u64 total, const u64* __restrict__ toff, u64 num_texts,
+    int idshift, const u16* __restrict__ code, const u64* __restrict__ counters,
+    u64* __restrict__ keys, u32* __restrict__ vals) {
+  __shared__ u16 s_code[256];
+  __shared__ u16 s_sym[kPackTile + kPackHalo];
+  const int t = threadIdx.x;
+  const u64 base = u64(blockIdx.x) * kPackTile;
+  const u32 w = u32(counters[kCtrCodeBits]);
+  const u32 c = u32(counters[kCtrChars]);
+  s_code[t] = code[t];
+  __syncthreads();
+  for (int i = t; i < kPackTile + kPackHalo; i += kPackBlock) {
+    const u64 p = base + u64(i);
+    s_sym[i] = (p < total) ? s_code[text[p]] : u16(0);
+  }
+  __syncthreads();
+  const int first = t * kPackItems;
+  const u64 g0 = base + u64(first);
+  if (g0 >= total) return;
+  u64 tx = text_of(toff, num_texts, g0);
+  u64 tstart = toff[tx], tend = toff[tx + 1];
+  for (int j = 0; j < kPackItems; ++j) {
+    const u64 g = g0 + u64(j);
+    if (g >= total) break;
+    while (g >= tend) {  // crossed into the next non-empty text
+      ++tx;
+      tstart = tend;
+      tend = toff[tx + 1];
+    }
+    u64 key = 0;
+    for (u32 q = 0; q < c; ++q) {
+      const u64 p = g + q;
+      key = (key << w) | u64(p < tend ? s_sym[first + j + int(q)] : u16(0));
+    }
+    keys[g] = (tx << idshift) | key;
+    vals[g] = u32(g - tstart);
+  }
+}
+
+void launch_pack_text_batch(const u8* text, u64 total, const u64* toff, u64 num_texts,
+                            int idshift, const u16* code, const u64* counters, u64* keys,
+                            u32* vals, hipStream_t s) {
+  if (total == 0) return;
+  hipLaunchKernelGGL(pack_text_batch_kernel, dim3(u32(ceil_div(total, kPackTile))),
+                     dim3(kPackBlock), 0, s, text, total, toff, num_texts, idshift, code,
+                     counters, keys, vals);
+}
+
+// Later-round keys of a batch: for a surviving (text t, local i, rank r):
+// key = (t << idshift) | (r << b) | (i + h < n_t ? ISA[toff[t] + i + h] : 0).
+__global__ __launch_bounds__(256) void pack_pairs_batch_kernel(
+    const u64* __restrict__ act_ti, const u32* __restrict__ act_rank, u64 count,
+    const u64* __restrict__ toff, u64 h, int b, int idshift, const u32* __restrict__ isa,
+    u64* __restrict__ keys, u32* __restrict__ vals) {
+  const u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const u64 ti = act_ti[p];
+  const u64 t = ti >> 32;
+  const u32 i = u32(ti);
+  const u64 gb = toff[t];
+  const u64 nt = toff[t + 1] - gb;
+  const u64 j = u64(i) + h;
+  const u32 r1 = (j < nt) ? isa[gb + j] : 0u;
+  keys[p] = (t << idshift) | (u64(act_rank[p]) << b) | u64(r1);
+  vals[p] = i;
+}
+
+void launch_pack_pairs_batch(const u64* act_ti, const u32* act_rank, u64 count, const u64* toff,
+                             u64 h, int b, int idshift, const u32* isa, u64* keys, u32* vals,
+                             hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(pack_pairs_batch_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
+                     act_ti, act_rank, count, toff, h, b, idshift, isa, keys, vals);
 }
 
 }  // namespace sa
