@@ -28,12 +28,22 @@ WORKLOADS = {
     "markov_256m": "order-3 Markov text, 96 printable bytes, Dirichlet(0.1) rows, n=2^28",
     "dna_1m": "uniform ACGT text, seed 0, n=2^20",
     "repetitive_1g": "256 KiB base x 4096 copies, 1e-4 substitutions, n=2^30",
+    "batch_4096": "4096 texts, lengths log-uniform in [4 KiB, 8 MiB], half ACGT, half "
+                  "order-3 Markov (96 bytes); one batched build",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_03007_amd", "csrc", "sa_kernels.hip")
 
 
 def make_text(name: str):
+    """Returns (text, offsets or None)."""
+    import workloads as W
+    if name == "batch_4096":
+        return W.batch()
+    return make_single(name), None
+
+
+def make_single(name: str):
     import workloads as W
     if name == "markov_256m":
         return W.markov3(1 << 28, chain_seed=2)
@@ -62,19 +72,34 @@ def measured_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(text, sample: int):
+def cpu_baseline(text, sample: int, offsets=None):
     import oracle
-    s = text[:sample].copy()
-    t0 = time.perf_counter()
-    oracle.sa(s, parallel=True)
-    dt = time.perf_counter() - t0
+    if offsets is None:
+        s = text[:sample].copy()
+        t0 = time.perf_counter()
+        oracle.sa(s, parallel=True)
+        dt = time.perf_counter() - t0
+        total = s.size
+        what = f"first {s.size} bytes of the same text"
+    else:
+        # Whole texts of the batch, in order, until the sample size is reached.
+        t0 = time.perf_counter()
+        total = ntexts = 0
+        for t in range(offsets.size - 1):
+            a, b = int(offsets[t]), int(offsets[t + 1])
+            oracle.sa(text[a:b], parallel=True)
+            total += b - a
+            ntexts += 1
+            if total >= sample:
+                break
+        dt = time.perf_counter() - t0
+        what = f"the first {ntexts} texts of the batch ({total} bytes), one oracle call per text"
     return {
-        "value": round(s.size / dt / 1e6, 3),
+        "value": round(total / dt / 1e6, 3),
         "unit": "Msuffixes/s",
         "cores": oracle.num_threads(parallel=True),
         "kind": "oracle",
-        "sample": f"first {s.size} bytes of the same text, plain prefix doubling "
-                  f"(GNU parallel std::sort), {dt:.2f} s",
+        "sample": f"{what}, plain prefix doubling (GNU parallel std::sort), {dt:.2f} s",
     }
 
 
@@ -85,7 +110,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="markov_256m", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-sample", type=int, default=1 << 28,
-                    help="bytes of the text the CPU oracle is timed on (0 = skip)")
+                    help="bytes of the text the CPU oracle is timed on (0 = skip; batches "
+                         "are sampled by whole texts)")
     ap.add_argument("--sort-items", type=int, default=0,
                     help="radix-sort items per thread (0 = library default)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
@@ -104,7 +130,7 @@ def main() -> int:
     from paper_1610_03007_amd import SuffixArrayBuilder
 
     t_gen = time.perf_counter()
-    text = make_text(args.workload)
+    text, offsets = make_text(args.workload)
     n = int(text.size)
     print(f"[bench] workload {args.workload} n={n} generated in "
           f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
@@ -116,8 +142,14 @@ def main() -> int:
     if args.sort_items:
         b.set_tuning(sort_items=args.sort_items)
 
+    def step():
+        if offsets is None:
+            b.build(d_text, out=d_sa)
+        else:
+            b.build_batch(d_text, offsets, out=d_sa)
+
     for _ in range(args.warmup):
-        b.build(d_text, out=d_sa)
+        step()
     torch.cuda.synchronize()
     print(f"[bench] warmup done: {b.last_info()}", file=sys.stderr, flush=True)
 
@@ -130,7 +162,7 @@ def main() -> int:
     t0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        b.build(d_text, out=d_sa)
+        step()
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -186,8 +218,29 @@ def main() -> int:
         "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in stats.items()},
         "wall_s": round(wall, 3),
     }
+    if offsets is not None:
+        # Per-text baseline on the same GPU: one sa_build per text, in order.
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for t in range(offsets.size - 1):
+            a, z = int(offsets[t]), int(offsets[t + 1])
+            if z > a:
+                b.build(d_text[a:z], out=d_sa[a:z])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per_text_ms = e0.elapsed_time(e1)
+        per_text = n / (per_text_ms / 1e3) / 1e6
+        result["batch"] = {
+            "texts": int(offsets.size - 1),
+            "batched_msuffixes_s": round(value, 2),
+            "per_text_msuffixes_s": round(per_text, 2),
+            "per_text_ms": round(per_text_ms, 2),
+            "batched_vs_per_text": round(value / per_text, 3),
+        }
     if args.cpu_sample > 0:
-        result["cpu_baseline"] = cpu_baseline(text, min(args.cpu_sample, n))
+        result["cpu_baseline"] = cpu_baseline(text, min(args.cpu_sample, n), offsets)
     else:
         result["cpu_baseline"] = None
 

@@ -80,6 +80,38 @@ sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigm
 sa_status sa_build_batch(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets,
                          uint32_t num_texts, uint32_t* d_sas, void* stream);
 
+/* Continuous-batching server. A worker thread owns the device work: requests
+ * are admitted in arrival order while a slot is free and their text fits in
+ * the server's device arena (their HBM footprint), and every loop runs one
+ * merged doubling round for all admitted requests: new ones start round 0 while
+ * the others do their own next round, in the same sort and re-rank launches.
+ * A request's rank arrays stay on the device between rounds. Results equal
+ * sa_build of the same text alone. */
+typedef struct sa_server sa_server;
+/* capacity_bytes: device memory the server may use (0 = half of the free
+ * memory); max_text: longest accepted text (0 = 2^26). At most
+ * 2^(64 - 2 * bits(max_text)) requests (capped at 1024) are in flight. */
+sa_status sa_server_create(sa_server** out, int device, uint64_t capacity_bytes,
+                           uint64_t max_text);
+/* Stops the worker (requests still queued or running are dropped). */
+sa_status sa_server_destroy(sa_server* srv);
+/* Queues a copy of host text h_text[0, n); *ticket identifies the request.
+ * SA_ETOOBIG if n exceeds max_text or the arena. */
+sa_status sa_server_submit(sa_server* srv, const uint8_t* h_text, uint64_t n, uint64_t* ticket);
+/* *done = 1 once the request finished: its suffix array is copied to host
+ * h_sa_out[0, n) and the request is released; latency_ms (may be NULL)
+ * receives the time from submit to the suffix array being complete on the
+ * device. *done = 0 while it is queued or running. A failed request returns
+ * its error once and is released. */
+sa_status sa_server_poll(sa_server* srv, uint64_t ticket, uint32_t* h_sa_out, int* done,
+                         double* latency_ms);
+typedef struct {
+  uint64_t completed, failed, suffixes, rounds;
+  double busy_ms;                    /* worker time spent in rounds */
+  uint64_t queued, running, slots, arena_positions;
+} sa_server_stats_t;
+sa_status sa_server_stats(sa_server* srv, sa_server_stats_t* out);
+
 /* Per-build diagnostics of the last sa_build / sa_build_batch / sa_build_rounds call. */
 #define SA_MAX_ROUNDS 64
 typedef struct {

@@ -20,7 +20,7 @@ import torch
 from . import _native
 from ._native import SAError, check
 
-__all__ = ["SuffixArrayBuilder", "SAError", "workspace_bytes"]
+__all__ = ["SuffixArrayBuilder", "SuffixArrayServer", "SAError", "workspace_bytes"]
 
 
 def _stream_handle(device: torch.device):
@@ -179,3 +179,61 @@ class SuffixArrayBuilder:
                   "sa_ctx_get_kernel_stats")
             out[name] = {"launches": int(st.launches), "ms": float(st.ms), "bytes": float(st.bytes)}
         return out
+
+
+class SuffixArrayServer:
+    """Continuous-batching suffix-array service on one GPU (sa_server_* ABI).
+
+    ``submit`` queues a host text and returns a ticket; the library's worker
+    thread admits requests as slots and device memory free up and runs merged
+    doubling rounds over all admitted requests. ``poll`` returns the suffix
+    array once it is complete, with the submit-to-ready latency."""
+
+    def __init__(self, device: int = 0, capacity_bytes: int = 0, max_text: int = 0):
+        self._lib = _native.lib()
+        self._srv = ctypes.c_void_p()
+        self.device = device
+        with torch.cuda.device(device):
+            check(self._lib.sa_server_create(ctypes.byref(self._srv), device, capacity_bytes,
+                                             max_text), "sa_server_create")
+        self._n = {}
+
+    def close(self) -> None:
+        if self._srv:
+            self._lib.sa_server_destroy(self._srv)
+            self._srv = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, text) -> int:
+        import numpy as np
+        a = np.ascontiguousarray(np.frombuffer(bytes(text), np.uint8)
+                                 if isinstance(text, (bytes, bytearray)) else text, dtype=np.uint8)
+        t = ctypes.c_uint64()
+        check(self._lib.sa_server_submit(self._srv, a.ctypes.data_as(ctypes.c_void_p), a.size,
+                                         ctypes.byref(t)), "sa_server_submit")
+        self._n[t.value] = a.size
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(done, suffix array as numpy uint32 or None, latency in ms or None)."""
+        import numpy as np
+        n = self._n[ticket]
+        out = np.empty(n, dtype=np.uint32)
+        done = ctypes.c_int(0)
+        lat = ctypes.c_double(0.0)
+        check(self._lib.sa_server_poll(self._srv, ticket, out.ctypes.data_as(ctypes.c_void_p),
+                                       ctypes.byref(done), ctypes.byref(lat)), "sa_server_poll")
+        if not done.value:
+            return False, None, None
+        del self._n[ticket]
+        return True, out, float(lat.value)
+
+    def stats(self) -> dict:
+        st = _native.ServerStats()
+        check(self._lib.sa_server_stats(self._srv, ctypes.byref(st)), "sa_server_stats")
+        return {k: getattr(st, k) for k, _ in _native.ServerStats._fields_}

@@ -32,6 +32,8 @@ EXPORTED = [
     "sa_build_rounds",
     "sa_radix_sort_pairs", "sa_workspace_bytes", "sa_ctx_set_trace", "sa_ctx_reset_stats",
     "sa_ctx_set_isa_mode", "sa_ctx_set_tuning", "sa_ctx_get_tuning",
+    "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll",
+    "sa_server_stats",
     "sa_ctx_get_kernel_stats", "sa_strerror",
 ]
 
@@ -70,6 +72,14 @@ class Tuning(ctypes.Structure):
                 ("reserved", ctypes.c_uint32 * 4)]
 
 
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("suffixes", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
+                ("busy_ms", ctypes.c_double), ("queued", ctypes.c_uint64),
+                ("running", ctypes.c_uint64), ("slots", ctypes.c_uint64),
+                ("arena_positions", ctypes.c_uint64)]
+
+
 class KernelStats(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_uint64), ("ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
@@ -102,6 +112,12 @@ def _declare(lib: ctypes.CDLL) -> None:
         "sa_ctx_reset_stats": ([vp], i32),
         "sa_ctx_get_kernel_stats": ([vp, i32, ctypes.POINTER(KernelStats)], i32),
         "sa_strerror": ([i32], ctypes.c_char_p),
+        "sa_server_create": ([ctypes.POINTER(vp), i32, u64, u64], i32),
+        "sa_server_destroy": ([vp], i32),
+        "sa_server_submit": ([vp, vp, u64, ctypes.POINTER(u64)], i32),
+        "sa_server_poll": ([vp, u64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
+                           i32),
+        "sa_server_stats": ([vp, ctypes.POINTER(ServerStats)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

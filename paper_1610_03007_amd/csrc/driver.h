@@ -1,0 +1,161 @@
+// Internal host-side driver shared by the single-text, batched and serving
+// paths: the context (workspace, plans, tracing) and the round building blocks.
+#pragma once
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/sa.h"
+#include "kernels.h"
+
+using namespace sa;
+
+// Automatic ISA mode: lazy when at most 1/kLazyRatio of the suffixes survive
+// round 0 (each later gather may then cost a binary search instead of every
+// suffix costing a random 4-byte write).
+constexpr u64 kLazyRatioDefault = 8;
+
+struct TraceRec {
+  hipEvent_t start, stop;
+  int kind;
+  double bytes;      // algorithmic bytes, if known at launch
+  int sort_slot;     // >= 0: bytes depend on the plan of this sort (pass `pass`)
+  int pass;
+  u64 count;
+};
+
+struct sa_ctx {
+  int device = 0;
+  u64 cap = 0;  // element capacity of the workspace
+  u64* keysA = nullptr;
+  u64* keysB = nullptr;
+  u32* valsA = nullptr;
+  u32* valsB = nullptr;
+  u32* isa = nullptr;
+  u32* act_idx = nullptr;
+  u32* act_rank = nullptr;
+  u64* act_ti = nullptr;  // batch survivors: (text << 32) | local position
+  u64 act_ti_cap = 0;
+  u64* toff = nullptr;    // batch text offsets on the device
+  u64 toff_cap = 0;
+  u64* status = nullptr;  // sort look-back: [tiles][kRadix]
+  u64* st3 = nullptr;     // re-rank look-back: 3 x [tiles]
+  u64 rr_tiles_cap = 0;
+  // Small control block: hist_in | hist_run | tickets | counters | plan | present | code.
+  void* small = nullptr;
+  u32* hist_in = nullptr;   // [kMaxPasses][kChunks][kRadix] input-order chunk histograms
+  u32* hist_run = nullptr;  // [kMaxPasses][kChunks][kRadix] histograms fed forward by sweeps
+  u32* tickets = nullptr;   // [kMaxPasses][kChunks] tile tickets
+  u64* counters = nullptr;
+  SortPlan* plan = nullptr;
+  u32* present = nullptr;
+  u16* code = nullptr;
+  // Pinned readback area: counters copy + per-sort plan flags.
+  u64* h_counters = nullptr;
+  u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][3 * kMaxPasses]
+  u32 gen = 0;
+  int isa_mode = SA_ISA_AUTO;
+  int sort_items = kSortItemsDefault;  // radix-sort items per thread (tile size)
+  int sort_wgs_per_cu = 0;             // persistent sweep workgroups per CU (0 = by tile size)
+  int num_cus = 256;
+  u64 lazy_ratio = kLazyRatioDefault;
+  int round0_trim = 1;  // round-0 keys fill whole radix digits
+  bool trace = false;
+  std::vector<TraceRec> recs;
+  std::vector<hipEvent_t> event_pool;
+  size_t event_used = 0;
+  sa_kernel_stats stats[SA_KERNEL_KINDS];
+  sa_build_info info;
+};
+
+
+namespace drv {
+
+constexpr size_t kChunkHistWords = size_t(kMaxPasses) * kChunks * kRadix;
+constexpr size_t kTicketWords = size_t(kMaxPasses) * kChunks;
+constexpr size_t kSmallHist = (2 * kChunkHistWords + kTicketWords) * sizeof(u32);
+constexpr size_t kSmallCounters = size_t(kCtrCount) * sizeof(u64);
+constexpr size_t kSmallPlan = (sizeof(SortPlan) + 255) / 256 * 256;
+constexpr size_t kSmallPresent = 256 * sizeof(u32);
+constexpr size_t kSmallCode = 256 * sizeof(u16);
+constexpr size_t kSmallBytes = kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent + kSmallCode;
+constexpr int kPlanFlagWords = 3 * kMaxPasses + 1;  // skip, src, iota, final_buf
+
+
+template <typename T>
+bool dev_alloc(T** p, u64 count) {
+  if (hipMalloc(reinterpret_cast<void**>(p), std::max<u64>(count, 1) * sizeof(T)) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+u64 sort_status_words(u64 cap);
+u64 rerank_tiles(u64 cap);
+int bits_of(u64 v);
+void free_workspace(sa_ctx* c);
+sa_status ensure_workspace(sa_ctx* c, u64 n);
+u32 next_gen(sa_ctx* c, hipStream_t s);
+hipEvent_t take_event(sa_ctx* c);
+
+// Brackets one launch with events when tracing.
+struct Tracer {
+  sa_ctx* c;
+  hipStream_t s;
+  TraceRec rec{};
+  bool on;
+  Tracer(sa_ctx* ctx, hipStream_t st, int kind, double bytes, int sort_slot = -1, int pass = 0,
+         u64 count = 0)
+      : c(ctx), s(st), on(ctx->trace) {
+    if (!on) return;
+    rec.kind = kind;
+    rec.bytes = bytes;
+    rec.sort_slot = sort_slot;
+    rec.pass = pass;
+    rec.count = count;
+    rec.start = take_event(c);
+    rec.stop = take_event(c);
+    if (!rec.start || !rec.stop) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(rec.start, s);
+  }
+  ~Tracer() {
+    if (!on) return;
+    (void)hipEventRecord(rec.stop, s);
+    c->recs.push_back(rec);
+  }
+};
+
+void collect_trace(sa_ctx* c);
+
+// Ping-pong buffers of one sort: input in (kA, vA), output in A or B.
+struct Bufs {
+  u64* kA;
+  u64* kB;
+  u32* vA;
+  u32* vB;
+};
+
+Bufs full_bufs(sa_ctx* c);
+SortGeom make_geom(u64 count, int items);
+int default_wgs_per_cu(int items);
+void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
+              hipStream_t s);
+void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s);
+RerankArgs single_args(u64 count, u64 n, int b, int mode);
+sa_status readback(sa_ctx* c, hipStream_t s);
+u32 passes_run(const sa_ctx* c, int slot, int npass);
+u32 final_buf_of(const sa_ctx* c, int slot);
+sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_sa, u32* d_isa,
+                       hipStream_t s);
+// Settles trace records after a build: collected on success, dropped on error.
+void settle_trace(sa_ctx* c, sa_status st);
+
+}  // namespace drv

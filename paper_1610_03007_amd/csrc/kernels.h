@@ -65,10 +65,10 @@ constexpr int kRerankWriteRanks = 2;
 // Key layout of the sorted set:
 //   group     = key >> gshift (64: one group, round 0 of a single text)
 //   old rank  = (key >> rshift) & rmask (rmask 0: every element has rank 1)
-//   text id   = key >> idshift when toff (batch text offsets, T + 1) is set;
-//               ranks and positions are then local to that text, SA and ISA
-//               are addressed at toff[t] + local, survivors go to act_ti as
-//               (t << 32) | local instead of act_idx.
+//   text id   = key >> idshift in multi-text mode; ranks and positions are
+//               then local to that text, SA and ISA are addressed at
+//               tbase[t] + local, survivors go to act_ti as (t << 32) | local
+//               instead of act_idx.
 struct RerankArgs {
   u64 count;
   u64 n;
@@ -77,7 +77,12 @@ struct RerankArgs {
   u64 rmask;
   int idshift;
   int mode;
-  const u64* toff;
+  // Multi-text mode (tbase set): text t = key >> idshift starts at tbase[t] in
+  // the SA / ISA arenas and has tlen[t] suffixes; texts with tround0[t] set
+  // carry round-0 keys (one group per text, every rank 1).
+  const u64* tbase;
+  const u64* tlen;
+  const u8* tround0;
 };
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            const u32* valsB, const SortPlan* plan, const RerankArgs& args,
@@ -103,14 +108,45 @@ void launch_fill_u32(u32* p, u64 count, u32 value, hipStream_t s);
 
 __host__ __device__ inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }
 
-// Batch (toff = device u64[num_texts + 1] text offsets, total = toff[num_texts]).
-// Round 0: keys (t << idshift | packed codes of text t), values = local position.
-void launch_pack_text_batch(const u8* text, u64 total, const u64* toff, u64 num_texts,
-                            int idshift, const u16* code, const u64* counters, u64* keys,
-                            u32* vals, hipStream_t s);
-// Later rounds: key = t << idshift | rank << b | ISA[toff[t] + i + h] (0 past text end).
-void launch_pack_pairs_batch(const u64* act_ti, const u32* act_rank, u64 count, const u64* toff,
-                             u64 h, int b, int idshift, const u32* isa, u64* keys, u32* vals,
+// ---------------------------------------------------------------------------
+// Multi-text engine (batched builds and the server): per-text tables.
+struct TextTab {
+  u64* base;     // [slots] first position of the text in the text / SA / ISA arenas
+  u64* len;      // [slots] text length
+  u16* code;     // [slots][256] character codes 1..sigma_t (0: absent)
+  u32* present;  // [slots][8] bitmap of the bytes present (zero between uses)
+  u32* wc;       // [slots] code width w | characters per round-0 key c << 16
+  u64* h;        // [slots] doubling offset of the text's next round
+  u8* round0;    // [slots] 1 while the text's elements carry round-0 keys
+  u32* surv;     // [slots] survivors of the text after the last round
+};
+// Texts entering round 0 this round: text slot t[i] (i < m), whose elements go
+// to positions out[i] .. out[i] + len of the merged key array; chunk0[i] is the
+// first of its ceil(len / kNewChunk) chunks (chunk0[m] = total chunks).
+constexpr int kNewChunk = 2048;
+struct NewList {
+  const u32* t;
+  const u64* out;
+  const u64* chunk0;
+  u32 m;
+  u64 chunks;
+};
+void launch_multi_presence(const u8* arena, TextTab tab, NewList nl, hipStream_t s);
+// c = characters per round-0 key: floor((64 - idbits) / w), trimmed to whole
+// 8-bit digits of the full key when trim != 0. Clears the presence bitmaps.
+void launch_multi_codes(TextTab tab, NewList nl, int idbits, int trim, hipStream_t s);
+// Round-0 keys: (t << idshift) | c codes of text t from local position i (0 past
+// its end); values = i.
+void launch_multi_pack0(const u8* arena, TextTab tab, NewList nl, int idshift, u64* keys,
+                        u32* vals, hipStream_t s);
+// Later-round keys for survivors (t, i, r): (t << idshift) | (r << b) |
+// (i + h_t < n_t ? ISA[base_t + i + h_t] : 0); values = i.
+void launch_multi_pack_pairs(const u64* act_ti, const u32* act_rank, u64 count, TextTab tab,
+                             int b, int idshift, const u32* isa, u64* keys, u32* vals,
                              hipStream_t s);
+// surv[t] += number of survivors of text t among act_ti[0 .. *count_ptr)
+// (surv must be cleared before; bound >= *count_ptr sizes the launch).
+void launch_multi_count_survivors(const u64* act_ti, const u64* count_ptr, u64 bound, u32* surv,
+                                  hipStream_t s);
 
 }  // namespace sa

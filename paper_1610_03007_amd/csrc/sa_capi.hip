@@ -7,87 +7,9 @@
 // suffix is left. One 8-byte readback per round tells the host how many
 // suffixes remain.
 
-#include <algorithm>
-#include <cstdio>
-#include <cstring>
-#include <new>
-#include <vector>
+#include "driver.h"
 
-#include "../../include/sa.h"
-#include "kernels.h"
-
-using namespace sa;
-
-// Automatic ISA mode: lazy when at most 1/kLazyRatio of the suffixes survive
-// round 0 (each later gather may then cost a binary search instead of every
-// suffix costing a random 4-byte write).
-constexpr u64 kLazyRatioDefault = 8;
-
-struct TraceRec {
-  hipEvent_t start, stop;
-  int kind;
-  double bytes;      // algorithmic bytes, if known at launch
-  int sort_slot;     // >= 0: bytes depend on the plan of this sort (pass `pass`)
-  int pass;
-  u64 count;
-};
-
-struct sa_ctx {
-  int device = 0;
-  u64 cap = 0;  // element capacity of the workspace
-  u64* keysA = nullptr;
-  u64* keysB = nullptr;
-  u32* valsA = nullptr;
-  u32* valsB = nullptr;
-  u32* isa = nullptr;
-  u32* act_idx = nullptr;
-  u32* act_rank = nullptr;
-  u64* act_ti = nullptr;  // batch survivors: (text << 32) | local position
-  u64 act_ti_cap = 0;
-  u64* toff = nullptr;    // batch text offsets on the device
-  u64 toff_cap = 0;
-  u64* status = nullptr;  // sort look-back: [tiles][kRadix]
-  u64* st3 = nullptr;     // re-rank look-back: 3 x [tiles]
-  u64 rr_tiles_cap = 0;
-  // Small control block: hist_in | hist_run | tickets | counters | plan | present | code.
-  void* small = nullptr;
-  u32* hist_in = nullptr;   // [kMaxPasses][kChunks][kRadix] input-order chunk histograms
-  u32* hist_run = nullptr;  // [kMaxPasses][kChunks][kRadix] histograms fed forward by sweeps
-  u32* tickets = nullptr;   // [kMaxPasses][kChunks] tile tickets
-  u64* counters = nullptr;
-  SortPlan* plan = nullptr;
-  u32* present = nullptr;
-  u16* code = nullptr;
-  // Pinned readback area: counters copy + per-sort plan flags.
-  u64* h_counters = nullptr;
-  u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][3 * kMaxPasses]
-  u32 gen = 0;
-  int isa_mode = SA_ISA_AUTO;
-  int sort_items = kSortItemsDefault;  // radix-sort items per thread (tile size)
-  int sort_wgs_per_cu = 0;             // persistent sweep workgroups per CU (0 = by tile size)
-  int num_cus = 256;
-  u64 lazy_ratio = kLazyRatioDefault;
-  int round0_trim = 1;  // round-0 keys fill whole radix digits
-  bool trace = false;
-  std::vector<TraceRec> recs;
-  std::vector<hipEvent_t> event_pool;
-  size_t event_used = 0;
-  sa_kernel_stats stats[SA_KERNEL_KINDS];
-  sa_build_info info;
-};
-
-namespace {
-
-constexpr size_t kChunkHistWords = size_t(kMaxPasses) * kChunks * kRadix;
-constexpr size_t kTicketWords = size_t(kMaxPasses) * kChunks;
-constexpr size_t kSmallHist = (2 * kChunkHistWords + kTicketWords) * sizeof(u32);
-constexpr size_t kSmallCounters = size_t(kCtrCount) * sizeof(u64);
-constexpr size_t kSmallPlan = (sizeof(SortPlan) + 255) / 256 * 256;
-constexpr size_t kSmallPresent = 256 * sizeof(u32);
-constexpr size_t kSmallCode = 256 * sizeof(u16);
-constexpr size_t kSmallBytes = kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent + kSmallCode;
-constexpr int kPlanFlagWords = 3 * kMaxPasses + 1;  // skip, src, iota, final_buf
-
+namespace drv {
 
 u64 sort_status_words(u64 cap) { return ceil_div(cap, kSortTileMin) * kRadix; }
 u64 rerank_tiles(u64 cap) { return ceil_div(cap, kRerankTile); }
@@ -112,16 +34,6 @@ void free_workspace(sa_ctx* c) {
   c->status = c->st3 = nullptr;
   c->cap = 0;
   c->rr_tiles_cap = 0;
-}
-
-template <typename T>
-bool dev_alloc(T** p, u64 count) {
-  if (hipMalloc(reinterpret_cast<void**>(p), std::max<u64>(count, 1) * sizeof(T)) != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return false;
-  }
-  return true;
 }
 
 sa_status ensure_workspace(sa_ctx* c, u64 n) {
@@ -170,36 +82,6 @@ hipEvent_t take_event(sa_ctx* c) {
   return c->event_pool[c->event_used++];
 }
 
-// Brackets one launch with events when tracing.
-struct Tracer {
-  sa_ctx* c;
-  hipStream_t s;
-  TraceRec rec{};
-  bool on;
-  Tracer(sa_ctx* ctx, hipStream_t st, int kind, double bytes, int sort_slot = -1, int pass = 0,
-         u64 count = 0)
-      : c(ctx), s(st), on(ctx->trace) {
-    if (!on) return;
-    rec.kind = kind;
-    rec.bytes = bytes;
-    rec.sort_slot = sort_slot;
-    rec.pass = pass;
-    rec.count = count;
-    rec.start = take_event(c);
-    rec.stop = take_event(c);
-    if (!rec.start || !rec.stop) {
-      on = false;
-      return;
-    }
-    (void)hipEventRecord(rec.start, s);
-  }
-  ~Tracer() {
-    if (!on) return;
-    (void)hipEventRecord(rec.stop, s);
-    c->recs.push_back(rec);
-  }
-};
-
 void collect_trace(sa_ctx* c) {
   for (const TraceRec& r : c->recs) {
     float ms = 0;
@@ -223,14 +105,6 @@ void collect_trace(sa_ctx* c) {
   c->recs.clear();
   c->event_used = 0;
 }
-
-// Ping-pong buffers of one sort: input in (kA, vA), output in A or B.
-struct Bufs {
-  u64* kA;
-  u64* kB;
-  u32* vA;
-  u32* vB;
-};
 
 Bufs full_bufs(sa_ctx* c) { return Bufs{c->keysA, c->keysB, c->valsA, c->valsB}; }
 
@@ -302,7 +176,7 @@ void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hi
   Tracer t(c, s, SA_KERNEL_RERANK, bytes);
   const u64 rt = c->rr_tiles_cap;
   launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->isa, d_sa,
-                        args.toff ? nullptr : c->act_idx, args.toff ? c->act_ti : nullptr,
+                        args.tbase ? nullptr : c->act_idx, args.tbase ? c->act_ti : nullptr,
                         c->act_rank, c->st3, c->st3 + rt, c->st3 + 2 * rt, c->counters, gen, s);
 }
 
@@ -317,7 +191,9 @@ RerankArgs single_args(u64 count, u64 n, int b, int mode) {
   a.rmask = b > 0 ? ~u64(0) : 0;
   a.idshift = 0;
   a.mode = mode;
-  a.toff = nullptr;
+  a.tbase = nullptr;
+  a.tlen = nullptr;
+  a.tround0 = nullptr;
   return a;
 }
 
@@ -459,139 +335,27 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   return SA_OK;
 }
 
-// Batch: T texts concatenated at device `text`, host offsets h_off[0..T]. One
-// sort and one re-rank per round for all texts: the text id sits in the high
-// key bits, ranks are local (Section 2.1 names per text), SA entries are local
-// positions written at h_off[t] + rank - 1.
-sa_status build_batch(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d_sa,
-                      hipStream_t s) {
-  std::memset(&c->info, 0, sizeof(c->info));
-  if (!h_off || T == 0) return SA_EINVAL;
-  if (h_off[0] != 0) return SA_EINVAL;
-  u64 max_n = 0;
-  for (u32 t = 0; t < T; ++t) {
-    if (h_off[t + 1] < h_off[t]) return SA_EINVAL;
-    max_n = std::max<u64>(max_n, h_off[t + 1] - h_off[t]);
+void settle_trace(sa_ctx* c, sa_status st) {
+  if (st == SA_OK && c->trace) {
+    collect_trace(c);
+  } else {
+    // Events of a failed build may not have completed.
+    c->recs.clear();
+    c->event_used = 0;
   }
-  const u64 N = h_off[T];
-  c->info.n = N;
-  if (max_n >= (u64(1) << 32)) return SA_ETOOBIG;
-  if (N == 0) return SA_OK;
-  if (!text || !d_sa) return SA_EINVAL;
-  if (T == 1) return build_rounds(c, text, N, 0, d_sa, nullptr, s);
-  const int idbits = bits_of(u64(T) - 1);
-  const int B = bits_of(max_n);
-  if (idbits + 2 * B > 64) return SA_ETOOBIG;
-  if (hipSetDevice(c->device) != hipSuccess) return SA_EDEVICE;
-  sa_status st = ensure_workspace(c, N);
-  if (st != SA_OK) return st;
-  if (c->act_ti_cap < c->cap) {
-    (void)hipFree(c->act_ti);
-    c->act_ti = nullptr;
-    c->act_ti_cap = 0;
-    if (!dev_alloc(&c->act_ti, c->cap)) return SA_ENOMEM;
-    c->act_ti_cap = c->cap;
-  }
-  if (c->toff_cap < u64(T) + 1) {
-    (void)hipFree(c->toff);
-    c->toff = nullptr;
-    c->toff_cap = 0;
-    if (!dev_alloc(&c->toff, u64(T) + 1)) return SA_ENOMEM;
-    c->toff_cap = u64(T) + 1;
-  }
-  if (hipMemcpyAsync(c->toff, h_off, (u64(T) + 1) * sizeof(u64), hipMemcpyHostToDevice, s) !=
-      hipSuccess)
-    return SA_EDEVICE;
-
-  const Bufs full = full_bufs(c);
-  const int idshift0 = 64 - idbits;
-  {
-    Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    launch_fill_u64(c->counters, kCtrCount, 0, s);
-    launch_fill_u64(reinterpret_cast<u64*>(c->present), 256 / 2, 0, s);
-  }
-  {
-    Tracer t(c, s, SA_KERNEL_OTHER, double(N));
-    launch_byte_presence(text, N, c->present, s);
-    launch_alphabet_codes(c->present, c->code, c->counters, c->round0_trim, idbits, s);
-  }
-  {
-    Tracer t(c, s, SA_KERNEL_PACK_TEXT, double(N) * 13.0);
-    launch_pack_text_batch(text, N, c->toff, T, idshift0, c->code, c->counters, c->keysA,
-                           c->valsA, s);
-  }
-  run_sort(c, full, N, kMaxPasses, 1, 0, s);
-  RerankArgs a{};
-  a.count = N;
-  a.n = 0;
-  a.gshift = idshift0;  // round 0: one group per text, every rank 1
-  a.rshift = 0;
-  a.rmask = 0;
-  a.idshift = idshift0;
-  a.mode = kRerankScatterIsa;
-  a.toff = c->toff;
-  run_rerank(c, full, a, d_sa, s);
-  st = readback(c, s);
-  if (st != SA_OK) return st;
-
-  sa_build_info& info = c->info;
-  info.sigma = u32(c->h_counters[kCtrSigma]);
-  info.code_bits = u32(c->h_counters[kCtrCodeBits]);
-  info.chars0 = u32(c->h_counters[kCtrChars]);
-  info.rounds = 1;
-  info.active[0] = N;
-  info.key_bits[0] = u32(idbits) + info.code_bits * info.chars0;
-  info.passes_run[0] = passes_run(c, 0, kMaxPasses);
-  u64 h = info.chars0;
-  info.prefix_len = h;
-  u64 active = c->h_counters[kCtrActive];
-
-  const int key_bits = idbits + 2 * B;
-  const int npass = int(ceil_div(u64(key_bits), kRadixBits));
-  a.gshift = B;  // group = (text, rank)
-  a.rshift = B;
-  a.rmask = (u64(1) << B) - 1;
-  a.idshift = 2 * B;
-  while (active > 0) {
-    if (info.rounds >= SA_MAX_ROUNDS) return SA_EDEVICE;
-    const int slot = int(info.rounds);
-    {
-      Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
-      launch_pack_pairs_batch(c->act_ti, c->act_rank, active, c->toff, h, B, 2 * B, c->isa,
-                              c->keysA, c->valsA, s);
-    }
-    run_sort(c, full, active, npass, 1, slot, s);
-    a.count = active;
-    run_rerank(c, full, a, d_sa, s);
-    st = readback(c, s);
-    if (st != SA_OK) return st;
-    info.active[slot] = active;
-    info.key_bits[slot] = u32(key_bits);
-    info.passes_run[slot] = passes_run(c, slot, npass);
-    info.rounds += 1;
-    h *= 2;
-    info.prefix_len = h;
-    active = c->h_counters[kCtrActive];
-  }
-  return SA_OK;
 }
 
-// Runs a build and settles the trace records: collected on success, dropped on
-// error (their events may not have completed).
 sa_status build_impl(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_sa, u32* d_isa,
                      hipStream_t s) {
   if (!c) return SA_EINVAL;
   sa_status st = build_rounds(c, text, n, max_rounds, d_sa, d_isa, s);
-  if (st == SA_OK && c->trace) {
-    collect_trace(c);
-  } else {
-    c->recs.clear();
-    c->event_used = 0;
-  }
+  settle_trace(c, st);
   return st;
 }
 
-}  // namespace
+}  // namespace drv
+
+using namespace drv;
 
 extern "C" {
 
@@ -655,20 +419,6 @@ sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigm
   if (!ctx) return SA_EINVAL;
   if (sigma == 0 || sigma > 256) return SA_EINVAL;
   return build_impl(ctx, d_text, n, 0, d_sa, nullptr, static_cast<hipStream_t>(stream));
-}
-
-sa_status sa_build_batch(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets,
-                         uint32_t num_texts, uint32_t* d_sas, void* stream) {
-  if (!ctx) return SA_EINVAL;
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  sa_status st = build_batch(ctx, d_texts, h_offsets, num_texts, d_sas, s);
-  if (st == SA_OK && ctx->trace) {
-    collect_trace(ctx);
-  } else {
-    ctx->recs.clear();
-    ctx->event_used = 0;
-  }
-  return st;
 }
 
 sa_status sa_build_rounds(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t max_rounds,

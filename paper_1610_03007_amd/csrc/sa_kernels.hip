@@ -812,7 +812,9 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64 kp = j ? k[j - 1] : kprev;
     const u64 kn = (j + 1 < I) ? k[j + 1] : knext;
     const bool head = (p == 0) || (k[j] != kp);
-    const bool grp = (p == 0) || (a.gshift < 64 && (k[j] >> a.gshift) != (kp >> a.gshift));
+    int gsh = a.gshift;
+    if (a.tbase && a.tround0[k[j] >> a.idshift]) gsh = a.idshift;  // group = text
+    const bool grp = (p == 0) || (gsh < 64 && (k[j] >> gsh) != (kp >> gsh));
     const bool uniq = head && ((p + 1 == count) || (kn != k[j]));
     if (head) {
       flags |= 1u << j;
@@ -902,17 +904,19 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     if (p >= count) break;
     if ((flags >> j) & 1u) ss = p;
     if ((gflags >> j) & 1u) gs = p;
-    const u64 r0 = a.rmask ? ((k[j] >> a.rshift) & a.rmask) : 1;
+    // Text of the element: the whole text, or (multi-text) the one named by
+    // the key's high bits; ranks and positions are local to it.
+    u64 gb = 0, nt = a.n, t = 0;
+    bool first_round = a.rmask == 0;
+    if (a.tbase) {
+      t = k[j] >> a.idshift;
+      gb = a.tbase[t];
+      nt = a.tlen[t];
+      first_round = a.tround0[t] != 0;
+    }
+    const u64 r0 = first_round ? 1 : ((k[j] >> a.rshift) & a.rmask);
     const u64 nr = r0 + ss - gs;
     const bool uniq = (flags >> (16 + j)) & 1u;
-    // Text of the element: the whole text, or (batch) the one named by the
-    // key's high bits; ranks and positions are local to it.
-    u64 gb = 0, nt = a.n, t = 0;
-    if (a.toff) {
-      t = k[j] >> a.idshift;
-      gb = a.toff[t];
-      nt = a.toff[t + 1] - gb;
-    }
     if (v[j] >= nt || nr == 0 || nr > nt || (!uniq && out >= count)) {
       bad = true;
       break;
@@ -1092,18 +1096,18 @@ void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const
 }
 
 // ---------------------------------------------------------------------------
-// Batched rounds: many texts concatenated (CSR offsets toff[0..T]); keys carry
-// the text id in their high bits so that one sort and one re-rank per round
-// serve every text; ranks, values and SA entries are local to each text.
+// Multi-text engine: many texts in one round. Keys carry the text slot in their
+// high bits so that one sort and one re-rank per round serve every text; each
+// text has its own alphabet codes, its own round and its own doubling offset.
 
 namespace {
 
-// Text containing global position g: the last t with toff[t] <= g.
-__device__ inline u64 text_of(const u64* __restrict__ toff, u64 num_texts, u64 g) {
-  u64 lo = 0, hi = num_texts;  // toff[lo] <= g < toff[hi]
+// Index i of the new text owning chunk `b`: the last i with chunk0[i] <= b.
+__device__ inline u32 new_text_of(const u64* __restrict__ chunk0, u32 m, u64 b) {
+  u32 lo = 0, hi = m;
   while (hi - lo > 1) {
-    const u64 mid = (lo + hi) >> 1;
-    if (toff[mid] <= g)
+    const u32 mid = (lo + hi) >> 1;
+    if (chunk0[mid] <= b)
       lo = mid;
     else
       hi = mid;
@@ -1113,82 +1117,199 @@ __device__ inline u64 text_of(const u64* __restrict__ toff, u64 num_texts, u64 g
 
 }  // namespace
 
-// Round-0 keys of a batch: key[g] = (t << idshift) | c character codes of text t
-// from local position i (0 past the end of text t); val[g] = i.
-__global__ __launch_bounds__(kPackBlock) void pack_text_batch_kernel(
-    const u8* __restrict__ text, u64 total, const u64* __restrict__ toff, u64 num_texts,
-    int idshift, const u16* __restrict__ code, const u64* __restrict__ counters,
-    u64* __restrict__ keys, u32* __restrict__ vals) {
+__global__ __launch_bounds__(256) void multi_presence_kernel(const u8* __restrict__ arena,
+                                                             TextTab tab, NewList nl) {
+  __shared__ u32 seen[256];
+  seen[threadIdx.x] = 0;
+  __syncthreads();
+  const u64 b = blockIdx.x;
+  const u32 i = new_text_of(nl.chunk0, nl.m, b);
+  const u32 t = nl.t[i];
+  const u64 start = (b - nl.chunk0[i]) * kNewChunk;
+  const u64 len = tab.len[t];
+  const u64 end = (start + kNewChunk < len) ? start + kNewChunk : len;
+  // Absolute byte range [lo, hi) of the chunk: 16-byte words inside it, single
+  // bytes at the unaligned ends.
+  const u64 lo = tab.base[t] + start, hi = tab.base[t] + end;
+  const u64 alo = (lo + 15) & ~u64(15), ahi = hi & ~u64(15);
+  if (alo < ahi) {
+    const uint4* v = reinterpret_cast<const uint4*>(arena + alo);
+    const u64 words = (ahi - alo) / 16;
+    for (u64 q = threadIdx.x; q < words; q += 256) {
+      const uint4 w = v[q];
+      const u32 ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int by = 0; by < 4; ++by) seen[(ws[k] >> (8 * by)) & 0xFFu] = 1;
+      }
+    }
+    for (u64 q = lo + threadIdx.x; q < alo; q += 256) seen[arena[q]] = 1;
+    for (u64 q = ahi + threadIdx.x; q < hi; q += 256) seen[arena[q]] = 1;
+  } else {
+    for (u64 q = lo + threadIdx.x; q < hi; q += 256) seen[arena[q]] = 1;
+  }
+  __syncthreads();
+  if (seen[threadIdx.x])
+    atomicOr(&tab.present[t * 8 + threadIdx.x / 32], 1u << (threadIdx.x % 32));
+}
+
+void launch_multi_presence(const u8* arena, TextTab tab, NewList nl, hipStream_t s) {
+  if (nl.chunks == 0) return;
+  hipLaunchKernelGGL(multi_presence_kernel, dim3(u32(nl.chunks)), dim3(256), 0, s, arena, tab, nl);
+}
+
+__global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList nl, int idbits,
+                                                          int trim) {
+  __shared__ u32 wsum[4];
+  const u32 t = nl.t[blockIdx.x];
+  const int d = threadIdx.x;
+  const u32 p = (tab.present[t * 8 + d / 32] >> (d % 32)) & 1u;
+  const u32 inc = wave_inclusive_sum(p);
+  if (lane_id() == kWave - 1) wsum[d / kWave] = inc;
+  __syncthreads();
+  u32 off = 0, total = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < d / kWave) off += wsum[w];
+    total += wsum[w];
+  }
+  tab.code[size_t(t) * 256 + d] = p ? u16(off + inc) : u16(0);
+  __syncthreads();
+  if (d < 8) tab.present[t * 8 + d] = 0;  // clean for the slot's next text
+  if (d == 0) {
+    u32 w = 32 - __clz(total);
+    if (w == 0) w = 1;
+    const u32 avail = 64u - u32(idbits);
+    u32 c = avail / w;
+    if (c < 1) c = 1;
+    const u32 used = u32(idbits) + c * w;
+    if (trim && used % kRadixBits != 0 && used > kRadixBits) {
+      const u32 full = (used / kRadixBits) * kRadixBits;
+      if (full > u32(idbits)) {
+        const u32 ct = (full - u32(idbits)) / w;
+        if (ct >= 1) c = ct;
+      }
+    }
+    tab.wc[t] = w | (c << 16);
+  }
+}
+
+void launch_multi_codes(TextTab tab, NewList nl, int idbits, int trim, hipStream_t s) {
+  if (nl.m == 0) return;
+  hipLaunchKernelGGL(multi_codes_kernel, dim3(nl.m), dim3(256), 0, s, tab, nl, idbits, trim);
+}
+
+__global__ __launch_bounds__(kPackBlock) void multi_pack0_kernel(const u8* __restrict__ arena,
+                                                                 TextTab tab, NewList nl,
+                                                                 int idshift,
+                                                                 u64* __restrict__ keys,
+                                                                 u32* __restrict__ vals) {
+  static_assert(kNewChunk == kPackTile, "one chunk per packing workgroup");
   __shared__ u16 s_code[256];
   __shared__ u16 s_sym[kPackTile + kPackHalo];
-  const int t = threadIdx.x;
-  const u64 base = u64(blockIdx.x) * kPackTile;
-  const u32 w = u32(counters[kCtrCodeBits]);
-  const u32 c = u32(counters[kCtrChars]);
-  s_code[t] = code[t];
+  __shared__ u64 s_out[kPackTile];
+  const int th = threadIdx.x;
+  const u64 b = blockIdx.x;
+  const u32 i = new_text_of(nl.chunk0, nl.m, b);
+  const u32 t = nl.t[i];
+  const u64 start = (b - nl.chunk0[i]) * kNewChunk;
+  const u64 len = tab.len[t];
+  const u8* txt = arena + tab.base[t];
+  const u32 wc = tab.wc[t];
+  const u32 w = wc & 0xFFFFu, c = wc >> 16;
+  s_code[th] = tab.code[size_t(t) * 256 + th];
   __syncthreads();
-  for (int i = t; i < kPackTile + kPackHalo; i += kPackBlock) {
-    const u64 p = base + u64(i);
-    s_sym[i] = (p < total) ? s_code[text[p]] : u16(0);
+  for (int q = th; q < kPackTile + kPackHalo; q += kPackBlock) {
+    const u64 p = start + u64(q);
+    s_sym[q] = (p < len) ? s_code[txt[p]] : u16(0);
   }
   __syncthreads();
-  const int first = t * kPackItems;
-  const u64 g0 = base + u64(first);
-  if (g0 >= total) return;
-  u64 tx = text_of(toff, num_texts, g0);
-  u64 tstart = toff[tx], tend = toff[tx + 1];
-  for (int j = 0; j < kPackItems; ++j) {
-    const u64 g = g0 + u64(j);
-    if (g >= total) break;
-    while (g >= tend) {  // crossed into the next non-empty text
-      ++tx;
-      tstart = tend;
-      tend = toff[tx + 1];
+  const u64 keymask = (c * w >= 64) ? ~u64(0) : ((u64(1) << (c * w)) - 1);
+  const int first = th * kPackItems;
+  u64 key = 0;
+  for (u32 j = 0; j < c; ++j) key = (key << w) | u64(s_sym[first + int(j)]);
+  s_out[first] = key;
+#pragma unroll
+  for (int j = 1; j < kPackItems; ++j) {
+    key = ((key << w) | u64(s_sym[first + j + int(c) - 1])) & keymask;
+    s_out[first + j] = key;
+  }
+  __syncthreads();
+  const u64 tag = u64(t) << idshift;
+  const u64 out = nl.out[i] + start;
+  for (int q = th; q < kPackTile; q += kPackBlock) {
+    const u64 p = start + u64(q);
+    if (p < len) {
+      keys[out + q] = tag | s_out[q];
+      vals[out + q] = u32(p);
     }
-    u64 key = 0;
-    for (u32 q = 0; q < c; ++q) {
-      const u64 p = g + q;
-      key = (key << w) | u64(p < tend ? s_sym[first + j + int(q)] : u16(0));
-    }
-    keys[g] = (tx << idshift) | key;
-    vals[g] = u32(g - tstart);
   }
 }
 
-void launch_pack_text_batch(const u8* text, u64 total, const u64* toff, u64 num_texts,
-                            int idshift, const u16* code, const u64* counters, u64* keys,
-                            u32* vals, hipStream_t s) {
-  if (total == 0) return;
-  hipLaunchKernelGGL(pack_text_batch_kernel, dim3(u32(ceil_div(total, kPackTile))),
-                     dim3(kPackBlock), 0, s, text, total, toff, num_texts, idshift, code,
-                     counters, keys, vals);
+void launch_multi_pack0(const u8* arena, TextTab tab, NewList nl, int idshift, u64* keys,
+                        u32* vals, hipStream_t s) {
+  if (nl.chunks == 0) return;
+  hipLaunchKernelGGL(multi_pack0_kernel, dim3(u32(nl.chunks)), dim3(kPackBlock), 0, s, arena, tab,
+                     nl, idshift, keys, vals);
 }
 
-// Later-round keys of a batch: for a surviving (text t, local i, rank r):
-// key = (t << idshift) | (r << b) | (i + h < n_t ? ISA[toff[t] + i + h] : 0).
-__global__ __launch_bounds__(256) void pack_pairs_batch_kernel(
-    const u64* __restrict__ act_ti, const u32* __restrict__ act_rank, u64 count,
-    const u64* __restrict__ toff, u64 h, int b, int idshift, const u32* __restrict__ isa,
-    u64* __restrict__ keys, u32* __restrict__ vals) {
+__global__ __launch_bounds__(256) void multi_pack_pairs_kernel(
+    const u64* __restrict__ act_ti, const u32* __restrict__ act_rank, u64 count, TextTab tab,
+    int b, int idshift, const u32* __restrict__ isa, u64* __restrict__ keys,
+    u32* __restrict__ vals) {
   const u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= count) return;
   const u64 ti = act_ti[p];
   const u64 t = ti >> 32;
   const u32 i = u32(ti);
-  const u64 gb = toff[t];
-  const u64 nt = toff[t + 1] - gb;
-  const u64 j = u64(i) + h;
+  const u64 gb = tab.base[t];
+  const u64 nt = tab.len[t];
+  const u64 j = u64(i) + tab.h[t];
   const u32 r1 = (j < nt) ? isa[gb + j] : 0u;
   keys[p] = (t << idshift) | (u64(act_rank[p]) << b) | u64(r1);
   vals[p] = i;
 }
 
-void launch_pack_pairs_batch(const u64* act_ti, const u32* act_rank, u64 count, const u64* toff,
-                             u64 h, int b, int idshift, const u32* isa, u64* keys, u32* vals,
+void launch_multi_pack_pairs(const u64* act_ti, const u32* act_rank, u64 count, TextTab tab,
+                             int b, int idshift, const u32* isa, u64* keys, u32* vals,
                              hipStream_t s) {
   if (count == 0) return;
-  hipLaunchKernelGGL(pack_pairs_batch_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
-                     act_ti, act_rank, count, toff, h, b, idshift, isa, keys, vals);
+  hipLaunchKernelGGL(multi_pack_pairs_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
+                     act_ti, act_rank, count, tab, b, idshift, isa, keys, vals);
+}
+
+__global__ __launch_bounds__(256) void multi_count_survivors_kernel(
+    const u64* __restrict__ act_ti, const u64* __restrict__ count_ptr, u32* __restrict__ surv) {
+  const u64 count = *count_ptr;
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  // Grid-stride with a wave-uniform trip count so that every lane takes part
+  // in the shuffles and ballots.
+  for (u64 base = u64(blockIdx.x) * blockDim.x; base < count; base += stride) {
+    const u64 p = base + threadIdx.x;
+    const bool valid = p < count;
+    const u32 t = valid ? u32(act_ti[p] >> 32) : 0xFFFFFFFFu;
+    // Survivors of one text are mostly adjacent: one atomic per run in the wave.
+    const u32 tprev = __shfl_up(t, 1, kWave);
+    const bool lead = valid && (lane_id() == 0 || tprev != t);
+    const u64 leads = __ballot(lead);
+    const u64 vm = __ballot(valid);
+    if (lead) {
+      const u64 above = leads & ~((u64(2) << lane_id()) - 1);  // next run start in the wave
+      const int next = above ? __ffsll((long long)above) - 1 : kWave;
+      const int last_valid = 63 - __clzll((long long)vm);
+      const int end = next < kWave ? next : last_valid + 1;
+      atomicAdd(&surv[t], u32(end - lane_id()));
+    }
+  }
+}
+
+void launch_multi_count_survivors(const u64* act_ti, const u64* count_ptr, u64 bound, u32* surv,
+                                  hipStream_t s) {
+  if (bound == 0) return;
+  u64 blocks = ceil_div(bound, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(multi_count_survivors_kernel, dim3(u32(blocks)), dim3(256), 0, s, act_ti,
+                     count_ptr, surv);
 }
 
 }  // namespace sa
