@@ -30,7 +30,11 @@ WORKLOADS = {
     "repetitive_1g": "256 KiB base x 4096 copies, 1e-4 substitutions, n=2^30",
     "batch_4096": "4096 texts, lengths log-uniform in [4 KiB, 8 MiB], half ACGT, half "
                   "order-3 Markov (96 bytes); one batched build",
+    "serve": "Poisson arrivals at 330.5 req/s (2 GB/s of text), lengths log-uniform in "
+             "[1 KiB, 64 MiB], ACGT or Markov slices; continuous-batching server",
 }
+SERVE_RATE = 330.5
+SERVE_LO, SERVE_HI = 1024, 1 << 26
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_03007_amd", "csrc", "sa_kernels.hip")
 
@@ -103,6 +107,189 @@ def cpu_baseline(text, sample: int, offsets=None):
     }
 
 
+def serve_stream(seconds: float, seed: int = 6):
+    """Arrival times, lengths and generators of a Poisson request stream."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    count = int(SERVE_RATE * seconds * 1.2) + 16
+    gaps = rng.exponential(1.0 / SERVE_RATE, count)
+    t = np.cumsum(gaps)
+    keep = t < seconds
+    t = t[keep]
+    n = np.floor(np.exp(rng.uniform(np.log(SERVE_LO), np.log(SERVE_HI), count)))[keep]
+    kind = rng.integers(0, 2, count)[keep]
+    off = rng.random(count)[keep]
+    return t, n.astype(np.int64), kind, off
+
+
+def serve_pools():
+    """1 GiB of each source; requests are slices at random offsets (the sources
+    are stationary, so a slice stands for a fresh draw)."""
+    import workloads as W
+    return [W.dna(1 << 30, seed=600), W.markov3(1 << 30, chain_seed=601)]
+
+
+def run_server_load(pools, stream, warm: float, mode: str):
+    """Replays the stream in real time. mode 'server': the continuous-batching
+    server; 'per_text': one sa_build per request, first come first served.
+    Returns (latencies of requests arriving after `warm` in ms, suffixes done in
+    the window, window seconds)."""
+    import queue
+    import threading
+    import numpy as np
+    import torch
+    t_arr, lens, kind, off = stream
+    texts = []
+    for n, k, o in zip(lens, kind, off):
+        pool = pools[int(k)]
+        a = int(o * (pool.size - n))
+        texts.append(pool[a:a + int(n)])
+    lat = {}
+    done_sufs = [0]
+    t_end = float(t_arr[-1]) if len(t_arr) else 0.0
+    start = time.perf_counter() + 0.05
+    if mode == "server":
+        from paper_1610_03007_amd import SuffixArrayServer
+        srv = SuffixArrayServer(0, capacity_bytes=96 << 30, max_text=SERVE_HI)
+        tickets = {}
+        lock = threading.Lock()
+        finished = threading.Event()
+
+        def producer():
+            for i, ta in enumerate(t_arr):
+                d = start + float(ta) - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tk = srv.submit(texts[i])
+                with lock:
+                    tickets[tk] = i
+            finished.set()
+
+        th = threading.Thread(target=producer)
+        th.start()
+        while True:
+            with lock:
+                pending = list(tickets.items())
+            for tk, i in pending:
+                ok, sa, ms = srv.poll(tk)
+                if ok:
+                    with lock:
+                        del tickets[tk]
+                    lat[i] = ms
+                    if t_arr[i] >= warm:
+                        done_sufs[0] += int(lens[i])
+            if finished.is_set() and not pending:
+                with lock:
+                    if not tickets:
+                        break
+            time.sleep(0.0005)
+        th.join()
+        stats = srv.stats()
+        srv.close()
+    else:
+        from paper_1610_03007_amd import SuffixArrayBuilder
+        b = SuffixArrayBuilder(0)
+        dev = torch.device("cuda", 0)
+        q = queue.Queue()
+
+        def producer():
+            for i, ta in enumerate(t_arr):
+                d = start + float(ta) - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                q.put((i, time.perf_counter()))
+            q.put(None)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        while True:
+            item = q.get()
+            if item is None:
+                break
+            i, t_sub = item
+            d = torch.from_numpy(texts[i]).to(dev)
+            sa = b.build(d)
+            torch.cuda.synchronize()
+            # Latency to the array ready on the device, as the server reports;
+            # the caller then gets it in host memory, as from poll().
+            lat[i] = (time.perf_counter() - t_sub) * 1e3
+            host = torch.empty(sa.numel(), dtype=torch.int32, pin_memory=True)
+            host.copy_(sa)
+            del sa, host
+            if t_arr[i] >= warm:
+                done_sufs[0] += int(lens[i])
+        th.join()
+        stats = None
+        b.close()
+    window = max(1e-9, (time.perf_counter() - start) - warm)
+    ls = np.array([lat[i] for i in range(len(t_arr)) if t_arr[i] >= warm])
+    return ls, done_sufs[0], window, stats
+
+
+def serve_main(args) -> int:
+    import numpy as np
+    t0 = time.perf_counter()
+    pools = serve_pools()
+    stream = serve_stream(args.serve_seconds)
+    print(f"[bench] serve: {len(stream[0])} requests over {args.serve_seconds}s, "
+          f"{stream[1].sum() / 1e9:.2f} GB of text; pools in {time.perf_counter() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+    warm = min(2.0, args.serve_seconds / 4)
+    res = {}
+    for mode in ("server", "per_text"):
+        ls, sufs, window, stats = run_server_load(pools, stream, warm, mode)
+        res[mode] = {
+            "requests": int(ls.size),
+            "msuffixes_s": round(sufs / window / 1e6, 2),
+            "p50_ms": round(float(np.percentile(ls, 50)), 3) if ls.size else None,
+            "p99_ms": round(float(np.percentile(ls, 99)), 3) if ls.size else None,
+            "mean_ms": round(float(ls.mean()), 3) if ls.size else None,
+        }
+        if stats:
+            res[mode]["rounds"] = int(stats["rounds"])
+            res[mode]["busy_ms"] = round(float(stats["busy_ms"]), 1)
+        print(f"[bench] {mode}: {res[mode]}", file=sys.stderr, flush=True)
+    # Capacity: the first requests of the stream all submitted at once.
+    cap_n = int(np.searchsorted(stream[0], min(4.0, args.serve_seconds)))
+    sat = (np.zeros(cap_n), stream[1][:cap_n], stream[2][:cap_n], stream[3][:cap_n])
+    for mode in ("server", "per_text"):
+        ls, sufs, window, _ = run_server_load(pools, sat, 0.0, mode)
+        res[mode]["capacity_msuffixes_s"] = round(sufs / window / 1e6, 2)
+        res[mode]["capacity_requests"] = cap_n
+        print(f"[bench] {mode} capacity: {res[mode]['capacity_msuffixes_s']} Msuffixes/s",
+              file=sys.stderr, flush=True)
+    offered = float(stream[1][stream[0] >= warm].sum()) / (args.serve_seconds - warm) / 1e6
+    result = {
+        "metric": "Msuffixes/s on 1 GPU + HBM roofline %; batched vs per-text; p50/p99 latency",
+        "value": res["server"]["msuffixes_s"],
+        "unit": "Msuffixes/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(args.serve_seconds * 1e3, 1),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "serve", "description": WORKLOADS["serve"],
+                   "seconds": args.serve_seconds, "warmup_s": warm,
+                   "offered_msuffixes_s": round(offered, 2), "parallelism": "single GPU"},
+        "serve": {
+            "p50_ms": res["server"]["p50_ms"], "p99_ms": res["server"]["p99_ms"],
+            "server": res["server"], "per_text": res["per_text"],
+            "p99_per_text_over_server": (round(res["per_text"]["p99_ms"] / res["server"]["p99_ms"], 3)
+                                         if res["server"]["p99_ms"] else None),
+            "capacity_server_over_per_text": round(
+                res["server"]["capacity_msuffixes_s"] / res["per_text"]["capacity_msuffixes_s"], 3),
+        },
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -114,6 +301,8 @@ def main() -> int:
                          "are sampled by whole texts)")
     ap.add_argument("--sort-items", type=int, default=0,
                     help="radix-sort items per thread (0 = library default)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the replayed request stream (serve workload)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy to run after the steps (counter calibration)")
     args = ap.parse_args()
@@ -123,6 +312,9 @@ def main() -> int:
               f"(a single text does not shard without an all-to-all exchange step).",
               file=sys.stderr)
         return 2
+
+    if args.workload == "serve":
+        return serve_main(args)
 
     import numpy as np
     import torch

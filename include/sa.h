@@ -89,20 +89,28 @@ sa_status sa_build_batch(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_
  * sa_build of the same text alone. */
 typedef struct sa_server sa_server;
 /* capacity_bytes: device memory the server may use (0 = half of the free
- * memory); max_text: longest accepted text (0 = 2^26). At most
- * 2^(64 - 2 * bits(max_text)) requests (capped at 1024) are in flight. */
+ * memory); max_text: longest accepted text (0 = 2^26). When max_text exceeds
+ * 16 MiB the server runs two lanes on separate streams: texts up to 1 MiB
+ * (a quarter of the memory) and longer texts, so short requests never wait
+ * behind a long text's round. Each lane holds at most
+ * 2^(64 - 2 * bits(lane max text)) requests (capped at 1024) in flight. */
 sa_status sa_server_create(sa_server** out, int device, uint64_t capacity_bytes,
                            uint64_t max_text);
 /* Stops the worker (requests still queued or running are dropped). */
 sa_status sa_server_destroy(sa_server* srv);
 /* Queues a copy of host text h_text[0, n); *ticket identifies the request.
- * SA_ETOOBIG if n exceeds max_text or the arena. */
+ * The copy goes into a pinned host pool of the lane (up to 4 GiB) when it has
+ * room, else into pageable memory. SA_ETOOBIG if n exceeds max_text or the
+ * arena. */
 sa_status sa_server_submit(sa_server* srv, const uint8_t* h_text, uint64_t n, uint64_t* ticket);
-/* *done = 1 once the request finished: its suffix array is copied to host
- * h_sa_out[0, n) and the request is released; latency_ms (may be NULL)
+/* *done = 1 once the request finished: its suffix array is copied to
+ * h_sa_out[0, n) and the request is released. h_sa_out may be host memory
+ * (pinned memory gets one direct copy) or device memory of the server's GPU; latency_ms (may be NULL)
  * receives the time from submit to the suffix array being complete on the
- * device. *done = 0 while it is queued or running. A failed request returns
- * its error once and is released. */
+ * device. *done = 0 while it is queued or running. With h_sa_out NULL a
+ * finished request reports *done = 2 and stays until polled with a buffer.
+ * A failed request returns its error once and is released; an unknown ticket
+ * gives SA_EINVAL. */
 sa_status sa_server_poll(sa_server* srv, uint64_t ticket, uint32_t* h_sa_out, int* done,
                          double* latency_ms);
 typedef struct {

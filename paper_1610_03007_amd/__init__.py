@@ -219,19 +219,38 @@ class SuffixArrayServer:
         self._n[t.value] = a.size
         return int(t.value)
 
-    def poll(self, ticket: int):
-        """(done, suffix array as numpy uint32 or None, latency in ms or None)."""
+    def poll(self, ticket: int, out=None):
+        """(done, suffix array or None, latency in ms or None).
+
+        Without ``out`` the array comes back as numpy uint32 over pinned host
+        memory (one direct copy from the device). ``out`` may instead be a
+        contiguous 32-bit torch tensor of the text's length, in host or device
+        memory, which is filled and returned."""
         import numpy as np
         n = self._n[ticket]
-        out = np.empty(n, dtype=np.uint32)
         done = ctypes.c_int(0)
         lat = ctypes.c_double(0.0)
-        check(self._lib.sa_server_poll(self._srv, ticket, out.ctypes.data_as(ctypes.c_void_p),
-                                       ctypes.byref(done), ctypes.byref(lat)), "sa_server_poll")
-        if not done.value:
+        if n:
+            # Ask first without a buffer (cheap while the request is running).
+            check(self._lib.sa_server_poll(self._srv, ticket, None, ctypes.byref(done), None),
+                  "sa_server_poll")
+            if done.value != 2:
+                return False, None, None
+        if out is None:
+            buf = torch.empty(n, dtype=torch.int32, pin_memory=n > 0)
+            res = buf.numpy().view(np.uint32)
+        else:
+            if not (isinstance(out, torch.Tensor) and out.is_contiguous()
+                    and out.dtype in (torch.int32, torch.uint32) and out.numel() == n):
+                raise ValueError("out must be a contiguous 32-bit tensor of the text's length")
+            buf = res = out
+        ptr = ctypes.c_void_p(buf.data_ptr()) if n else None
+        check(self._lib.sa_server_poll(self._srv, ticket, ptr, ctypes.byref(done),
+                                       ctypes.byref(lat)), "sa_server_poll")
+        if done.value != 1:
             return False, None, None
         del self._n[ticket]
-        return True, out, float(lat.value)
+        return True, res, float(lat.value)
 
     def stats(self) -> dict:
         st = _native.ServerStats()

@@ -11,6 +11,7 @@
 
 #include <chrono>
 #include <condition_variable>
+#include <cstring>
 #include <deque>
 #include <map>
 #include <memory>
@@ -41,6 +42,9 @@ struct Engine {
   std::vector<u8> busy, round0;
   u32* h_wc = nullptr;    // pinned
   u32* h_surv = nullptr;  // pinned
+  char* h_up = nullptr;   // pinned mirror of the per-round upload tables
+  size_t up_bytes = 0, o_up_base = 0, o_up_len = 0, o_up_h = 0, o_up_r0 = 0, o_up_nt = 0,
+         o_up_no = 0, o_up_nc = 0;
   u64 active = 0;         // survivors carried into the next round
   std::vector<u32> live;  // slots with elements in the active set or joining now
 
@@ -50,7 +54,9 @@ struct Engine {
     dev = nullptr;
     if (h_wc) (void)hipHostFree(h_wc);
     if (h_surv) (void)hipHostFree(h_surv);
+    if (h_up) (void)hipHostFree(h_up);
     h_wc = h_surv = nullptr;
+    h_up = nullptr;
   }
 
   sa_status init(sa_ctx* ctx, u32 nslots, int id_bits, int rank_bits) {
@@ -65,10 +71,15 @@ struct Engine {
       bytes += (b + 255) / 256 * 256;
       return at;
     };
-    const size_t o_base = take(S * 8), o_len = take(S * 8), o_code = take(S * 256 * 2),
-                 o_pres = take(S * 32), o_wc = take(S * 4), o_h = take(S * 8), o_r0 = take(S),
-                 o_surv = take(S * 4), o_nt = take(S * 4), o_no = take((S + 1) * 8),
-                 o_nc = take((S + 1) * 8);
+    // The tables written by the host each round come first, contiguous, so
+    // that one copy from a pinned mirror uploads them all.
+    const size_t o_base = take(S * 8), o_len = take(S * 8), o_h = take(S * 8), o_r0 = take(S),
+                 o_nt = take(S * 4), o_no = take((S + 1) * 8), o_nc = take((S + 1) * 8);
+    up_bytes = bytes;
+    o_up_base = o_base, o_up_len = o_len, o_up_h = o_h, o_up_r0 = o_r0, o_up_nt = o_nt,
+    o_up_no = o_no, o_up_nc = o_nc;
+    const size_t o_code = take(S * 256 * 2), o_pres = take(S * 32), o_wc = take(S * 4),
+                 o_surv = take(S * 4);
     if (hipMalloc(&dev, bytes) != hipSuccess) {
       dev = nullptr;
       (void)hipGetLastError();
@@ -88,7 +99,8 @@ struct Engine {
     d_new_out = reinterpret_cast<u64*>(p + o_no);
     d_new_chunk0 = reinterpret_cast<u64*>(p + o_nc);
     if (hipHostMalloc(reinterpret_cast<void**>(&h_wc), S * 4) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h_surv), S * 4) != hipSuccess)
+        hipHostMalloc(reinterpret_cast<void**>(&h_surv), S * 4) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h_up), up_bytes) != hipSuccess)
       return SA_ENOMEM;
     base.assign(S, 0);
     len.assign(S, 0);
@@ -132,23 +144,21 @@ struct Engine {
       h[t] = u64(chars[t]) << (round[t] - 1);
     }
     for (u32 t : nt) round0[t] = 1;
-    // Upload the tables that changed (small: a few values per slot).
+    // Upload the per-round tables (a few values per slot) in one copy from
+    // the pinned mirror. The previous round synchronised the stream, so the
+    // mirror is free to be rewritten.
+    std::memcpy(h_up + o_up_base, base.data(), slots * 8);
+    std::memcpy(h_up + o_up_len, len.data(), slots * 8);
+    std::memcpy(h_up + o_up_h, h.data(), slots * 8);
+    std::memcpy(h_up + o_up_r0, round0.data(), slots);
     if (m) {
-      if (hipMemcpyAsync(d_new_t, nt.data(), m * 4, hipMemcpyHostToDevice, s) != hipSuccess ||
-          hipMemcpyAsync(d_new_out, nout.data(), (m + 1) * 8, hipMemcpyHostToDevice, s) !=
-              hipSuccess ||
-          hipMemcpyAsync(d_new_chunk0, nchunk.data(), (m + 1) * 8, hipMemcpyHostToDevice, s) !=
-              hipSuccess)
-        return SA_EDEVICE;
+      std::memcpy(h_up + o_up_nt, nt.data(), m * 4);
+      std::memcpy(h_up + o_up_no, nout.data(), (m + 1) * 8);
+      std::memcpy(h_up + o_up_nc, nchunk.data(), (m + 1) * 8);
     }
-    if (hipMemcpyAsync(tab.base, base.data(), slots * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(tab.len, len.data(), slots * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(tab.h, h.data(), slots * 8, hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(tab.round0, round0.data(), slots, hipMemcpyHostToDevice, s) != hipSuccess)
+    const size_t up = m ? o_up_nc + (m + 1) * 8 : o_up_r0 + slots;
+    if (hipMemcpyAsync(dev, h_up, up, hipMemcpyHostToDevice, s) != hipSuccess)
       return SA_EDEVICE;
-    // The host vectors must stay alive until the copies ran: the round ends
-    // with a stream synchronisation below, and the vectors are members or
-    // locals that outlive it.
     NewList nl{d_new_t, d_new_out, d_new_chunk0, m, nchunk.back()};
     {
       Tracer tr(c, s, SA_KERNEL_OTHER, 0);
@@ -315,7 +325,9 @@ double now_s() {
 }
 
 struct Request {
-  std::vector<u8> text;  // host copy until the text is on the device
+  std::vector<u8> text;  // pageable host copy, used when the pinned pool is full
+  u8* pinned = nullptr;  // host copy in the lane's pinned pool, or null
+  u64 pin_at = 0;
   u64 n = 0;
   double t_arrive = 0, t_admit = 0, t_done = 0;
   int state = 0;  // 0 queued, 1 running, 2 done, 3 failed, 4 being copied out
@@ -326,7 +338,11 @@ struct Request {
 
 }  // namespace
 
-struct sa_server {
+namespace {
+
+// One lane of the server: its own context, stream, engine, device arena and
+// worker thread.
+struct Lane {
   sa_ctx* ctx = nullptr;
   Engine eng;
   int device = 0;
@@ -336,6 +352,11 @@ struct sa_server {
   u32* d_sa = nullptr;
   hipStream_t stream = nullptr;
   std::map<u64, u64> free_ranges;  // start -> length
+  // Pinned host pool holding submitted texts until they are on the device, so
+  // that each upload is one direct copy instead of a staged pageable one.
+  u8* h_pool = nullptr;
+  u64 pool_cap = 0;
+  std::map<u64, u64> pool_free;
   std::deque<u64> queue;
   std::unordered_map<u64, std::unique_ptr<Request>> reqs;
   std::vector<u32> free_slots;
@@ -344,39 +365,53 @@ struct sa_server {
   std::condition_variable cv;
   std::thread worker;
   bool stop = false;
-  u64 next_ticket = 1;
   // statistics
   u64 completed = 0, failed = 0, suffixes = 0, rounds = 0;
   double busy_s = 0;
 
-  bool alloc(u64 n, u64* out) {
-    for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+  // First-fit range allocation over a free list (start -> length).
+  static bool range_alloc(std::map<u64, u64>& fr, u64 n, u64* out) {
+    for (auto it = fr.begin(); it != fr.end(); ++it) {
       if (it->second >= n) {
         *out = it->first;
         const u64 rest = it->second - n, start = it->first + n;
-        free_ranges.erase(it);
-        if (rest) free_ranges[start] = rest;
+        fr.erase(it);
+        if (rest) fr[start] = rest;
         return true;
       }
     }
     return false;
   }
 
-  void release(u64 start, u64 n) {
+  static void range_release(std::map<u64, u64>& fr, u64 start, u64 n) {
     if (n == 0) return;
-    auto it = free_ranges.emplace(start, n).first;
+    auto it = fr.emplace(start, n).first;
     auto nx = std::next(it);
-    if (nx != free_ranges.end() && it->first + it->second == nx->first) {
+    if (nx != fr.end() && it->first + it->second == nx->first) {
       it->second += nx->second;
-      free_ranges.erase(nx);
+      fr.erase(nx);
     }
-    if (it != free_ranges.begin()) {
+    if (it != fr.begin()) {
       auto pv = std::prev(it);
       if (pv->first + pv->second == it->first) {
         pv->second += it->second;
-        free_ranges.erase(it);
+        fr.erase(it);
       }
     }
+  }
+
+  bool alloc(u64 n, u64* out) { return range_alloc(free_ranges, n, out); }
+  void release(u64 start, u64 n) { range_release(free_ranges, start, n); }
+
+  // Pool ranges are rounded to 64 bytes so that uploads start aligned.
+  static u64 pool_len(u64 n) { return (n + 63) & ~u64(63); }
+
+  void drop_host_copy(Request* r) {
+    if (r->pinned) {
+      range_release(pool_free, r->pin_at, pool_len(r->n));
+      r->pinned = nullptr;
+    }
+    std::vector<u8>().swap(r->text);
   }
 
   void run() {
@@ -417,17 +452,35 @@ struct sa_server {
       }
       const double t0 = now_s();
       sa_status st = SA_OK;
-      for (Request* r : copies)
-        if (hipMemcpyAsync(d_text + r->base, r->text.data(), r->n, hipMemcpyHostToDevice,
-                           stream) != hipSuccess)
-          st = SA_EDEVICE;
-      if (st == SA_OK) st = eng.round_step(d_text, d_sa, joining, finished, 0, stream);
-      if (st == SA_OK) {
-        // The texts are on the device once the round has synchronised.
-        for (Request* r : copies) std::vector<u8>().swap(r->text);
+      // A text that waited in pageable memory moves to the pinned pool first
+      // when there is room: a host copy and one direct upload beat the
+      // runtime's chunked staging of pageable memory.
+      for (Request* r : copies) {
+        if (r->pinned || !h_pool) continue;
+        bool got;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          got = range_alloc(pool_free, pool_len(r->n), &r->pin_at);
+        }
+        if (got) {
+          r->pinned = h_pool + r->pin_at;
+          std::memcpy(r->pinned, r->text.data(), r->n);
+        }
       }
+      for (Request* r : copies) {
+        const void* src = r->pinned ? static_cast<const void*>(r->pinned)
+                                    : static_cast<const void*>(r->text.data());
+        if (hipMemcpyAsync(d_text + r->base, src, r->n, hipMemcpyHostToDevice, stream) !=
+            hipSuccess)
+          st = SA_EDEVICE;
+      }
+      if (st == SA_OK) st = eng.round_step(d_text, d_sa, joining, finished, 0, stream);
+      // The round ends with a synchronisation, so the uploads are complete (or
+      // the stream is in error) and the host copies can go.
+      if (st != SA_OK) (void)hipStreamSynchronize(stream);
       const double t1 = now_s();
       std::lock_guard<std::mutex> lk(mu);
+      for (Request* r : copies) drop_host_copy(r);
       busy_s += t1 - t0;
       rounds += 1;
       if (st != SA_OK) {
@@ -460,6 +513,171 @@ struct sa_server {
   }
 };
 
+}  // namespace
+
+namespace {
+
+// Creates a lane serving texts of at most max_text bytes with capacity_bytes of
+// device memory.
+sa_status lane_create(std::unique_ptr<Lane>& out, int device, u64 capacity_bytes, u64 max_text) {
+  out.reset(new (std::nothrow) Lane());
+  if (!out) return SA_ENOMEM;
+  Lane* L = out.get();
+  L->device = device;
+  L->max_text = max_text;
+  const int B = bits_of(max_text);
+  int idbits = 64 - 2 * B;
+  if (idbits < 1) return SA_ETOOBIG;
+  if (idbits > 10) idbits = 10;  // at most 1024 requests in flight per lane
+  sa_status st = sa_ctx_create(&L->ctx, device, nullptr);
+  if (st != SA_OK) return st;
+  // Per arena position: text 1 + SA 4 + ISA 4 + keys 16 + values 8 + survivors
+  // 16 + look-back status ~1.
+  const u64 per = 50;
+  L->arena_cap = capacity_bytes / per;
+  if (L->arena_cap < max_text) return SA_ENOMEM;
+  sa_ctx* c = L->ctx;
+  st = ensure_workspace(c, L->arena_cap);
+  if (st != SA_OK) return st;
+  if (!dev_alloc(&c->act_ti, c->cap)) return SA_ENOMEM;
+  c->act_ti_cap = c->cap;
+  if (!dev_alloc(&L->d_text, L->arena_cap) || !dev_alloc(&L->d_sa, L->arena_cap))
+    return SA_ENOMEM;
+  const u32 slots = 1u << idbits;
+  st = L->eng.init(c, slots, idbits, B);
+  if (st != SA_OK) return st;
+  if (hipStreamCreateWithFlags(&L->stream, hipStreamNonBlocking) != hipSuccess)
+    return SA_EDEVICE;
+  // Pinned pool: twice the text arena, between 16 MiB and 4 GiB. Texts that do
+  // not fit wait in pageable memory instead.
+  u64 pool = 2 * L->arena_cap;
+  if (pool < (u64(16) << 20)) pool = u64(16) << 20;
+  if (pool > (u64(4) << 30)) pool = u64(4) << 30;
+  if (hipHostMalloc(reinterpret_cast<void**>(&L->h_pool), pool, hipHostMallocDefault) ==
+      hipSuccess) {
+    L->pool_cap = pool;
+    L->pool_free[0] = pool;
+  } else {
+    L->h_pool = nullptr;
+    (void)hipGetLastError();
+  }
+  L->free_ranges[0] = L->arena_cap;
+  L->slot_ticket.assign(slots, 0);
+  for (u32 k = slots; k-- > 0;) L->free_slots.push_back(k);
+  try {
+    L->worker = std::thread([L] { L->run(); });
+  } catch (...) {
+    return SA_ENOMEM;
+  }
+  return SA_OK;
+}
+
+void lane_destroy(Lane* L) {
+  if (!L) return;
+  {
+    std::lock_guard<std::mutex> lk(L->mu);
+    L->stop = true;
+  }
+  L->cv.notify_all();
+  if (L->worker.joinable()) L->worker.join();
+  (void)hipSetDevice(L->device);
+  if (L->stream) (void)hipStreamDestroy(L->stream);
+  (void)hipFree(L->d_text);
+  (void)hipFree(L->d_sa);
+  if (L->h_pool) (void)hipHostFree(L->h_pool);
+  L->eng.release();
+  if (L->ctx) sa_ctx_destroy(L->ctx);
+}
+
+sa_status lane_submit(Lane* L, u64 ticket, const uint8_t* h_text, uint64_t n) {
+  std::unique_ptr<Request> r(new (std::nothrow) Request());
+  if (!r) return SA_ENOMEM;
+  r->n = n;
+  r->t_arrive = now_s();
+  if (n) {
+    bool got = false;
+    {
+      std::lock_guard<std::mutex> lk(L->mu);
+      got = L->h_pool && Lane::range_alloc(L->pool_free, Lane::pool_len(n), &r->pin_at);
+    }
+    if (got) {
+      r->pinned = L->h_pool + r->pin_at;
+      std::memcpy(r->pinned, h_text, n);
+    } else {
+      try {
+        r->text.assign(h_text, h_text + n);
+      } catch (...) {
+        return SA_ENOMEM;
+      }
+    }
+  }
+  std::lock_guard<std::mutex> lk(L->mu);
+  if (n == 0) {
+    r->state = 2;
+    r->t_admit = r->t_done = r->t_arrive;
+    L->completed += 1;
+  } else {
+    L->queue.push_back(ticket);
+  }
+  L->reqs[ticket] = std::move(r);
+  L->cv.notify_all();
+  return SA_OK;
+}
+
+sa_status lane_poll(Lane* L, uint64_t ticket, uint32_t* h_sa_out, int* done, double* latency_ms,
+                    bool* released) {
+  *released = false;
+  Request* r = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(L->mu);
+    auto it = L->reqs.find(ticket);
+    if (it == L->reqs.end()) return SA_EINVAL;
+    r = it->second.get();
+    if (r->state == 3) {
+      const sa_status e = r->err;
+      L->reqs.erase(it);
+      *released = true;
+      return e;
+    }
+    if (r->state != 2) return SA_OK;
+    if (r->n && !h_sa_out) {
+      *done = 2;  // ready: call again with an output buffer
+      return SA_OK;
+    }
+    r->state = 4;
+  }
+  sa_status st = SA_OK;
+  if (r->n) {
+    if (hipSetDevice(L->device) != hipSuccess ||
+        hipMemcpy(h_sa_out, L->d_sa + r->base, r->n * sizeof(u32), hipMemcpyDefault) !=
+            hipSuccess)
+      st = SA_EDEVICE;
+  }
+  std::lock_guard<std::mutex> lk(L->mu);
+  if (latency_ms) *latency_ms = (r->t_done - r->t_arrive) * 1e3;
+  L->release(r->base, r->n);
+  L->reqs.erase(ticket);
+  L->cv.notify_all();
+  *released = true;
+  if (st == SA_OK) *done = 1;
+  return st;
+}
+
+}  // namespace
+
+// The server: size-class lanes, each a continuous-batching engine on its own
+// stream, so that short requests are never queued behind the sort of a long
+// text's round.
+struct sa_server {
+  int device = 0;
+  u64 max_text = 0;
+  std::vector<std::unique_ptr<Lane>> lanes;
+  std::vector<u64> lane_max;  // lane k takes texts with n <= lane_max[k]
+  std::mutex mu;
+  std::unordered_map<u64, int> owner;
+  u64 next_ticket = 1;
+};
+
 extern "C" {
 
 sa_status sa_server_create(sa_server** out, int device, uint64_t capacity_bytes,
@@ -468,49 +686,40 @@ sa_status sa_server_create(sa_server** out, int device, uint64_t capacity_bytes,
   *out = nullptr;
   if (max_text == 0) max_text = u64(1) << 26;
   if (max_text >= (u64(1) << 32)) return SA_ETOOBIG;
-  const int B = bits_of(max_text);
-  int idbits = 64 - 2 * B;
-  if (idbits < 1) return SA_ETOOBIG;
-  if (idbits > 10) idbits = 10;  // at most 1024 requests in flight
+  if (64 - 2 * bits_of(max_text) < 1) return SA_ETOOBIG;
+  if (capacity_bytes == 0) {
+    if (hipSetDevice(device) != hipSuccess) return SA_EDEVICE;
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return SA_EDEVICE;
+    capacity_bytes = u64(free_b) / 2;
+  }
   sa_server* srv = new (std::nothrow) sa_server();
   if (!srv) return SA_ENOMEM;
   srv->device = device;
   srv->max_text = max_text;
-  auto fail = [srv](sa_status e) {
-    sa_server_destroy(srv);  // frees whatever was set up; no worker yet
-    return e;
+  // Two lanes when the size range is wide: texts up to 1 MiB share a lane with
+  // a quarter of the memory; longer texts use the rest.
+  const u64 small = u64(1) << 20;
+  struct Spec {
+    u64 cap, maxn;
   };
-  sa_status st = sa_ctx_create(&srv->ctx, device, nullptr);
-  if (st != SA_OK) return fail(st);
-  if (capacity_bytes == 0) {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) return fail(SA_EDEVICE);
-    capacity_bytes = u64(free_b) / 2;
+  std::vector<Spec> specs;
+  if (max_text > 16 * small && capacity_bytes / 4 / 50 >= small) {
+    specs.push_back({capacity_bytes / 4, small});
+    specs.push_back({capacity_bytes - capacity_bytes / 4, max_text});
+  } else {
+    specs.push_back({capacity_bytes, max_text});
   }
-  // Per arena position: text 1 + SA 4 + ISA 4 + keys 16 + values 8 + survivors
-  // 16 + look-back status ~1.
-  const u64 per = 50;
-  srv->arena_cap = capacity_bytes / per;
-  if (srv->arena_cap < max_text) return fail(SA_ENOMEM);
-  sa_ctx* c = srv->ctx;
-  st = ensure_workspace(c, srv->arena_cap);
-  if (st != SA_OK) return fail(st);
-  if (!dev_alloc(&c->act_ti, c->cap)) return fail(SA_ENOMEM);
-  c->act_ti_cap = c->cap;
-  if (!dev_alloc(&srv->d_text, srv->arena_cap) || !dev_alloc(&srv->d_sa, srv->arena_cap))
-    return fail(SA_ENOMEM);
-  const u32 slots = 1u << idbits;
-  st = srv->eng.init(c, slots, idbits, B);
-  if (st != SA_OK) return fail(st);
-  if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess)
-    return fail(SA_EDEVICE);
-  srv->free_ranges[0] = srv->arena_cap;
-  srv->slot_ticket.assign(slots, 0);
-  for (u32 k = slots; k-- > 0;) srv->free_slots.push_back(k);
-  try {
-    srv->worker = std::thread([srv] { srv->run(); });
-  } catch (...) {
-    return fail(SA_ENOMEM);
+  for (const Spec& sp : specs) {
+    std::unique_ptr<Lane> L;
+    sa_status st = lane_create(L, device, sp.cap, sp.maxn);
+    if (st != SA_OK) {
+      lane_destroy(L.get());
+      sa_server_destroy(srv);
+      return st;
+    }
+    srv->lanes.push_back(std::move(L));
+    srv->lane_max.push_back(sp.maxn);
   }
   *out = srv;
   return SA_OK;
@@ -518,46 +727,35 @@ sa_status sa_server_create(sa_server** out, int device, uint64_t capacity_bytes,
 
 sa_status sa_server_destroy(sa_server* srv) {
   if (!srv) return SA_OK;
-  {
-    std::lock_guard<std::mutex> lk(srv->mu);
-    srv->stop = true;
-  }
-  srv->cv.notify_all();
-  if (srv->worker.joinable()) srv->worker.join();
-  (void)hipSetDevice(srv->device);
-  if (srv->stream) (void)hipStreamDestroy(srv->stream);
-  (void)hipFree(srv->d_text);
-  (void)hipFree(srv->d_sa);
-  srv->eng.release();
-  if (srv->ctx) sa_ctx_destroy(srv->ctx);
+  for (auto& L : srv->lanes) lane_destroy(L.get());
+  srv->lanes.clear();
   delete srv;
   return SA_OK;
 }
 
 sa_status sa_server_submit(sa_server* srv, const uint8_t* h_text, uint64_t n, uint64_t* ticket) {
   if (!srv || !ticket || (!h_text && n)) return SA_EINVAL;
-  if (n > srv->max_text || n > srv->arena_cap) return SA_ETOOBIG;
-  std::unique_ptr<Request> r(new (std::nothrow) Request());
-  if (!r) return SA_ENOMEM;
-  r->n = n;
-  r->t_arrive = now_s();
-  try {
-    r->text.assign(h_text, h_text + n);
-  } catch (...) {
-    return SA_ENOMEM;
+  if (n > srv->max_text) return SA_ETOOBIG;
+  int lane = -1;
+  for (size_t k = 0; k < srv->lanes.size(); ++k)
+    if (n <= srv->lane_max[k] && n <= srv->lanes[k]->arena_cap) {
+      lane = int(k);
+      break;
+    }
+  if (lane < 0) return SA_ETOOBIG;
+  u64 t;
+  {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    t = srv->next_ticket++;
+    srv->owner[t] = lane;
   }
-  std::lock_guard<std::mutex> lk(srv->mu);
-  const u64 t = srv->next_ticket++;
-  if (n == 0) {
-    r->state = 2;
-    r->t_admit = r->t_done = r->t_arrive;
-    srv->completed += 1;
-  } else {
-    srv->queue.push_back(t);
+  sa_status st = lane_submit(srv->lanes[lane].get(), t, h_text, n);
+  if (st != SA_OK) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->owner.erase(t);
+    return st;
   }
-  srv->reqs[t] = std::move(r);
   *ticket = t;
-  srv->cv.notify_all();
   return SA_OK;
 }
 
@@ -565,50 +763,37 @@ sa_status sa_server_poll(sa_server* srv, uint64_t ticket, uint32_t* h_sa_out, in
                          double* latency_ms) {
   if (!srv || !done) return SA_EINVAL;
   *done = 0;
-  Request* r = nullptr;
+  int lane;
   {
     std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->reqs.find(ticket);
-    if (it == srv->reqs.end()) return SA_EINVAL;
-    r = it->second.get();
-    if (r->state == 3) {
-      const sa_status e = r->err;
-      srv->reqs.erase(it);
-      return e;
-    }
-    if (r->state != 2) return SA_OK;
-    if (r->n && !h_sa_out) return SA_EINVAL;
-    r->state = 4;
+    auto it = srv->owner.find(ticket);
+    if (it == srv->owner.end()) return SA_EINVAL;
+    lane = it->second;
   }
-  sa_status st = SA_OK;
-  if (r->n) {
-    if (hipSetDevice(srv->device) != hipSuccess ||
-        hipMemcpy(h_sa_out, srv->d_sa + r->base, r->n * sizeof(u32), hipMemcpyDeviceToHost) !=
-            hipSuccess)
-      st = SA_EDEVICE;
+  bool released = false;
+  sa_status st = lane_poll(srv->lanes[lane].get(), ticket, h_sa_out, done, latency_ms, &released);
+  if (released) {
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->owner.erase(ticket);
   }
-  std::lock_guard<std::mutex> lk(srv->mu);
-  if (latency_ms) *latency_ms = (r->t_done - r->t_arrive) * 1e3;
-  srv->release(r->base, r->n);
-  srv->reqs.erase(ticket);
-  srv->cv.notify_all();
-  if (st == SA_OK) *done = 1;
   return st;
 }
 
 sa_status sa_server_stats(sa_server* srv, sa_server_stats_t* out) {
   if (!srv || !out) return SA_EINVAL;
-  std::lock_guard<std::mutex> lk(srv->mu);
   std::memset(out, 0, sizeof(*out));
-  out->completed = srv->completed;
-  out->failed = srv->failed;
-  out->suffixes = srv->suffixes;
-  out->rounds = srv->rounds;
-  out->busy_ms = srv->busy_s * 1e3;
-  out->queued = srv->queue.size();
-  out->running = srv->eng.live.size();
-  out->slots = srv->eng.slots;
-  out->arena_positions = srv->arena_cap;
+  for (auto& L : srv->lanes) {
+    std::lock_guard<std::mutex> lk(L->mu);
+    out->completed += L->completed;
+    out->failed += L->failed;
+    out->suffixes += L->suffixes;
+    out->rounds += L->rounds;
+    out->busy_ms += L->busy_s * 1e3;
+    out->queued += L->queue.size();
+    out->running += L->eng.live.size();
+    out->slots += L->eng.slots;
+    out->arena_positions += L->arena_cap;
+  }
   return SA_OK;
 }
 

@@ -181,27 +181,59 @@ void launch_set_zero_u32(u32* p, hipStream_t s) {
 // to compare below every character) and a round-0 key holds as many
 // characters as fit in 64 bits.
 
+// The set of byte values a lane has seen, as four 64-bit masks in registers:
+// adding a byte costs a few ALU operations and no memory traffic, where a store
+// into a shared LDS table serialises on the few addresses a small alphabet
+// hits.
+struct ByteSet {
+  u64 m0 = 0, m1 = 0, m2 = 0, m3 = 0;
+  __device__ inline void add(u32 b) {
+    const u64 bit = u64(1) << (b & 63u);
+    const u32 hi = b >> 6;
+    m0 |= hi == 0 ? bit : 0;
+    m1 |= hi == 1 ? bit : 0;
+    m2 |= hi == 2 ? bit : 0;
+    m3 |= hi == 3 ? bit : 0;
+  }
+  __device__ inline void add_word(u32 w) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) add((w >> (8 * k)) & 0xFFu);
+  }
+  // ORs the sets of the wave's lanes and merges the union into an 8-word LDS
+  // bitmap. Every lane of the wave must call it.
+  __device__ inline void flush(u32* lds8) const {
+    const u64 m[4] = {m0, m1, m2, m3};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      u32 v = u32(m[k >> 1] >> (32 * (k & 1)));
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
+      if ((threadIdx.x & 63) == 0 && v) atomicOr(&lds8[k], v);
+    }
+  }
+};
+
 __global__ __launch_bounds__(256) void byte_presence_kernel(const u8* __restrict__ text, u64 n,
                                                             int vec_ok, u32* __restrict__ present) {
-  __shared__ u32 seen[256];
-  seen[threadIdx.x] = 0;
+  __shared__ u32 seen[8];
+  if (threadIdx.x < 8) seen[threadIdx.x] = 0;
   __syncthreads();
+  ByteSet bs;
   const u64 nvec = vec_ok ? n / 16 : 0;
   const uint4* v = reinterpret_cast<const uint4*>(text);
   u64 stride = u64(gridDim.x) * blockDim.x;
   for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < nvec; i += stride) {
-    uint4 w = v[i];
-    u32 words[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-#pragma unroll
-      for (int b = 0; b < 4; ++b) seen[(words[q] >> (8 * b)) & 0xFF] = 1;
-    }
+    const uint4 w = v[i];
+    bs.add_word(w.x);
+    bs.add_word(w.y);
+    bs.add_word(w.z);
+    bs.add_word(w.w);
   }
   for (u64 i = nvec * 16 + u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    seen[text[i]] = 1;
+    bs.add(text[i]);
+  bs.flush(seen);
   __syncthreads();
-  if (seen[threadIdx.x]) atomicOr(&present[threadIdx.x], 1u);
+  if ((seen[threadIdx.x >> 5] >> (threadIdx.x & 31)) & 1u) atomicOr(&present[threadIdx.x], 1u);
 }
 
 void launch_byte_presence(const u8* text, u64 n, u32* present, hipStream_t s) {
@@ -1117,46 +1149,61 @@ __device__ inline u32 new_text_of(const u64* __restrict__ chunk0, u32 m, u64 b) 
 
 }  // namespace
 
+// Each workgroup scans a contiguous range of chunks (chunks of one text are
+// consecutive), accumulating the bytes seen in LDS and flushing them into the
+// text's bitmap whenever the text changes.
 __global__ __launch_bounds__(256) void multi_presence_kernel(const u8* __restrict__ arena,
-                                                             TextTab tab, NewList nl) {
-  __shared__ u32 seen[256];
-  seen[threadIdx.x] = 0;
-  __syncthreads();
-  const u64 b = blockIdx.x;
-  const u32 i = new_text_of(nl.chunk0, nl.m, b);
-  const u32 t = nl.t[i];
-  const u64 start = (b - nl.chunk0[i]) * kNewChunk;
-  const u64 len = tab.len[t];
-  const u64 end = (start + kNewChunk < len) ? start + kNewChunk : len;
-  // Absolute byte range [lo, hi) of the chunk: 16-byte words inside it, single
-  // bytes at the unaligned ends.
-  const u64 lo = tab.base[t] + start, hi = tab.base[t] + end;
-  const u64 alo = (lo + 15) & ~u64(15), ahi = hi & ~u64(15);
-  if (alo < ahi) {
+                                                             TextTab tab, NewList nl,
+                                                             u64 per_block) {
+  __shared__ u32 seen[8];
+  const u64 b0 = u64(blockIdx.x) * per_block;
+  u64 b1 = b0 + per_block;
+  if (b1 > nl.chunks) b1 = nl.chunks;
+  if (b0 >= b1) return;
+  u32 i = new_text_of(nl.chunk0, nl.m, b0);
+  u64 b = b0;
+  while (b < b1) {
+    while (i + 1 < nl.m && nl.chunk0[i + 1] <= b) ++i;
+    const u32 t = nl.t[i];
+    const u64 bend = (nl.chunk0[i + 1] < b1) ? nl.chunk0[i + 1] : b1;  // this text's chunks
+    if (threadIdx.x < 8) seen[threadIdx.x] = 0;
+    __syncthreads();
+    const u64 len = tab.len[t];
+    const u64 start = (b - nl.chunk0[i]) * kNewChunk;
+    u64 end = (bend - nl.chunk0[i]) * kNewChunk;
+    if (end > len) end = len;
+    // Absolute byte range: 16-byte words inside, single bytes at the ends.
+    const u64 lo = tab.base[t] + start, hi = tab.base[t] + end;
+    u64 alo = (lo + 15) & ~u64(15), ahi = hi & ~u64(15);
+    if (alo > ahi) alo = ahi = hi;
+    ByteSet bs;
     const uint4* v = reinterpret_cast<const uint4*>(arena + alo);
     const u64 words = (ahi - alo) / 16;
     for (u64 q = threadIdx.x; q < words; q += 256) {
       const uint4 w = v[q];
-      const u32 ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-#pragma unroll
-        for (int by = 0; by < 4; ++by) seen[(ws[k] >> (8 * by)) & 0xFFu] = 1;
-      }
+      bs.add_word(w.x);
+      bs.add_word(w.y);
+      bs.add_word(w.z);
+      bs.add_word(w.w);
     }
-    for (u64 q = lo + threadIdx.x; q < alo; q += 256) seen[arena[q]] = 1;
-    for (u64 q = ahi + threadIdx.x; q < hi; q += 256) seen[arena[q]] = 1;
-  } else {
-    for (u64 q = lo + threadIdx.x; q < hi; q += 256) seen[arena[q]] = 1;
+    for (u64 q = lo + threadIdx.x; q < alo; q += 256) bs.add(arena[q]);
+    for (u64 q = ahi + threadIdx.x; q < hi; q += 256) bs.add(arena[q]);
+    bs.flush(seen);
+    __syncthreads();
+    if (threadIdx.x < 8 && seen[threadIdx.x])
+      atomicOr(&tab.present[t * 8 + threadIdx.x], seen[threadIdx.x]);
+    __syncthreads();
+    b = bend;
   }
-  __syncthreads();
-  if (seen[threadIdx.x])
-    atomicOr(&tab.present[t * 8 + threadIdx.x / 32], 1u << (threadIdx.x % 32));
 }
 
 void launch_multi_presence(const u8* arena, TextTab tab, NewList nl, hipStream_t s) {
   if (nl.chunks == 0) return;
-  hipLaunchKernelGGL(multi_presence_kernel, dim3(u32(nl.chunks)), dim3(256), 0, s, arena, tab, nl);
+  u64 blocks = nl.chunks < 2048 ? nl.chunks : 2048;
+  const u64 per = ceil_div(nl.chunks, blocks);
+  blocks = ceil_div(nl.chunks, per);
+  hipLaunchKernelGGL(multi_presence_kernel, dim3(u32(blocks)), dim3(256), 0, s, arena, tab, nl,
+                     per);
 }
 
 __global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList nl, int idbits,
@@ -1189,6 +1236,12 @@ __global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList n
         const u32 ct = (full - u32(idbits)) / w;
         if (ct >= 1) c = ct;
       }
+    }
+    // A full 64-bit key costs an eighth sweep; drop characters to stay within
+    // seven digits while at least 12 remain (an alphabet of at most 7 symbols).
+    if (trim && u32(idbits) + c * w > 56 && 56 > u32(idbits)) {
+      const u32 ct = (56 - u32(idbits)) / w;
+      if (ct >= 12) c = ct;
     }
     tab.wc[t] = w | (c << 16);
   }
