@@ -290,6 +290,29 @@ def serve_main(args) -> int:
     return 0
 
 
+def tune_main(args) -> int:
+    """Autotunes each listed workload (one text, or the batch) and writes the
+    cache table; one progress line per workload."""
+    import torch
+
+    from paper_1610_03007_amd import SuffixArrayBuilder
+    dev = torch.device("cuda", 0)
+    b = SuffixArrayBuilder(0, tune_cache=args.tune)
+    for name in [w for w in args.tune_workloads.split(",") if w]:
+        t0 = time.perf_counter()
+        text, offsets = make_text(name)
+        d_text = torch.from_numpy(text).to(dev)
+        best, ms = b.tune(d_text, offsets, reps=args.tune_reps)
+        b.save_tuning()
+        print(json.dumps({"tune": name, "n": int(text.size), "best": best, "ms": round(ms, 3),
+                          "msuffixes_s": round(text.size / ms / 1e3, 1),
+                          "wall_s": round(time.perf_counter() - t0, 1)}), flush=True)
+        del d_text
+        torch.cuda.empty_cache()
+    b.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,6 +326,11 @@ def main() -> int:
                     help="radix-sort items per thread (0 = library default)")
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the replayed request stream (serve workload)")
+    ap.add_argument("--tune", metavar="OUT_JSON", default="",
+                    help="run the autotuner on --tune-workloads and write the cache table "
+                         "to OUT_JSON instead of benchmarking")
+    ap.add_argument("--tune-workloads", default="dna_1m,markov_256m,repetitive_1g,batch_4096")
+    ap.add_argument("--tune-reps", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="MiB of a plain device copy to run after the steps (counter calibration)")
     args = ap.parse_args()
@@ -315,6 +343,8 @@ def main() -> int:
 
     if args.workload == "serve":
         return serve_main(args)
+    if args.tune:
+        return tune_main(args)
 
     import numpy as np
     import torch
@@ -394,6 +424,7 @@ def main() -> int:
             "chars_round0": info["chars0"],
             "parallelism": "single GPU",
             "tuning": b.tuning(),
+            "tuning_source": b.tuning_source(),
         },
         "roofline": {
             "bound": "hbm",

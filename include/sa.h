@@ -47,7 +47,9 @@ typedef struct sa_ctx sa_ctx;
 
 /* Creates a context on HIP device `device`. The workspace grows on demand and
  * is kept for later calls. tune_cache_json: optional path of a tuning cache
- * (may be NULL). */
+ * (may be NULL). The file is read once here; a missing file is an empty cache,
+ * a malformed one gives SA_EINVAL. Builds without an explicit tuning take
+ * their knobs from the cache entry that matches the input (see sa_tune). */
 sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json);
 
 /* Frees the context and its device workspace. NULL is accepted. */
@@ -177,8 +179,44 @@ typedef struct {
                                (0 = what one CU holds for the tile shape; at most 16) */
   uint32_t reserved[4];  /* must be zero */
 } sa_tuning;
+/* Sets an explicit tuning, used by every later build of the context. t = NULL
+ * goes back to automatic choice: the cache entry for each input, else the
+ * defaults. */
 sa_status sa_ctx_set_tuning(sa_ctx* ctx, const sa_tuning* t);
+/* The knobs of the last build (or the explicit tuning, or the defaults). */
 sa_status sa_ctx_get_tuning(const sa_ctx* ctx, sa_tuning* out);
+/* Where the last build's knobs came from: 0 defaults, 1 the tuning cache,
+ * 2 an explicit sa_ctx_set_tuning. */
+sa_status sa_ctx_tuning_source(const sa_ctx* ctx, int* source);
+
+/* Autotuner. Times candidate tunings on the caller's input and records the
+ * fastest in the context's cache table, keyed by (GPU architecture, mode,
+ * floor(log2 of the total length), bits per character code of the input):
+ *   stage 1: sort_items in {8, 12, 16, 20, 24} x sort_wgs_per_cu in
+ *            {default, 1, 2, 3, 4, 6, 8};
+ *   stage 2: round0_full flipped; stage 3: lazy_ratio in {3, 4, 8, 16, 64}.
+ * Each candidate is one warm-up build plus the best of `reps` timed builds
+ * (0 = 3) on `stream`, measured with HIP events. d_texts / h_offsets /
+ * num_texts / d_sas are as sa_build_batch (num_texts = 1 tunes sa_build,
+ * mode "single"; more tunes the batched build, mode "batch"). d_sas receives
+ * a valid result. *best_out (may be NULL) gets the winner, *best_ms (may be
+ * NULL) its time. The caller's explicit tuning, if any, stays in force.
+ * A later build finds the entry when it has the same architecture and mode, a
+ * size within two binary orders of magnitude (nearest first) and, for
+ * sa_build, the nearest code width to bits(sigma hint) (a hint of 256 matches
+ * any width). */
+sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets,
+                  uint32_t num_texts, uint32_t* d_sas, void* stream, uint32_t reps,
+                  sa_tuning* best_out, double* best_ms);
+/* Writes the context's cache table as JSON to `path` (NULL: the path given to
+ * sa_ctx_create). The file is replaced atomically. */
+sa_status sa_tune_save(const sa_ctx* ctx, const char* path);
+/* Host-only lookup in a cache file (no device needed): the tuning a build of
+ * n bytes in `mode` ("single" or "batch") on `arch` (e.g. "gfx950") with
+ * code_bits bits per character (0: any) would take; *found = 0 and the
+ * defaults when no entry matches. A missing file is an empty cache. */
+sa_status sa_tune_lookup(const char* path, const char* arch, const char* mode, uint64_t n,
+                         uint32_t code_bits, sa_tuning* out, int* found);
 
 /* Device workspace a context needs for a text of n bytes. */
 size_t sa_workspace_bytes(uint64_t n);

@@ -14,6 +14,7 @@ library's kernels on the tensor's device and the current stream.
 from __future__ import annotations
 
 import ctypes
+import os
 
 import torch
 
@@ -21,6 +22,11 @@ from . import _native
 from ._native import SAError, check
 
 __all__ = ["SuffixArrayBuilder", "SuffixArrayServer", "SAError", "workspace_bytes"]
+
+
+# Tuning cache shipped with the package: entries found by the autotuner on
+# MI355X for the standard workload sizes. Builders use it unless told otherwise.
+DEFAULT_TUNE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
 
 def _stream_handle(device: torch.device):
@@ -33,9 +39,15 @@ def workspace_bytes(n: int) -> int:
 
 
 class SuffixArrayBuilder:
-    """Owns a library context (device workspace, kernel statistics) on one GPU."""
+    """Owns a library context (device workspace, kernel statistics) on one GPU.
+
+    ``tune_cache``: path of a tuning cache (JSON); None takes the package's
+    cache when present, "" none (library defaults)."""
 
     def __init__(self, device: int | torch.device | None = None, tune_cache: str | None = None):
+        if tune_cache is None:
+            tune_cache = DEFAULT_TUNE_CACHE if os.path.exists(DEFAULT_TUNE_CACHE) else ""
+        self.tune_cache = tune_cache or None
         if device is None:
             device = torch.cuda.current_device()
         self.device = torch.device("cuda", device if isinstance(device, int) else device.index)
@@ -148,22 +160,56 @@ class SuffixArrayBuilder:
               "sa_ctx_set_isa_mode")
 
     def tuning(self) -> dict:
+        """The knobs of the last build (or the explicit tuning, or the defaults)."""
         t = _native.Tuning()
         check(self._lib.sa_ctx_get_tuning(self._ctx, ctypes.byref(t)), "sa_ctx_get_tuning")
-        return {"sort_items": int(t.sort_items), "lazy_ratio": int(t.lazy_ratio),
-                "round0_full": int(t.round0_full), "sort_wgs_per_cu": int(t.sort_wgs_per_cu)}
+        return _native.tuning_dict(t)
+
+    def tuning_source(self) -> str:
+        """Where the last build's knobs came from: 'default', 'cache' or 'explicit'."""
+        v = ctypes.c_int(0)
+        check(self._lib.sa_ctx_tuning_source(self._ctx, ctypes.byref(v)), "sa_ctx_tuning_source")
+        return ("default", "cache", "explicit")[v.value]
 
     def set_tuning(self, **kw) -> None:
         """Set tuning knobs (sort_items, lazy_ratio, round0_full, sort_wgs_per_cu);
-        results never change."""
+        results never change. Unset knobs keep their current values."""
         cur = self.tuning()
         unknown = set(kw) - set(cur)
         if unknown:
             raise ValueError(f"unknown tuning knobs {sorted(unknown)}")
         cur.update(kw)
-        t = _native.Tuning(sort_items=cur["sort_items"], lazy_ratio=cur["lazy_ratio"],
-                           round0_full=cur["round0_full"], sort_wgs_per_cu=cur["sort_wgs_per_cu"])
+        t = _native.Tuning(**cur)
         check(self._lib.sa_ctx_set_tuning(self._ctx, ctypes.byref(t)), "sa_ctx_set_tuning")
+
+    def auto_tuning(self) -> None:
+        """Drop an explicit tuning: builds take the cache entry for their input,
+        else the defaults."""
+        check(self._lib.sa_ctx_set_tuning(self._ctx, None), "sa_ctx_set_tuning")
+
+    def tune(self, texts: torch.Tensor, offsets=None, reps: int = 3):
+        """Autotune on this input (one text, or a batch with ``offsets``): records
+        the fastest tuning in the context's cache table and returns
+        (tuning dict, best build ms). ``save_tuning`` writes the table."""
+        import numpy as np
+        t = self._text(texts)
+        off = np.ascontiguousarray(np.asarray([0, t.numel()] if offsets is None else offsets,
+                                              dtype=np.uint64))
+        if off.ndim != 1 or off.size < 2 or int(off[-1]) != t.numel():
+            raise ValueError("offsets must hold num_texts + 1 boundaries ending at the length")
+        sa = torch.empty(t.numel(), dtype=torch.int32, device=self.device)
+        best = _native.Tuning()
+        ms = ctypes.c_double(0)
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_tune(self._ctx, ctypes.c_void_p(t.data_ptr()),
+                                    off.ctypes.data_as(ctypes.c_void_p), off.size - 1,
+                                    ctypes.c_void_p(sa.data_ptr()), _stream_handle(self.device),
+                                    reps, ctypes.byref(best), ctypes.byref(ms)), "sa_tune")
+        return _native.tuning_dict(best), float(ms.value)
+
+    def save_tuning(self, path: str | None = None) -> None:
+        """Write the cache table as JSON (default: the tune_cache path)."""
+        check(self._lib.sa_tune_save(self._ctx, path.encode() if path else None), "sa_tune_save")
 
     def set_trace(self, on: bool = True) -> None:
         check(self._lib.sa_ctx_set_trace(self._ctx, 1 if on else 0), "sa_ctx_set_trace")

@@ -31,7 +31,8 @@ EXPORTED = [
     "sa_ctx_create", "sa_ctx_destroy", "sa_build", "sa_build_batch", "sa_last_build_info",
     "sa_build_rounds",
     "sa_radix_sort_pairs", "sa_workspace_bytes", "sa_ctx_set_trace", "sa_ctx_reset_stats",
-    "sa_ctx_set_isa_mode", "sa_ctx_set_tuning", "sa_ctx_get_tuning",
+    "sa_ctx_set_isa_mode", "sa_ctx_set_tuning", "sa_ctx_get_tuning", "sa_ctx_tuning_source",
+    "sa_tune", "sa_tune_save", "sa_tune_lookup",
     "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll",
     "sa_server_stats",
     "sa_ctx_get_kernel_stats", "sa_strerror",
@@ -72,6 +73,22 @@ class Tuning(ctypes.Structure):
                 ("reserved", ctypes.c_uint32 * 4)]
 
 
+TUNING_KNOBS = ("sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu")
+
+
+def tuning_dict(t: "Tuning") -> dict:
+    return {k: int(getattr(t, k)) for k in TUNING_KNOBS}
+
+
+def tune_lookup(path: str, arch: str, mode: str, n: int, code_bits: int = 0):
+    """(found, tuning dict) a build would take from the cache file at ``path``."""
+    t = Tuning()
+    found = ctypes.c_int(0)
+    check(lib().sa_tune_lookup(path.encode(), arch.encode(), mode.encode(), n, code_bits,
+                               ctypes.byref(t), ctypes.byref(found)), "sa_tune_lookup")
+    return bool(found.value), tuning_dict(t)
+
+
 class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
                 ("suffixes", ctypes.c_uint64), ("rounds", ctypes.c_uint64),
@@ -109,6 +126,12 @@ def _declare(lib: ctypes.CDLL) -> None:
         "sa_ctx_set_isa_mode": ([vp, i32], i32),
         "sa_ctx_set_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
         "sa_ctx_get_tuning": ([vp, ctypes.POINTER(Tuning)], i32),
+        "sa_ctx_tuning_source": ([vp, ctypes.POINTER(i32)], i32),
+        "sa_tune": ([vp, vp, vp, u32, vp, vp, u32, ctypes.POINTER(Tuning),
+                     ctypes.POINTER(ctypes.c_double)], i32),
+        "sa_tune_save": ([vp, ctypes.c_char_p], i32),
+        "sa_tune_lookup": ([ctypes.c_char_p, ctypes.c_char_p, ctypes.c_char_p, u64, u32,
+                            ctypes.POINTER(Tuning), ctypes.POINTER(i32)], i32),
         "sa_ctx_reset_stats": ([vp], i32),
         "sa_ctx_get_kernel_stats": ([vp, i32, ctypes.POINTER(KernelStats)], i32),
         "sa_strerror": ([i32], ctypes.c_char_p),

@@ -84,8 +84,8 @@ constexpr int kRerankTile = kRerankBlock * kRerankItems;  // 4096 elements
 // Device-side 64-bit counters shared by one build (slot indices).
 enum CounterSlot : int {
   kCtrSortTiles = 0,                 // kMaxPasses slots: tile tickets per pass
-  kCtrRerankTiles = kMaxPasses,      // tile tickets of the re-rank kernel
-  kCtrActive = kMaxPasses + 1,       // survivors written by the last re-rank
+  kCtrRerankTiles = kMaxPasses,      // spare (cleared with the sort tickets)
+  kCtrActive = kMaxPasses + 1,       // survivors written by the last re-rank (atomic sum)
   kCtrError = kMaxPasses + 2,        // error bits (kErr*)
   kCtrSigma = kMaxPasses + 3,        // distinct bytes in the text
   kCtrCodeBits = kMaxPasses + 4,     // w: bits per character code

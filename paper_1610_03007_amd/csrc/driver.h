@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/sa.h"
@@ -17,6 +18,20 @@ using namespace sa;
 // round 0 (each later gather may then cost a binary search instead of every
 // suffix costing a random 4-byte write).
 constexpr u64 kLazyRatioDefault = 8;
+
+// Tuning cache: one entry per (architecture, mode, log2 size, code bits).
+constexpr const char* kTuneFormat = "sa_mi355x_tune/1";
+struct TuneEntry {
+  std::string arch;  // e.g. "gfx950"
+  std::string mode;  // "single" or "batch"
+  u32 log2n = 0;     // floor(log2 of the text or batch length)
+  u32 code_bits = 0; // bits per character code of the tuned input (0: any)
+  sa_tuning t{};
+  double ms = 0;     // build time of the winner when tuned
+};
+struct TuneTable {
+  std::vector<TuneEntry> entries;
+};
 
 struct TraceRec {
   hipEvent_t start, stop;
@@ -42,8 +57,6 @@ struct sa_ctx {
   u64* toff = nullptr;    // batch text offsets on the device
   u64 toff_cap = 0;
   u64* status = nullptr;  // sort look-back: [tiles][kRadix]
-  u64* st3 = nullptr;     // re-rank look-back: 3 x [tiles]
-  u64 rr_tiles_cap = 0;
   // Small control block: hist_in | hist_run | tickets | counters | plan | present | code.
   void* small = nullptr;
   u32* hist_in = nullptr;   // [kMaxPasses][kChunks][kRadix] input-order chunk histograms
@@ -63,6 +76,15 @@ struct sa_ctx {
   int num_cus = 256;
   u64 lazy_ratio = kLazyRatioDefault;
   int round0_trim = 1;  // round-0 keys fill whole radix digits
+  // Tuning: an explicit choice from sa_ctx_set_tuning wins; otherwise each
+  // build looks its input up in the cache table (defaults when absent).
+  bool tuning_explicit = false;
+  sa_tuning explicit_tuning{};
+  TuneTable* tune = nullptr;
+  std::string tune_path;
+  std::string arch;         // architecture name without feature suffixes
+  u32 sigma_hint = 0;       // alphabet hint of the current sa_build (0: none)
+  int tuned_from_cache = 0; // 1 if the last build took its knobs from the table
   bool trace = false;
   std::vector<TraceRec> recs;
   std::vector<hipEvent_t> event_pool;
@@ -96,7 +118,6 @@ bool dev_alloc(T** p, u64 count) {
 }
 
 u64 sort_status_words(u64 cap);
-u64 rerank_tiles(u64 cap);
 int bits_of(u64 v);
 void free_workspace(sa_ctx* c);
 sa_status ensure_workspace(sa_ctx* c, u64 n);
@@ -157,5 +178,15 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
                        hipStream_t s);
 // Settles trace records after a build: collected on success, dropped on error.
 void settle_trace(sa_ctx* c, sa_status st);
+sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d_sa,
+                           hipStream_t s);
+
+// Tuning (tune.hip).
+bool tuning_valid(const sa_tuning& t);
+sa_tuning default_tuning();
+void apply_tuning(sa_ctx* c, const sa_tuning& t);
+sa_tuning current_tuning(const sa_ctx* c);
+sa_status tune_load(const char* path, TuneTable& out);
+void resolve_tuning(sa_ctx* c, const char* mode, u64 n, u32 code_bits);
 
 }  // namespace drv

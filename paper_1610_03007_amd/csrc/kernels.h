@@ -87,8 +87,7 @@ struct RerankArgs {
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            const u32* valsB, const SortPlan* plan, const RerankArgs& args,
                            u32* isa, u32* sa_out, u32* act_idx, u64* act_ti, u32* act_rank,
-                           u64* st_head, u64* st_grp, u64* st_surv, u64* counters, u32 gen,
-                           hipStream_t s);
+                           u64* counters, hipStream_t s);
 
 // ISA after round 0. Eager: ISA[vals[p]] = ranks[p] over the sorted pairs (the
 // ranks written by the re-rank with kRerankWriteRanks). Lazy: ISA cleared,

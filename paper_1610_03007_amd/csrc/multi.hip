@@ -235,10 +235,10 @@ struct sa_batch_state {
   Engine eng;
 };
 
-namespace {
+namespace drv {
 
-sa_status build_batch(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d_sa,
-                      hipStream_t s) {
+sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d_sa,
+                           hipStream_t s) {
   std::memset(&c->info, 0, sizeof(c->info));
   if (!h_off || T == 0) return SA_EINVAL;
   if (h_off[0] != 0) return SA_EINVAL;
@@ -257,6 +257,7 @@ sa_status build_batch(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d
   const int B = bits_of(max_n);
   if (idbits + 2 * B > 64) return SA_ETOOBIG;
   if (hipSetDevice(c->device) != hipSuccess) return SA_EDEVICE;
+  resolve_tuning(c, "batch", N, 0);
   sa_status st = ensure_workspace(c, N);
   if (st != SA_OK) return st;
   if (c->act_ti_cap < c->cap) {
@@ -297,14 +298,14 @@ sa_status build_batch(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d
   return SA_OK;
 }
 
-}  // namespace
+}  // namespace drv
 
 extern "C" sa_status sa_build_batch(sa_ctx* ctx, const uint8_t* d_texts,
                                     const uint64_t* h_offsets, uint32_t num_texts,
                                     uint32_t* d_sas, void* stream) {
   if (!ctx) return SA_EINVAL;
-  sa_status st = build_batch(ctx, d_texts, h_offsets, num_texts, d_sas,
-                             static_cast<hipStream_t>(stream));
+  sa_status st = build_batch_impl(ctx, d_texts, h_offsets, num_texts, d_sas,
+                                  static_cast<hipStream_t>(stream));
   settle_trace(ctx, st);
   return st;
 }

@@ -12,7 +12,6 @@
 namespace drv {
 
 u64 sort_status_words(u64 cap) { return ceil_div(cap, kSortTileMin) * kRadix; }
-u64 rerank_tiles(u64 cap) { return ceil_div(cap, kRerankTile); }
 
 int bits_of(u64 v) { return v == 0 ? 0 : 64 - __builtin_clzll(v); }
 
@@ -25,15 +24,13 @@ void free_workspace(sa_ctx* c) {
   (void)hipFree(c->act_idx);
   (void)hipFree(c->act_rank);
   (void)hipFree(c->status);
-  (void)hipFree(c->st3);
   (void)hipFree(c->act_ti);
   c->act_ti = nullptr;
   c->act_ti_cap = 0;
   c->keysA = c->keysB = nullptr;
   c->valsA = c->valsB = c->isa = c->act_idx = c->act_rank = nullptr;
-  c->status = c->st3 = nullptr;
+  c->status = nullptr;
   c->cap = 0;
-  c->rr_tiles_cap = 0;
 }
 
 sa_status ensure_workspace(sa_ctx* c, u64 n) {
@@ -42,32 +39,28 @@ sa_status ensure_workspace(sa_ctx* c, u64 n) {
   u64 cap = std::max<u64>(n, 1 << 16);
   bool ok = dev_alloc(&c->keysA, cap) && dev_alloc(&c->keysB, cap) && dev_alloc(&c->valsA, cap) &&
             dev_alloc(&c->valsB, cap) && dev_alloc(&c->isa, cap) && dev_alloc(&c->act_idx, cap) &&
-            dev_alloc(&c->act_rank, cap) && dev_alloc(&c->status, sort_status_words(cap)) &&
-            dev_alloc(&c->st3, 3 * rerank_tiles(cap));
+            dev_alloc(&c->act_rank, cap) && dev_alloc(&c->status, sort_status_words(cap));
   if (!ok) {
     free_workspace(c);
     return SA_ENOMEM;
   }
-  // Status arrays start cleared; generations then keep them valid without
+  // The status array starts cleared; generations then keep it valid without
   // further clearing.
   if (hipMemset(c->status, 0, sort_status_words(cap) * sizeof(u64)) != hipSuccess ||
-      hipMemset(c->st3, 0, 3 * rerank_tiles(cap) * sizeof(u64)) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     free_workspace(c);
     return SA_EDEVICE;
   }
   c->cap = cap;
-  c->rr_tiles_cap = rerank_tiles(cap);
   c->gen = 0;
   return SA_OK;
 }
 
-// Next look-back generation; clears the status arrays when the 22-bit counter
+// Next look-back generation; clears the status array when the 22-bit counter
 // wraps.
 u32 next_gen(sa_ctx* c, hipStream_t s) {
   if (c->gen + 1 >= kGenMask) {
     launch_fill_u64(c->status, sort_status_words(c->cap), 0, s);
-    launch_fill_u64(c->st3, 3 * c->rr_tiles_cap, 0, s);
     c->gen = 0;
   }
   return ++c->gen;
@@ -142,9 +135,9 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
   const SortGeom geo = make_geom(count, c->sort_items);
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    // Chunk histograms and tickets; the re-rank ticket counter.
+    // Chunk histograms and tickets; the survivor count the re-rank adds to.
     launch_fill_u32(c->hist_in, 2 * kChunkHistWords + kTicketWords, 0, s);
-    launch_fill_u64(c->counters, kCtrRerankTiles + 1, 0, s);
+    launch_fill_u64(c->counters, kCtrActive + 1, 0, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_HISTOGRAM, double(count) * 8.0);
@@ -169,15 +162,13 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
 }
 
 void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s) {
-  u32 gen = next_gen(c, s);
   const double count = double(args.count);
   double bytes = count * 16.0 + ((args.mode & kRerankWriteRanks) ? 4.0 * count : 0.0) -
                  ((args.mode & kRerankScatterIsa) ? 0.0 : 4.0 * count);
   Tracer t(c, s, SA_KERNEL_RERANK, bytes);
-  const u64 rt = c->rr_tiles_cap;
   launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->isa, d_sa,
                         args.tbase ? nullptr : c->act_idx, args.tbase ? c->act_ti : nullptr,
-                        c->act_rank, c->st3, c->st3 + rt, c->st3 + 2 * rt, c->counters, gen, s);
+                        c->act_rank, c->counters, s);
 }
 
 // Re-rank arguments of a single text: round 0 (one group, every rank 1) or a
@@ -226,6 +217,8 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   if (!text || !d_sa) return SA_EINVAL;
   if (n >= (u64(1) << 32)) return SA_ETOOBIG;
   if (hipSetDevice(c->device) != hipSuccess) return SA_EDEVICE;
+  resolve_tuning(c, "single", n,
+                 c->sigma_hint && c->sigma_hint < 256 ? u32(bits_of(c->sigma_hint)) : 0);
   sa_status st = ensure_workspace(c, n);
   if (st != SA_OK) return st;
 
@@ -360,7 +353,6 @@ using namespace drv;
 extern "C" {
 
 sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
-  (void)tune_cache_json;
   if (!out) return SA_EINVAL;
   *out = nullptr;
   int ndev = 0;
@@ -378,6 +370,26 @@ sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
     c->num_cus = cus;
   std::memset(c->stats, 0, sizeof(c->stats));
   std::memset(&c->info, 0, sizeof(c->info));
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->arch = prop.gcnArchName;
+    const size_t colon = c->arch.find(':');
+    if (colon != std::string::npos) c->arch.resize(colon);
+  }
+  if (tune_cache_json && tune_cache_json[0]) {
+    c->tune = new (std::nothrow) TuneTable();
+    if (!c->tune) {
+      delete c;
+      return SA_ENOMEM;
+    }
+    c->tune_path = tune_cache_json;
+    const sa_status ts = tune_load(tune_cache_json, *c->tune);
+    if (ts != SA_OK) {
+      delete c->tune;
+      delete c;
+      return ts;
+    }
+  }
   if (hipMalloc(&c->small, kSmallBytes) != hipSuccess) {
     delete c;
     return SA_ENOMEM;
@@ -410,6 +422,7 @@ sa_status sa_ctx_destroy(sa_ctx* ctx) {
   if (ctx->h_plans) (void)hipHostFree(ctx->h_plans);
   (void)hipFree(ctx->toff);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
+  delete ctx->tune;
   delete ctx;
   return SA_OK;
 }
@@ -418,7 +431,11 @@ sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigm
                    void* stream) {
   if (!ctx) return SA_EINVAL;
   if (sigma == 0 || sigma > 256) return SA_EINVAL;
-  return build_impl(ctx, d_text, n, 0, d_sa, nullptr, static_cast<hipStream_t>(stream));
+  ctx->sigma_hint = sigma;
+  const sa_status st =
+      build_impl(ctx, d_text, n, 0, d_sa, nullptr, static_cast<hipStream_t>(stream));
+  ctx->sigma_hint = 0;
+  return st;
 }
 
 sa_status sa_build_rounds(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t max_rounds,
@@ -472,7 +489,7 @@ sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, u
 
 size_t sa_workspace_bytes(uint64_t n) {
   u64 cap = std::max<u64>(n, 1 << 16);
-  return size_t(cap) * (2 * 8 + 5 * 4) + sort_status_words(cap) * 8 + 3 * rerank_tiles(cap) * 8 +
+  return size_t(cap) * (2 * 8 + 5 * 4) + sort_status_words(cap) * 8 +
          kSmallBytes;
 }
 
@@ -489,28 +506,28 @@ sa_status sa_ctx_set_isa_mode(sa_ctx* ctx, int mode) {
 }
 
 sa_status sa_ctx_set_tuning(sa_ctx* ctx, const sa_tuning* t) {
-  if (!ctx || !t) return SA_EINVAL;
-  const u32 it = t->sort_items;
-  if (it != 8 && it != 12 && it != 16 && it != 20 && it != 24) return SA_EINVAL;
-  if (t->lazy_ratio < 3) return SA_EINVAL;
-  if (t->round0_full > 1) return SA_EINVAL;
-  if (t->sort_wgs_per_cu > 16) return SA_EINVAL;
-  for (u32 r : t->reserved)
-    if (r != 0) return SA_EINVAL;
-  ctx->sort_items = int(it);
-  ctx->lazy_ratio = t->lazy_ratio;
-  ctx->round0_trim = t->round0_full ? 0 : 1;
-  ctx->sort_wgs_per_cu = int(t->sort_wgs_per_cu);
+  if (!ctx) return SA_EINVAL;
+  if (!t) {
+    ctx->tuning_explicit = false;
+    apply_tuning(ctx, default_tuning());
+    return SA_OK;
+  }
+  if (!tuning_valid(*t)) return SA_EINVAL;
+  ctx->tuning_explicit = true;
+  ctx->explicit_tuning = *t;
+  apply_tuning(ctx, *t);
   return SA_OK;
 }
 
 sa_status sa_ctx_get_tuning(const sa_ctx* ctx, sa_tuning* out) {
   if (!ctx || !out) return SA_EINVAL;
-  std::memset(out, 0, sizeof(*out));
-  out->sort_items = u32(ctx->sort_items);
-  out->lazy_ratio = u32(ctx->lazy_ratio);
-  out->round0_full = ctx->round0_trim ? 0u : 1u;
-  out->sort_wgs_per_cu = u32(ctx->sort_wgs_per_cu);
+  *out = current_tuning(ctx);
+  return SA_OK;
+}
+
+sa_status sa_ctx_tuning_source(const sa_ctx* ctx, int* source) {
+  if (!ctx || !source) return SA_EINVAL;
+  *source = ctx->tuning_explicit ? 2 : ctx->tuned_from_cache ? 1 : 0;
   return SA_OK;
 }
 

@@ -19,35 +19,12 @@ namespace {
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
-// LDS index with one pad slot after every 8 entries.
-__device__ inline int pad8(int i) { return i + (i >> 3); }
-
 __device__ inline u32 wave_inclusive_sum(u32 v) {
   const int lane = lane_id();
 #pragma unroll
   for (int off = 1; off < kWave; off <<= 1) {
     u32 t = __shfl_up(v, off, kWave);
     if (lane >= off) v += t;
-  }
-  return v;
-}
-
-__device__ inline u64 wave_inclusive_sum64(u64 v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    u64 t = __shfl_up(v, off, kWave);
-    if (lane >= off) v += t;
-  }
-  return v;
-}
-
-__device__ inline u64 wave_inclusive_max64(u64 v) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    u64 t = __shfl_up(v, off, kWave);
-    if (lane >= off) v = t > v ? t : v;
   }
   return v;
 }
@@ -81,62 +58,6 @@ __device__ u64 lookback(u64* status, u64 stride, u64 tile, u64 agg, u32 gen, boo
   }
   u64 inc = op_max ? (agg > excl ? agg : excl) : excl + agg;
   store_status(status + tile * stride, status_pack(gen, kFlagPrefix, inc));
-  return excl;
-}
-
-// Look-back by one whole wave over a window of 64 earlier tiles per round trip:
-// lane l reads the status of tile hi - l; the wave combines the aggregates up
-// to the nearest inclusive prefix, or up to the nearest tile not yet published
-// and then waits on that one. Must be called by all 64 lanes with tile > 0.
-// Publishes the inclusive prefix from lane 0 and returns the exclusive one.
-__device__ u64 lookback_wave(u64* status, u64 tile, u64 agg, u32 gen, bool op_max, u64* counters,
-                             u32* timed_out) {
-  const int lane = lane_id();
-  u64 excl = 0;
-  long long hi = (long long)tile - 1;
-  u32 spins = 0;
-  for (;;) {
-    const long long t = hi - lane;
-    bool ready = true, pre = true;
-    u64 v = 0;
-    if (t >= 0) {
-      const u64 s = load_status(status + t);
-      const u32 f = status_flag(s);
-      ready = status_gen(s) == (gen & kGenMask) && f != 0;
-      pre = ready && f == kFlagPrefix;
-      v = ready ? status_value(s) : 0;
-    }
-    const u64 stop = __ballot(!ready || pre);
-    const u64 pres = __ballot(pre);
-    const int first = stop ? __ffsll((long long)stop) - 1 : kWave;
-    const bool first_pre = first < kWave && ((pres >> first) & 1u);
-    u64 x = (lane < first || (lane == first && first_pre)) ? v : 0;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-      const u64 y = __shfl_xor(x, off, kWave);
-      x = op_max ? (y > x ? y : x) : x + y;
-    }
-    excl = op_max ? (x > excl ? x : excl) : excl + x;
-    if (first_pre) break;
-    if (first == kWave) {
-      hi -= kWave;
-      continue;
-    }
-    hi -= first;  // wait for the nearest unpublished tile
-    if (++spins > kSpinLimit) {
-      if (lane == 0) {
-        atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
-                 (unsigned long long)kErrLookbackTimeout);
-        *timed_out = 1;
-      }
-      break;
-    }
-    __builtin_amdgcn_s_sleep(1);
-  }
-  if (lane == 0) {
-    const u64 inc = op_max ? (agg > excl ? agg : excl) : excl + agg;
-    store_status(status + tile, status_pack(gen, kFlagPrefix, inc));
-  }
   return excl;
 }
 
@@ -738,6 +659,46 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
 }
 
 // ---------------------------------------------------------------------------
+// First position q <= p whose key agrees with keys[p] in the bits above `sh`
+// (x = keys[p] >> sh, sh < 64) in the ascending array `keys`: the start of the
+// run (sh = 0) or group containing p. One wave, every lane: 64 probes per step,
+// galloping down from p in strides 1, 64, 64^2, ... until a probe falls below
+// x, then narrowing the bracketed interval 64-fold per step. A run of length L
+// costs about 2 log64(L) dependent wave loads; every probe is inside [0, p].
+__device__ u64 run_start_wave(const u64* __restrict__ keys, u64 p, int sh, u64 x) {
+  using i64 = long long;
+  const int lane = lane_id();
+  i64 hi = i64(p);  // (keys[hi] >> sh) == x
+  i64 lo = -1;      // (keys[lo] >> sh) < x, or -1
+  i64 stride = 1;
+  for (;;) {
+    const i64 pos = hi - stride * (lane + 1);
+    const bool below = pos < 0 || (keys[pos] >> sh) < x;
+    const u64 m = __ballot(below);
+    if (m) {
+      const int l = __ffsll((long long)m) - 1;
+      const i64 pl = hi - stride * (l + 1);
+      lo = pl < -1 ? -1 : pl;
+      if (l) hi -= stride * l;
+      break;
+    }
+    hi -= stride * kWave;
+    stride *= kWave;
+  }
+  while (hi - lo > 1) {
+    const i64 st = (hi - lo + kWave - 1) / kWave;
+    const i64 pos = hi - st * (lane + 1);
+    const bool below = pos <= lo || (keys[pos] >> sh) < x;
+    const u64 m = __ballot(below);  // lane 63 probes at or below lo: m != 0
+    const int l = __ffsll((long long)m) - 1;
+    const i64 nlo = hi - st * (l + 1);
+    lo = nlo > lo ? nlo : lo;
+    if (l) hi -= st * l;
+  }
+  return u64(hi);
+}
+
+// ---------------------------------------------------------------------------
 // Re-rank, ISA scatter, finalisation and compaction (one pass over the sorted
 // active set).
 //
@@ -756,15 +717,18 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
 //
 // Layout: thread t of the tile owns kRerankItems consecutive elements and
 // scans them sequentially; one wave-level scan per tile combines the threads,
-// then the waves of the block, then the tiles by decoupled look-back. Loads and
-// the rank store are 16-byte vector accesses.
+// then the waves of the block. No tile waits for another: the run and the
+// group that the tile's first element continues from an earlier tile are
+// found by searching the sorted keys (run_start_wave), and the survivors take
+// their output range with one atomic add per tile, so survivors keep their
+// sorted order inside a tile but tiles land in any order (the next round
+// sorts them anyway). Loads and the rank store are 16-byte vector accesses.
 __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
     const SortPlan* __restrict__ plan, const RerankArgs a, u32* __restrict__ isa,
     u32* __restrict__ sa_out, u32* __restrict__ act_idx, u64* __restrict__ act_ti,
-    u32* __restrict__ act_rank, u64* __restrict__ st_head, u64* __restrict__ st_grp,
-    u64* __restrict__ st_surv, u64* __restrict__ counters, u32 gen) {
+    u32* __restrict__ act_rank, u64* __restrict__ counters) {
   constexpr int NW = kRerankBlock / kWave;
   constexpr int I = kRerankItems;
   constexpr int T = kRerankTile;
@@ -773,8 +737,6 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   static_assert(I % 4 == 0, "vector loads of four values");
   __shared__ u32 s_wh[NW], s_wg[NW], s_ws[NW];
   __shared__ u64 s_prefix[3];
-  __shared__ u64 s_tile;
-  __shared__ u32 s_abort;
 
   const u32 fb = plan->final_buf;
   const u64* keys = fb ? keysB : keysA;
@@ -787,12 +749,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
-  if (tid == 0) {
-    s_tile = atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrRerankTiles), 1ull);
-    s_abort = 0;
-  }
-  __syncthreads();
-  const u64 tile = s_tile;
+  const u64 tile = blockIdx.x;
   const u64 base = tile * T;
   const u32 lfirst = u32(tid) * I;  // first element of this thread inside the tile
   const u64 first = base + lfirst;
@@ -884,7 +841,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   if (lane == 0) xh = xg = 0;
   u32 xs = is - ts;
   __syncthreads();
-  u32 eh = 0, eg = 0, es = 0, tth = 0, ttg = 0, tts = 0;
+  u32 eh = 0, eg = 0, es = 0, tts = 0;
 #pragma unroll
   for (int w = 0; w < NW; ++w) {
     const u32 a = s_wh[w], g = s_wg[w], c = s_ws[w];
@@ -893,36 +850,37 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
       eg = g > eg ? g : eg;
       es += c;
     }
-    tth = a > tth ? a : tth;
-    ttg = g > ttg ? g : ttg;
     tts += c;
   }
   xh = xh > eh ? xh : eh;
   xg = xg > eg ? xg : eg;
   xs += es;
 
-  // Tile prefixes from earlier tiles: waves 0, 1, 2 look back for the head,
-  // group and survivor scans. Head and group are max-scans of global positions
-  // (0 is the identity: position 0 is always a head and a group start); the
-  // survivor scan is a sum.
-  if (wave < 3) {
-    u64* st = wave == 0 ? st_head : (wave == 1 ? st_grp : st_surv);
-    const u32 loc = wave == 0 ? tth : (wave == 1 ? ttg : 0);
-    const u64 agg = wave == 2 ? u64(tts) : (loc ? base + loc - 1 : 0);
-    u64 pre = 0;
-    if (tile == 0) {
-      if (lane == 0) store_status(st, status_pack(gen, kFlagPrefix, agg));
-    } else {
-      if (lane == 0) store_status(st + tile, status_pack(gen, kFlagAggregate, agg));
-      pre = lookback_wave(st, tile, agg, gen, wave != 2, counters, &s_abort);
+  // What precedes the tile: wave 0 finds the start of the run of keys equal to
+  // keys[base] and wave 1 the start of its group (the last head and the last
+  // group start before the tile, when the tile does not begin with one);
+  // thread 0 reserves the tile's survivor slots.
+  if (wave < 2) {
+    const u64 kb = keys[base];
+    int sh = 0;
+    if (wave == 1) {
+      sh = a.gshift;
+      if (a.tbase && a.tround0[kb >> a.idshift]) sh = a.idshift;  // group = text
     }
-    if (lane == 0) {
-      s_prefix[wave] = pre;
-      if (wave == 2 && base + T >= count) counters[kCtrActive] = pre + agg;  // last tile
+    u64 start = base;
+    if (sh >= 64) {
+      start = 0;  // one group holds every element
+    } else if (base > 0) {
+      const u64 x = kb >> sh;
+      if ((keys[base - 1] >> sh) == x) start = run_start_wave(keys, base, sh, x);
     }
+    if (lane == 0) s_prefix[wave] = start;
   }
+  if (tid == 0)
+    s_prefix[2] = tts ? atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
+                                  (unsigned long long)tts)
+                      : 0;
   __syncthreads();
-  if (s_abort) return;
 
   u64 ss = xh ? base + xh - 1 : s_prefix[0];
   u64 gs = xg ? base + xg - 1 : s_prefix[1];
@@ -988,14 +946,12 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            const u32* valsB, const SortPlan* plan, const RerankArgs& args,
                            u32* isa, u32* sa_out, u32* act_idx, u64* act_ti, u32* act_rank,
-                           u64* st_head, u64* st_grp, u64* st_surv, u64* counters, u32 gen,
-                           hipStream_t s) {
+                           u64* counters, hipStream_t s) {
   if (args.count == 0) return;
   const u64 tiles = ceil_div(args.count, kRerankTile);
   hipLaunchKernelGGL(rerank_compact_kernel, dim3(u32(tiles)), dim3(kRerankBlock), 0, s, keysA,
                      keysB, valsA, valsB, plan, args, isa, sa_out, act_idx, act_ti, act_rank,
-                     st_head,
-                     st_grp, st_surv, counters, gen);
+                     counters);
 }
 
 // ---------------------------------------------------------------------------
