@@ -78,8 +78,8 @@ constexpr int kSortItemsMin = 8;
 constexpr int kSortTileMin = kSortBlock * kSortItemsMin;  // status arrays are sized for this
 constexpr int kHistBlock = 256;
 constexpr int kRerankBlock = 256;
-constexpr int kRerankItems = 16;
-constexpr int kRerankTile = kRerankBlock * kRerankItems;  // 4096 elements
+constexpr int kRerankRows = 16;  // rows of 64 elements per wave
+constexpr int kRerankTile = kRerankBlock * kRerankRows;  // 4096 elements
 
 // Device-side 64-bit counters shared by one build (slot indices).
 enum CounterSlot : int {

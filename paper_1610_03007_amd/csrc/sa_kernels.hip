@@ -713,16 +713,21 @@ __device__ u64 run_start_wave(const u64* __restrict__ keys, u64 p, int sh, u64 x
 // In round 0 every element starts in one group with r0 = 1.
 // An element is unique when it is a head and the next element is a head too
 // (Alg. 6 `Unique`); its rank is final, so SA[newrank - 1] = its position and it
-// is discarded. All others survive, in sorted order.
+// is discarded. All others survive.
 //
-// Layout: thread t of the tile owns kRerankItems consecutive elements and
-// scans them sequentially; one wave-level scan per tile combines the threads,
-// then the waves of the block. No tile waits for another: the run and the
-// group that the tile's first element continues from an earlier tile are
-// found by searching the sorted keys (run_start_wave), and the survivors take
-// their output range with one atomic add per tile, so survivors keep their
-// sorted order inside a tile but tiles land in any order (the next round
-// sorts them anyway). Loads and the rank store are 16-byte vector accesses.
+// Layout: the tile is kRerankBlock / 64 waves of kRerankRows rows of 64
+// consecutive elements; lane l of row r of wave w holds element
+// base + (w * kRerankRows + r) * 64 + l, so every load and store of a row is
+// one contiguous 64-element access. Within a row, the last head (group start)
+// at or before each lane comes from a ballot of the head (group) flags and a
+// count-leading-zeros of the bits up to the lane; the survivors' output slots
+// from a population count. Rows carry the last head / group start forward;
+// waves combine through LDS. No tile waits for another: the run and the group
+// that the tile's first element continues from an earlier tile are found by
+// searching the sorted keys (run_start_wave), and the survivors take their
+// output range with one atomic add per tile, so survivors keep their sorted
+// order inside a tile but tiles land in any order (the next round sorts them
+// anyway).
 __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
@@ -730,11 +735,11 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     u32* __restrict__ sa_out, u32* __restrict__ act_idx, u64* __restrict__ act_ti,
     u32* __restrict__ act_rank, u64* __restrict__ counters) {
   constexpr int NW = kRerankBlock / kWave;
-  constexpr int I = kRerankItems;
+  constexpr int R = kRerankRows;
   constexpr int T = kRerankTile;
+  static_assert(R <= 16, "flag bits of a lane: heads in 0..15, uniques in 16..31");
   const u64 count = a.count;
   const int mode = a.mode;
-  static_assert(I % 4 == 0, "vector loads of four values");
   __shared__ u32 s_wh[NW], s_wg[NW], s_ws[NW];
   __shared__ u64 s_prefix[3];
 
@@ -751,115 +756,12 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const int wave = tid / kWave;
   const u64 tile = blockIdx.x;
   const u64 base = tile * T;
-  const u32 lfirst = u32(tid) * I;  // first element of this thread inside the tile
-  const u64 first = base + lfirst;
-  const bool full = first + I <= count;
-
-  u64 k[I];
-  u32 v[I];
-  if (full) {
-    const uint4* kv = reinterpret_cast<const uint4*>(keys + first);
-    const uint4* vv = reinterpret_cast<const uint4*>(vals + first);
-#pragma unroll
-    for (int q = 0; q < I / 2; ++q) {
-      const uint4 w = kv[q];
-      k[2 * q] = (u64(w.y) << 32) | w.x;
-      k[2 * q + 1] = (u64(w.w) << 32) | w.z;
-    }
-#pragma unroll
-    for (int q = 0; q < I / 4; ++q) {
-      const uint4 w = vv[q];
-      v[4 * q] = w.x;
-      v[4 * q + 1] = w.y;
-      v[4 * q + 2] = w.z;
-      v[4 * q + 3] = w.w;
-    }
-  } else {
-#pragma unroll
-    for (int j = 0; j < I; ++j) {
-      const u64 p = first + j;
-      k[j] = p < count ? keys[p] : 0;
-      v[j] = p < count ? vals[p] : 0;
-    }
-  }
-  // Neighbour keys across thread boundaries (all lanes shuffle; the wave edges
-  // come from memory).
-  u64 kprev = __shfl_up(k[I - 1], 1, kWave);
-  u64 knext = __shfl_down(k[0], 1, kWave);
-  if (lane == 0) kprev = (first > 0 && first - 1 < count) ? keys[first - 1] : 0;
-  if (lane == kWave - 1) knext = (first + I < count) ? keys[first + I] : 0;
-
-  // Thread-local flags and sequential scans. Positions inside the tile are
-  // stored + 1 so that 0 means "none yet".
-  u32 flags = 0;  // bit j: head, bit 16+j: unique (group starts recomputed below)
-  u32 gflags = 0;
-  u32 th = 0, tg = 0, ts = 0;
-#pragma unroll
-  for (int j = 0; j < I; ++j) {
-    const u64 p = first + j;
-    if (p >= count) break;
-    const u64 kp = j ? k[j - 1] : kprev;
-    const u64 kn = (j + 1 < I) ? k[j + 1] : knext;
-    const bool head = (p == 0) || (k[j] != kp);
-    int gsh = a.gshift;
-    if (a.tbase && a.tround0[k[j] >> a.idshift]) gsh = a.idshift;  // group = text
-    const bool grp = (p == 0) || (gsh < 64 && (k[j] >> gsh) != (kp >> gsh));
-    const bool uniq = head && ((p + 1 == count) || (kn != k[j]));
-    if (head) {
-      flags |= 1u << j;
-      th = lfirst + j + 1;
-    }
-    if (grp) {
-      gflags |= 1u << j;
-      tg = lfirst + j + 1;
-    }
-    if (uniq)
-      flags |= 1u << (16 + j);
-    else
-      ++ts;
-  }
-  // Wave scans of the thread aggregates (max, max, sum).
-  u32 ih = th, ig = tg, is = ts;
-#pragma unroll
-  for (int off = 1; off < kWave; off <<= 1) {
-    const u32 a = __shfl_up(ih, off, kWave);
-    const u32 g = __shfl_up(ig, off, kWave);
-    const u32 c = __shfl_up(is, off, kWave);
-    if (lane >= off) {
-      ih = a > ih ? a : ih;
-      ig = g > ig ? g : ig;
-      is += c;
-    }
-  }
-  if (lane == kWave - 1) {
-    s_wh[wave] = ih;
-    s_wg[wave] = ig;
-    s_ws[wave] = is;
-  }
-  u32 xh = __shfl_up(ih, 1, kWave);  // exclusive within the wave
-  u32 xg = __shfl_up(ig, 1, kWave);
-  if (lane == 0) xh = xg = 0;
-  u32 xs = is - ts;
-  __syncthreads();
-  u32 eh = 0, eg = 0, es = 0, tts = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const u32 a = s_wh[w], g = s_wg[w], c = s_ws[w];
-    if (w < wave) {
-      eh = a > eh ? a : eh;
-      eg = g > eg ? g : eg;
-      es += c;
-    }
-    tts += c;
-  }
-  xh = xh > eh ? xh : eh;
-  xg = xg > eg ? xg : eg;
-  xs += es;
+  const u64 wbase = base + u64(wave) * (R * kWave);  // first element of the wave
+  const u64 lt_mask = (u64(1) << lane) - 1;
 
   // What precedes the tile: wave 0 finds the start of the run of keys equal to
   // keys[base] and wave 1 the start of its group (the last head and the last
-  // group start before the tile, when the tile does not begin with one);
-  // thread 0 reserves the tile's survivor slots.
+  // group start before the tile, when the tile does not begin with one).
   if (wave < 2) {
     const u64 kb = keys[base];
     int sh = 0;
@@ -876,71 +778,132 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     }
     if (lane == 0) s_prefix[wave] = start;
   }
-  if (tid == 0)
+
+  u64 k[R];
+  u32 v[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const u64 e = wbase + u64(r) * kWave + lane;
+    k[r] = e < count ? keys[e] : 0;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const u64 e = wbase + u64(r) * kWave + lane;
+    v[r] = e < count ? vals[e] : 0;
+  }
+
+  // Flags per element (bit r: head, bit 16 + r: unique; gflags bit r: group
+  // start) and the wave's aggregates: last head, last group start (tile-local
+  // position + 1, 0 = none) and survivor count.
+  u32 flags = 0, gflags = 0;
+  u32 wh = 0, wg = 0, ws = 0;
+  const u64 edge_next = wbase + u64(R) * kWave;
+  const u64 k_before = (lane == 0 && wbase > 0 && wbase - 1 < count) ? keys[wbase - 1] : 0;
+  const u64 k_after = (lane == kWave - 1 && edge_next < count) ? keys[edge_next] : 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const u64 e = wbase + u64(r) * kWave + lane;
+    u64 kp = __shfl_up(k[r], 1, kWave);
+    u64 kn = __shfl_down(k[r], 1, kWave);
+    const u64 last_prev = r > 0 ? __shfl(k[r - 1], kWave - 1, kWave) : k_before;
+    const u64 first_next = r + 1 < R ? __shfl(k[r + 1], 0, kWave) : k_after;
+    if (lane == 0) kp = last_prev;
+    if (lane == kWave - 1) kn = first_next;
+    const bool valid = e < count;
+    int gsh = a.gshift;
+    if (valid && a.tbase && a.tround0[k[r] >> a.idshift]) gsh = a.idshift;  // group = text
+    const bool head = valid && (e == 0 || k[r] != kp);
+    const bool grp = valid && (e == 0 || (gsh < 64 && (k[r] >> gsh) != (kp >> gsh)));
+    const bool uniq = head && (e + 1 == count || kn != k[r]);
+    if (head) flags |= 1u << r;
+    if (uniq) flags |= 1u << (16 + r);
+    if (grp) gflags |= 1u << r;
+    const u64 hm = __ballot(head), gm = __ballot(grp), sm = __ballot(valid && !uniq);
+    const u32 rowpos = u32((wave * R + r) * kWave);  // tile-local position of lane 0
+    if (hm) wh = rowpos + u32(63 - __clzll((long long)hm)) + 1;
+    if (gm) wg = rowpos + u32(63 - __clzll((long long)gm)) + 1;
+    ws += u32(__popcll(sm));
+  }
+  if (lane == 0) {
+    s_wh[wave] = wh;
+    s_wg[wave] = wg;
+    s_ws[wave] = ws;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    u32 tts = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) tts += s_ws[w];
     s_prefix[2] = tts ? atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
                                   (unsigned long long)tts)
                       : 0;
+  }
   __syncthreads();
 
-  u64 ss = xh ? base + xh - 1 : s_prefix[0];
-  u64 gs = xg ? base + xg - 1 : s_prefix[1];
-  u64 out = s_prefix[2] + xs;
-  u32 nrs[I];
+  // Carries into the wave's first row: from earlier waves of the tile, else
+  // from before the tile.
+  u32 eh = 0, eg = 0, es = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    if (w < wave) {
+      eh = s_wh[w] > eh ? s_wh[w] : eh;
+      eg = s_wg[w] > eg ? s_wg[w] : eg;
+      es += s_ws[w];
+    }
+  }
+  u64 carry_h = eh ? base + eh - 1 : s_prefix[0];
+  u64 carry_g = eg ? base + eg - 1 : s_prefix[1];
+  u64 out_base = s_prefix[2] + es;
   bool bad = false;
 #pragma unroll
-  for (int j = 0; j < I; ++j) {
-    const u64 p = first + j;
-    nrs[j] = 0;
-    if (p >= count) break;
-    if ((flags >> j) & 1u) ss = p;
-    if ((gflags >> j) & 1u) gs = p;
+  for (int r = 0; r < R; ++r) {
+    const u64 e = wbase + u64(r) * kWave + lane;
+    const u64 row0 = wbase + u64(r) * kWave;
+    const bool head = (flags >> r) & 1u;
+    const bool uniq = (flags >> (16 + r)) & 1u;
+    const bool grp = (gflags >> r) & 1u;
+    const bool valid = e < count;
+    const u64 hm = __ballot(head), gm = __ballot(grp), sm = __ballot(valid && !uniq);
+    const u64 upto = lt_mask | (u64(1) << lane);
+    const u64 hmine = hm & upto, gmine = gm & upto;
+    const u64 ss = hmine ? row0 + u64(63 - __clzll((long long)hmine)) : carry_h;
+    const u64 gs = gmine ? row0 + u64(63 - __clzll((long long)gmine)) : carry_g;
+    const u64 out = out_base + u64(__popcll(sm & lt_mask));
+    if (hm) carry_h = row0 + u64(63 - __clzll((long long)hm));
+    if (gm) carry_g = row0 + u64(63 - __clzll((long long)gm));
+    out_base += u64(__popcll(sm));
+    if (!valid) continue;
     // Text of the element: the whole text, or (multi-text) the one named by
     // the key's high bits; ranks and positions are local to it.
     u64 gb = 0, nt = a.n, t = 0;
     bool first_round = a.rmask == 0;
     if (a.tbase) {
-      t = k[j] >> a.idshift;
+      t = k[r] >> a.idshift;
       gb = a.tbase[t];
       nt = a.tlen[t];
       first_round = a.tround0[t] != 0;
     }
-    const u64 r0 = first_round ? 1 : ((k[j] >> a.rshift) & a.rmask);
+    const u64 r0 = first_round ? 1 : ((k[r] >> a.rshift) & a.rmask);
     const u64 nr = r0 + ss - gs;
-    const bool uniq = (flags >> (16 + j)) & 1u;
-    if (v[j] >= nt || nr == 0 || nr > nt || (!uniq && out >= count)) {
+    if (v[r] >= nt || nr == 0 || nr > nt || (!uniq && out >= count)) {
       bad = true;
-      break;
+      continue;
     }
-    nrs[j] = u32(nr);
-    if (scatter) isa[gb + v[j]] = u32(nr);
+    if (scatter) isa[gb + v[r]] = u32(nr);
+    if (write_ranks) ranks_out[e] = u32(nr);
     if (uniq) {
-      sa_out[gb + nr - 1] = v[j];
+      sa_out[gb + nr - 1] = v[r];
     } else {
       if (act_ti)
-        act_ti[out] = (t << 32) | v[j];
+        act_ti[out] = (t << 32) | v[r];
       else
-        act_idx[out] = v[j];
+        act_idx[out] = v[r];
       act_rank[out] = u32(nr);
-      ++out;
     }
   }
-  if (bad) {
+  if (bad)
     atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
              (unsigned long long)kErrBounds);
-    return;
-  }
-  if (write_ranks) {
-    if (full) {
-      uint4* rv = reinterpret_cast<uint4*>(ranks_out + first);
-#pragma unroll
-      for (int q = 0; q < I / 4; ++q)
-        rv[q] = make_uint4(nrs[4 * q], nrs[4 * q + 1], nrs[4 * q + 2], nrs[4 * q + 3]);
-    } else {
-#pragma unroll
-      for (int j = 0; j < I; ++j)
-        if (first + j < count) ranks_out[first + j] = nrs[j];
-    }
-  }
 }
 
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
