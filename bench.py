@@ -296,6 +296,7 @@ def tune_main(args) -> int:
     import torch
 
     from paper_1610_03007_amd import SuffixArrayBuilder
+    os.environ.setdefault("SA_TUNE_LOG", "1")  # one line per candidate: progress on stderr
     dev = torch.device("cuda", 0)
     b = SuffixArrayBuilder(0, tune_cache=args.tune)
     for name in [w for w in args.tune_workloads.split(",") if w]:

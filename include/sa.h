@@ -171,13 +171,16 @@ sa_status sa_ctx_set_isa_mode(sa_ctx* ctx, int mode);
 /* Tuning knobs (none changes a result). Unknown or unsupported values give
  * SA_EINVAL and leave the context unchanged. */
 typedef struct {
-  uint32_t sort_items;   /* radix-sort items per thread: 8, 12, 16, 20 or 24 (tile = 256x) */
+  uint32_t sort_items;   /* radix-sort items per thread: 8, 12, 16, 20 or 24 with 256-thread
+                            workgroups (tile = sort_block x sort_items) */
   uint32_t lazy_ratio;   /* auto ISA mode is lazy when survivors <= n / lazy_ratio (>= 3) */
   uint32_t round0_full;  /* 1: pack floor(64 / code bits) characters in round 0; 0 (default):
                             drop the characters that only half-fill a last 8-bit digit */
   uint32_t sort_wgs_per_cu; /* persistent radix-sweep workgroups per compute unit
                                (0 = what one CU holds for the tile shape; at most 16) */
-  uint32_t reserved[4];  /* must be zero */
+  uint32_t sort_block;   /* radix-sweep workgroup size: 256 (0 means 256) or 512; with 512,
+                            sort_items is 4, 8 or 12 */
+  uint32_t reserved[3];  /* must be zero */
 } sa_tuning;
 /* Sets an explicit tuning, used by every later build of the context. t = NULL
  * goes back to automatic choice: the cache entry for each input, else the
@@ -192,8 +195,8 @@ sa_status sa_ctx_tuning_source(const sa_ctx* ctx, int* source);
 /* Autotuner. Times candidate tunings on the caller's input and records the
  * fastest in the context's cache table, keyed by (GPU architecture, mode,
  * floor(log2 of the total length), bits per character code of the input):
- *   stage 1: sort_items in {8, 12, 16, 20, 24} x sort_wgs_per_cu in
- *            {default, 1, 2, 3, 4, 6, 8};
+ *   stage 1: (sort_items, sort_block) in {8, 12, 16, 20, 24} x 256 and
+ *            {4, 8, 12} x 512, x sort_wgs_per_cu in {default, 1, 2, 3, 4};
  *   stage 2: round0_full flipped; stage 3: lazy_ratio in {3, 4, 8, 16, 64}.
  * Each candidate is one warm-up build plus the best of `reps` timed builds
  * (0 = 3) on `stream`, measured with HIP events. d_texts / h_offsets /
@@ -204,7 +207,8 @@ sa_status sa_ctx_tuning_source(const sa_ctx* ctx, int* source);
  * A later build finds the entry when it has the same architecture and mode, a
  * size within two binary orders of magnitude (nearest first) and, for
  * sa_build, the nearest code width to bits(sigma hint) (a hint of 256 matches
- * any width). */
+ * any width). With SA_TUNE_LOG set in the environment, each candidate's time
+ * is printed to stderr. */
 sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets,
                   uint32_t num_texts, uint32_t* d_sas, void* stream, uint32_t reps,
                   sa_tuning* best_out, double* best_ms);

@@ -69,13 +69,13 @@ struct SortPlan {
 // before the sweep starts (for the first sweep from the up-front histogram,
 // for later ones accumulated by the sweep before), so a chunk's first tile
 // never waits on another chunk.
-constexpr int kChunks = 8;
+constexpr int kChunks = 32;
 
 // Workgroup and tile shapes.
-constexpr int kSortBlock = 256;
-constexpr int kSortItemsDefault = 16;
-constexpr int kSortItemsMin = 8;
-constexpr int kSortTileMin = kSortBlock * kSortItemsMin;  // status arrays are sized for this
+constexpr int kSortBlock = 256;          // the smaller sweep workgroup (one thread per digit)
+constexpr int kSortBlockDefault = 512;   // default sweep shape: 512 threads x 8 items
+constexpr int kSortItemsDefault = 8;
+constexpr int kSortTileMin = 2048;       // smallest tile (512 x 4); status arrays are sized for it
 constexpr int kHistBlock = 256;
 constexpr int kRerankBlock = 256;
 constexpr int kRerankRows = 16;  // rows of 64 elements per wave

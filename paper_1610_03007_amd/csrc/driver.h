@@ -72,6 +72,7 @@ struct sa_ctx {
   u32 gen = 0;
   int isa_mode = SA_ISA_AUTO;
   int sort_items = kSortItemsDefault;  // radix-sort items per thread (tile size)
+  int sort_block = kSortBlockDefault;  // radix-sort workgroup size (256 or 512)
   int sort_wgs_per_cu = 0;             // persistent sweep workgroups per CU (0 = by tile size)
   int num_cus = 256;
   u64 lazy_ratio = kLazyRatioDefault;
@@ -165,8 +166,8 @@ struct Bufs {
 };
 
 Bufs full_bufs(sa_ctx* c);
-SortGeom make_geom(u64 count, int items);
-int default_wgs_per_cu(int items);
+SortGeom make_geom(u64 count, int items, int block);
+int default_wgs_per_cu(int items, int block);
 void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
               hipStream_t s);
 void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s);

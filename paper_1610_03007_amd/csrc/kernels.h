@@ -48,12 +48,13 @@ void launch_radix_plan(const u32* hist_in, const SortGeom& geo, int npass, int v
                        SortPlan* plan, hipStream_t s);
 // One sweep. hist_run [kMaxPasses][kChunks][kRadix] and tickets
 // [kMaxPasses][kChunks] must be zero before the first sweep of a sort. `items`
-// per thread (8, 12, 16, 20 or 24) must match geo.tile = kSortBlock * items.
+// per thread (8, 12, 16, 20 or 24 with 256-thread workgroups; 4, 8 or 12 with
+// 512) and `block` must match geo.tile = block * items.
 // `grid` persistent workgroups (a multiple of geo.nchunks).
 void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
                           int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
                           u32* tickets, u64* status, u64* counters, u32 gen, int items,
-                          u32 grid, hipStream_t s);
+                          int block, u32 grid, hipStream_t s);
 
 // Re-rank the sorted active set, scatter the ISA, finalize unique suffixes into
 // the SA and compact the survivors.

@@ -101,12 +101,12 @@ void collect_trace(sa_ctx* c) {
 
 Bufs full_bufs(sa_ctx* c) { return Bufs{c->keysA, c->keysB, c->valsA, c->valsB}; }
 
-// Sweep geometry: tiles of kSortBlock * items pairs, chunks of a power-of-two
+// Sweep geometry: tiles of block * items pairs, chunks of a power-of-two
 // number of tiles so that at most kChunks chunks cover the input.
-SortGeom make_geom(u64 count, int items) {
+SortGeom make_geom(u64 count, int items, int block) {
   SortGeom g;
   g.count = count;
-  g.tile = u32(kSortBlock * items);
+  g.tile = u32(block * items);
   const u64 tiles = std::max<u64>(1, ceil_div(count, g.tile));
   const u64 per = ceil_div(tiles, kChunks);
   u32 lg = 0;
@@ -118,13 +118,13 @@ SortGeom make_geom(u64 count, int items) {
 
 // Sweep workgroups one CU holds at once for each tile shape (register and LDS
 // limits of the kernel instances).
-int default_wgs_per_cu(int items) {
-  switch (items) {
-    case 8: return 4;
-    case 12: return 3;
-    case 24: return 1;
-    default: return 2;
-  }
+int default_wgs_per_cu(int items, int block) {
+  // What one CU's 160 KB of LDS holds: the key tile (8 bytes + 1 digit byte per
+  // item), the per-wave digit counts (16 bits) and the chunk histograms of the
+  // next sweep, plus about 6 KB of small arrays.
+  const int lds = block * items * 9 + (block / kWave / 2) * kRadix * 4 + kChunks * kRadix * 4 + 6144;
+  const int n = (160 * 1024) / lds;
+  return n < 1 ? 1 : n;
 }
 
 // Sorts (kA, vA or generated values) by the low 8*npass bits. The sorted pairs
@@ -132,7 +132,7 @@ int default_wgs_per_cu(int items) {
 // h_plans slot `slot` on the stream.
 void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
               hipStream_t s) {
-  const SortGeom geo = make_geom(count, c->sort_items);
+  const SortGeom geo = make_geom(count, c->sort_items, c->sort_block);
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
     // Chunk histograms and tickets; the survivor count the re-rank adds to.
@@ -150,14 +150,16 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
   (void)hipMemcpyAsync(c->h_plans + size_t(slot) * kPlanFlagWords, c->plan->skip,
                        kPlanFlagWords * sizeof(u32), hipMemcpyDeviceToHost, s);
   const u64 tiles = ceil_div(count, geo.tile);
-  const int per_cu = c->sort_wgs_per_cu > 0 ? c->sort_wgs_per_cu : default_wgs_per_cu(c->sort_items);
+  const int per_cu = c->sort_wgs_per_cu > 0 ? c->sort_wgs_per_cu
+                                            : default_wgs_per_cu(c->sort_items, c->sort_block);
   const u64 want = std::min<u64>(tiles, u64(c->num_cus) * u64(per_cu));
   const u32 grid = u32(std::max<u64>(1, want / geo.nchunks) * geo.nchunks);
   for (int p = 0; p < npass; ++p) {
     u32 gen = next_gen(c, s);
     Tracer t(c, s, SA_KERNEL_SORT_PASS, 0, slot, p, count);
     launch_onesweep_pass(bf.kA, bf.kB, bf.vA, bf.vB, geo, p, c->plan, c->hist_in, c->hist_run,
-                         c->tickets, c->status, c->counters, gen, c->sort_items, grid, s);
+                         c->tickets, c->status, c->counters, gen, c->sort_items,
+                         c->sort_block, grid, s);
   }
 }
 

@@ -433,7 +433,7 @@ void launch_radix_plan(const u32* hist_in, const SortGeom& geo, int npass, int v
 
 // One stable counting sweep over digit `pass`, persistent: workgroup b works on
 // chunk b % nchunks and takes that chunk's tiles in order from a ticket. Per
-// tile of kSortBlock * ITEMS pairs: load ITEMS items per thread in
+// tile of BLOCK * ITEMS pairs: load ITEMS items per thread in
 // wave-striped order; rank every item among the equal digits of its wave (an
 // eight-ballot match mask, and one LDS fetch-add per match group issued back
 // to back for all items, which a wave executes in program order); combine the
@@ -442,24 +442,28 @@ void launch_radix_plan(const u32* hist_in, const SortGeom& geo, int npass, int v
 // digit's run out contiguously, then the values through the same LDS buffer.
 // While writing keys it counts, per output chunk, the digit of the next sweep
 // that runs, so that sweep starts with exact chunk bases as well.
-template <int ITEMS>
-__global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
+template <int ITEMS, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
     u64* __restrict__ keysA, u64* __restrict__ keysB, u32* __restrict__ valsA,
     u32* __restrict__ valsB, u64 count, int pass, u32 ct_log2, u32 nchunks,
     const SortPlan* __restrict__ plan, const u32* __restrict__ hist_in,
     u32* __restrict__ hist_run, u32* __restrict__ tickets, u64* __restrict__ status,
     u64* __restrict__ counters, u32 gen) {
-  static_assert(kSortBlock == kRadix, "one thread per digit value");
-  constexpr int NW = kSortBlock / kWave;
-  constexpr int TILE = kSortBlock * ITEMS;
+  static_assert(BLOCK == kRadix || BLOCK == 2 * kRadix, "the first kRadix threads own a digit");
+  constexpr int NW = BLOCK / kWave;
+  constexpr int DW = kRadix / kWave;  // waves that own digits
+  constexpr int TILE = BLOCK * ITEMS;
   __shared__ u64 s_buf[TILE];  // keys, then values (as u32)
   __shared__ u8 s_dig[TILE];   // digit of each reordered position
-  __shared__ u32 s_cnt[NW][kRadix];
+  // Per-wave digit counts, two waves per word (16 bits each: a wave ranks at
+  // most 64 * ITEMS items and a tile holds at most 6144).
+  static_assert(NW % 2 == 0 && TILE < 65536, "16-bit count halves");
+  __shared__ u32 s_cnt[NW / 2][kRadix];
   __shared__ u32 s_next[kChunks * kRadix];
   __shared__ u32 s_start[kRadix];
   __shared__ u64 s_base[kRadix];
   __shared__ u64 s_cbase[kRadix];
-  __shared__ u32 s_wsum[NW];
+  __shared__ u32 s_wsum[DW];
   __shared__ u32 s_ticket;
   __shared__ u32 s_abort;
 
@@ -485,22 +489,22 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
 
   // Start of each digit's output range for this chunk: global digit offset
   // plus that digit's count in the earlier chunks.
-  {
+  const bool digit_owner = tid < kRadix;  // thread tid owns digit tid
+  if (digit_owner) {
     const u32* h = (u32(pass) == plan->first_run ? hist_in : hist_run) +
                    size_t(pass) * kChunks * kRadix;
     u64 b = plan->offsets[pass][tid];
     for (u32 c = 0; c < chunk; ++c) b += h[c * kRadix + tid];
     s_cbase[tid] = b;
   }
-  for (int i = tid; i < kChunks * kRadix; i += kSortBlock) s_next[i] = 0;
+  for (int i = tid; i < kChunks * kRadix; i += BLOCK) s_next[i] = 0;
 
   for (;;) {
     if (tid == 0) {
       s_ticket = atomicAdd(tickets + pass * kChunks + chunk, 1u);
       s_abort = 0;
     }
-#pragma unroll
-    for (int w = 0; w < NW; ++w) s_cnt[w][tid] = 0;
+    for (int i = tid; i < (NW / 2) * kRadix; i += BLOCK) (&s_cnt[0][0])[i] = 0;
     __syncthreads();
     const u64 tile = c_first + s_ticket;
     if (tile >= c_end) break;  // uniform
@@ -528,7 +532,8 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
     }
 
     // Rank within the wave, items in (j, lane) order == input order.
-    u32* cnt = &s_cnt[wave][0];
+    u32* cnt = &s_cnt[wave >> 1][0];
+    const int half = 16 * (wave & 1);
     const u64 lt_mask = (u64(1) << lane) - 1;
     u32 rank[ITEMS];
     u32 packed[ITEMS];  // below | leader << 8
@@ -546,44 +551,48 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
       packed[j] = u32(__popcll(peers & lt_mask)) | (leader << 8);
       u32 old = 0;
       if (u32(lane) == leader)
-        old = __hip_atomic_fetch_add(cnt + d, u32(__popcll(peers)), __ATOMIC_RELAXED,
+        old = __hip_atomic_fetch_add(cnt + d, u32(__popcll(peers)) << half, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_WORKGROUP);
-      rank[j] = old;
+      rank[j] = (old >> half) & 0xFFFFu;
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j)
       rank[j] = __shfl(rank[j], int(packed[j] >> 8), kWave) + (packed[j] & 0xFFu);
     __syncthreads();
 
-    // Per digit (one per thread): exclusive prefix over waves, tile total.
-    u32 tot = 0;
+    // Per digit (one per owning thread): exclusive prefix over waves, tile
+    // total.
+    u32 tot = 0, inc = 0;
+    if (digit_owner) {
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      const u32 c = s_cnt[w][tid];
-      s_cnt[w][tid] = tot;
-      tot += c;
+      for (int w2 = 0; w2 < NW / 2; ++w2) {
+        const u32 c = s_cnt[w2][tid];
+        const u32 lo = tot, hi = tot + (c & 0xFFFFu);
+        s_cnt[w2][tid] = lo | (hi << 16);
+        tot = hi + (c >> 16);
+      }
+      u64* my_status = status + tile * kRadix + tid;
+      store_status(my_status,
+                   status_pack(gen, tile == c_first ? kFlagPrefix : kFlagAggregate, tot));
+      // Exclusive scan of the tile totals over digits: tile-local run starts.
+      inc = wave_inclusive_sum(tot);
+      if (lane == kWave - 1) s_wsum[wave] = inc;
     }
-    u64* my_status = status + tile * kRadix + tid;
-    store_status(my_status,
-                 status_pack(gen, tile == c_first ? kFlagPrefix : kFlagAggregate, tot));
-
-    // Exclusive scan of the tile totals over digits: tile-local run starts.
-    const u32 inc = wave_inclusive_sum(tot);
-    if (lane == kWave - 1) s_wsum[wave] = inc;
     __syncthreads();
-    u32 woff = 0;
+    if (digit_owner) {
+      u32 woff = 0;
 #pragma unroll
-    for (int w = 0; w < NW; ++w)
-      if (w < wave) woff += s_wsum[w];
-    const u32 start = woff + inc - tot;
-    s_start[tid] = start;
-
-    // The chunk's first tile publishes a prefix, so the look-back never
-    // leaves the chunk.
-    u64 excl = 0;
-    if (tile > c_first)
-      excl = lookback(status + tid, kRadix, tile, tot, gen, false, counters, &s_abort);
-    s_base[tid] = s_cbase[tid] + excl - u64(start);
+      for (int w = 0; w < DW; ++w)
+        if (w < wave) woff += s_wsum[w];
+      const u32 start = woff + inc - tot;
+      s_start[tid] = start;
+      // The chunk's first tile publishes a prefix, so the look-back never
+      // leaves the chunk.
+      u64 excl = 0;
+      if (tile > c_first)
+        excl = lookback(status + tid, kRadix, tile, tot, gen, false, counters, &s_abort);
+      s_base[tid] = s_cbase[tid] + excl - u64(start);
+    }
     __syncthreads();
 
     // Tile-local position of each item: its digit's run start, the wave's
@@ -591,7 +600,7 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const u32 d = u32(key[j] >> shift) & (kRadix - 1);
-      rank[j] += s_start[d] + s_cnt[wave][d];
+      rank[j] += s_start[d] + ((s_cnt[wave >> 1][d] >> half) & 0xFFFFu);
       s_buf[rank[j]] = key[j];
       s_dig[rank[j]] = u8(d);
     }
@@ -600,7 +609,7 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
 
     const u64 left = count - tile_base;
     const u32 valid = left < u64(TILE) ? u32(left) : u32(TILE);
-    for (u32 q = tid; q < valid; q += kSortBlock) {
+    for (u32 q = tid; q < valid; q += BLOCK) {
       const u64 k = s_buf[q];
       const u64 o = s_base[s_dig[q]] + q;
       if (o < count) {
@@ -619,7 +628,7 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
       if (e < wvalid) s_vals[rank[j]] = val[j];
     }
     __syncthreads();
-    for (u32 q = tid; q < valid; q += kSortBlock) {
+    for (u32 q = tid; q < valid; q += BLOCK) {
       const u64 o = s_base[s_dig[q]] + q;
       if (o < count) {
         vout[o] = s_vals[q];
@@ -632,7 +641,7 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
   }
   if (next >= 0) {
     u32* h = hist_run + size_t(next) * kChunks * kRadix;
-    for (int i = tid; i < kChunks * kRadix; i += kSortBlock) {
+    for (int i = tid; i < kChunks * kRadix; i += BLOCK) {
       const u32 v = s_next[i];
       if (v) atomicAdd(h + i, v);
     }
@@ -642,18 +651,26 @@ __global__ __launch_bounds__(kSortBlock) void onesweep_pass_kernel(
 void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
                           int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
                           u32* tickets, u64* status, u64* counters, u32 gen, int items,
-                          u32 grid, hipStream_t s) {
+                          int block, u32 grid, hipStream_t s) {
   if (geo.count == 0) return;
-#define SA_ONESWEEP(IT)                                                                          \
-  hipLaunchKernelGGL(onesweep_pass_kernel<IT>, dim3(grid), dim3(kSortBlock), 0, s, keysA, keysB, \
-                     valsA, valsB, geo.count, pass, geo.ct_log2, geo.nchunks, plan, hist_in,     \
+#define SA_ONESWEEP(IT, BL)                                                                   \
+  hipLaunchKernelGGL((onesweep_pass_kernel<IT, BL>), dim3(grid), dim3(BL), 0, s, keysA, keysB, \
+                     valsA, valsB, geo.count, pass, geo.ct_log2, geo.nchunks, plan, hist_in,   \
                      hist_run, tickets, status, counters, gen)
-  switch (items) {
-    case 8: SA_ONESWEEP(8); break;
-    case 12: SA_ONESWEEP(12); break;
-    case 20: SA_ONESWEEP(20); break;
-    case 24: SA_ONESWEEP(24); break;
-    default: SA_ONESWEEP(16); break;
+  if (block == 2 * kRadix) {
+    switch (items) {
+      case 4: SA_ONESWEEP(4, 512); break;
+      case 12: SA_ONESWEEP(12, 512); break;
+      default: SA_ONESWEEP(8, 512); break;
+    }
+  } else {
+    switch (items) {
+      case 8: SA_ONESWEEP(8, 256); break;
+      case 12: SA_ONESWEEP(12, 256); break;
+      case 20: SA_ONESWEEP(20, 256); break;
+      case 24: SA_ONESWEEP(24, 256); break;
+      default: SA_ONESWEEP(16, 256); break;
+    }
   }
 #undef SA_ONESWEEP
 }

@@ -161,7 +161,13 @@ bool num_field(const JVal& o, const char* k, double lo, double hi, double* out) 
 // Checks the knobs the way sa_ctx_set_tuning does.
 bool tuning_valid(const sa_tuning& t) {
   const u32 it = t.sort_items;
-  if (it != 8 && it != 12 && it != 16 && it != 20 && it != 24) return false;
+  if (t.sort_block == 512) {
+    if (it != 4 && it != 8 && it != 12) return false;
+  } else if (t.sort_block == 0 || t.sort_block == 256) {
+    if (it != 8 && it != 12 && it != 16 && it != 20 && it != 24) return false;
+  } else {
+    return false;
+  }
   if (t.lazy_ratio < 3 || t.round0_full > 1 || t.sort_wgs_per_cu > 16) return false;
   for (u32 r : t.reserved)
     if (r != 0) return false;
@@ -172,6 +178,7 @@ sa_tuning default_tuning() {
   sa_tuning t;
   std::memset(&t, 0, sizeof(t));
   t.sort_items = kSortItemsDefault;
+  t.sort_block = kSortBlockDefault;
   t.lazy_ratio = u32(kLazyRatioDefault);
   t.round0_full = 0;
   t.sort_wgs_per_cu = 0;
@@ -208,6 +215,11 @@ sa_status tune_parse(const std::string& text, TuneTable& out) {
     te.t.sort_items = u32(v);
     if (!num_field(e, "sort_wgs_per_cu", 0, 16, &v)) return SA_EINVAL;
     te.t.sort_wgs_per_cu = u32(v);
+    te.t.sort_block = kSortBlock;  // entries without the field predate 512-thread sweeps
+    if (e.get("sort_block")) {
+      if (!num_field(e, "sort_block", 0, 512, &v)) return SA_EINVAL;
+      te.t.sort_block = u32(v);
+    }
     if (!num_field(e, "lazy_ratio", 3, 1e9, &v)) return SA_EINVAL;
     te.t.lazy_ratio = u32(v);
     if (!num_field(e, "round0_full", 0, 1, &v)) return SA_EINVAL;
@@ -239,7 +251,8 @@ std::string tune_format(const TuneTable& t) {
     o << (k ? ",\n" : "\n") << "    {\"arch\": \"" << e.arch << "\", \"mode\": \"" << e.mode
       << "\", \"log2n\": " << e.log2n << ", \"code_bits\": " << e.code_bits
       << ", \"sort_items\": " << e.t.sort_items << ", \"sort_wgs_per_cu\": "
-      << e.t.sort_wgs_per_cu << ", \"lazy_ratio\": " << e.t.lazy_ratio
+      << e.t.sort_wgs_per_cu << ", \"sort_block\": " << e.t.sort_block
+      << ", \"lazy_ratio\": " << e.t.lazy_ratio
       << ", \"round0_full\": " << e.t.round0_full << ", \"ms\": " << ms << "}";
   }
   o << "\n  ]\n}\n";
@@ -294,6 +307,7 @@ void tune_upsert(TuneTable& t, const TuneEntry& e) {
 
 void apply_tuning(sa_ctx* c, const sa_tuning& t) {
   c->sort_items = int(t.sort_items);
+  c->sort_block = t.sort_block ? int(t.sort_block) : kSortBlock;
   c->lazy_ratio = t.lazy_ratio;
   c->round0_trim = t.round0_full ? 0 : 1;
   c->sort_wgs_per_cu = int(t.sort_wgs_per_cu);
@@ -303,6 +317,7 @@ sa_tuning current_tuning(const sa_ctx* c) {
   sa_tuning t;
   std::memset(&t, 0, sizeof(t));
   t.sort_items = u32(c->sort_items);
+  t.sort_block = u32(c->sort_block);
   t.lazy_ratio = u32(c->lazy_ratio);
   t.round0_full = c->round0_trim ? 0u : 1u;
   t.sort_wgs_per_cu = u32(c->sort_wgs_per_cu);
@@ -401,11 +416,20 @@ sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets
   sa_tuning best = default_tuning();
   double best_t = 0;
   sa_status st = SA_OK;
+  // SA_TUNE_LOG set in the environment: one line per candidate on stderr.
+  const bool log = std::getenv("SA_TUNE_LOG") != nullptr;
   auto trial = [&](const sa_tuning& t) -> sa_status {
     ctx->explicit_tuning = t;
     double ms = 0;
     sa_status e = time_build(ctx, d_texts, h_offsets, num_texts, d_sas, s, reps, &ms);
     if (e != SA_OK) return e;
+    if (log) {
+      std::fprintf(stderr,
+                   "sa_tune: items %u block %u wgs/cu %u round0_full %u lazy_ratio %u: %.3f ms\n",
+                   t.sort_items, t.sort_block, t.sort_wgs_per_cu, t.round0_full, t.lazy_ratio,
+                   ms);
+      std::fflush(stderr);
+    }
     if (best_t == 0 || ms < best_t) {
       best_t = ms;
       best = t;
@@ -414,15 +438,21 @@ sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets
   };
   // Stage 1: tile shape and persistent grid of the radix sweeps (the default
   // grid first, then explicit workgroups per CU).
-  const u32 items_set[] = {8, 12, 16, 20, 24};
-  const u32 wgs_set[] = {0, 1, 2, 3, 4, 6, 8};
-  for (u32 it : items_set) {
+  struct Shape {
+    u32 items, block;
+  };
+  const Shape shapes[] = {{8, 256}, {12, 256}, {16, 256}, {20, 256}, {24, 256},
+                          {4, 512}, {8, 512}, {12, 512}};
+  const u32 wgs_set[] = {0, 1, 2, 3, 4};
+  for (const Shape& sh : shapes) {
     for (u32 w : wgs_set) {
       if (st != SA_OK) break;
       sa_tuning t = default_tuning();
-      t.sort_items = it;
+      t.sort_items = sh.items;
+      t.sort_block = sh.block;
       t.sort_wgs_per_cu = w;
-      if (w != 0 && int(w) == default_wgs_per_cu(int(it))) continue;  // same as w = 0
+      if (w != 0 && int(w) == default_wgs_per_cu(int(sh.items), int(sh.block)))
+        continue;  // same as w = 0
       st = trial(t);
     }
   }

@@ -262,10 +262,11 @@ def test_full_size(builder, kind):
     sampled_direct_check(t, sa)
 
 
-@pytest.mark.parametrize("items", [8, 12, 16, 20, 24])
-def test_sort_tile_variants(builder, items):
+@pytest.mark.parametrize("items,block", [(8, 256), (12, 256), (16, 256), (20, 256), (24, 256),
+                                         (4, 512), (8, 512), (12, 512)])
+def test_sort_tile_variants(builder, items, block):
     """Every radix-sort tile shape sorts stably and builds the same SA."""
-    builder.set_tuning(sort_items=items)
+    builder.set_tuning(sort_items=items, sort_block=block)
     try:
         rng = np.random.default_rng(items)
         count = 100003
@@ -288,6 +289,8 @@ def test_tuning_rejects_bad_values(builder):
     from paper_1610_03007_amd import SAError
     with pytest.raises(SAError):
         builder.set_tuning(sort_items=10)
+    with pytest.raises(SAError):
+        builder.set_tuning(sort_items=16, sort_block=512)
     with pytest.raises(SAError):
         builder.set_tuning(lazy_ratio=1)
     assert builder.tuning()["sort_items"] in (8, 12, 16, 20, 24)

@@ -65,7 +65,10 @@ def test_knobs_round_trip(tmp_path):
     p = write(tmp_path, [entry(sort_items=12, sort_wgs_per_cu=6, lazy_ratio=64, round0_full=1)])
     found, t = _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)
     assert found
-    assert t == {"sort_items": 12, "sort_wgs_per_cu": 6, "lazy_ratio": 64, "round0_full": 1}
+    assert t == {"sort_items": 12, "sort_wgs_per_cu": 6, "lazy_ratio": 64, "round0_full": 1,
+                 "sort_block": 256}
+    p = write(tmp_path, [entry(sort_items=8, sort_block=512)])
+    assert _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)[1]["sort_block"] == 512
 
 
 @pytest.mark.parametrize("bad", [
@@ -80,11 +83,12 @@ def test_malformed_files_are_rejected(tmp_path, bad):
         _native.tune_lookup(str(p), "gfx950", "single", 1 << 20)
 
 
-@pytest.mark.parametrize("knob,value", [("sort_items", 10), ("lazy_ratio", 2),
-                                        ("round0_full", 2), ("sort_wgs_per_cu", 17),
-                                        ("log2n", 64), ("mode", "serve")])
-def test_invalid_knobs_are_rejected(tmp_path, knob, value):
-    p = write(tmp_path, [entry(**{knob: value})])
+@pytest.mark.parametrize("knob", [{"sort_items": 10}, {"lazy_ratio": 2}, {"round0_full": 2},
+                                  {"sort_wgs_per_cu": 17}, {"log2n": 64}, {"mode": "serve"},
+                                  {"sort_block": 384}, {"sort_block": 512, "sort_items": 16},
+                                  {"sort_items": 4}])
+def test_invalid_knobs_are_rejected(tmp_path, knob):
+    p = write(tmp_path, [entry(**knob)])
     with pytest.raises(SAError):
         _native.tune_lookup(p, "gfx950", "single", 1 << 28)
 
@@ -105,7 +109,7 @@ def test_autotune_save_and_reuse(tmp_path):
     try:
         best, ms = b.tune(d, reps=1)
         assert ms > 0
-        assert best["sort_items"] in (8, 12, 16, 20, 24)
+        assert best["sort_items"] in (4, 8, 12, 16, 20, 24) and best["sort_block"] in (256, 512)
         b.save_tuning()
         doc = json.load(open(path))
         assert doc["format"] == FORMAT and len(doc["entries"]) == 1
