@@ -66,6 +66,7 @@ struct sa_ctx {
   SortPlan* plan = nullptr;
   u32* present = nullptr;
   u16* code = nullptr;
+  u64* sample = nullptr;  // lazy ISA: sampled round-0 sorted keys
   // Pinned readback area: counters copy + per-sort plan flags.
   u64* h_counters = nullptr;
   u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][3 * kMaxPasses]
@@ -104,7 +105,9 @@ constexpr size_t kSmallCounters = size_t(kCtrCount) * sizeof(u64);
 constexpr size_t kSmallPlan = (sizeof(SortPlan) + 255) / 256 * 256;
 constexpr size_t kSmallPresent = 256 * sizeof(u32);
 constexpr size_t kSmallCode = 256 * sizeof(u16);
-constexpr size_t kSmallBytes = kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent + kSmallCode;
+constexpr size_t kSmallSample = size_t(kLazySamples) * sizeof(u64);
+constexpr size_t kSmallBytes =
+    kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent + kSmallCode + kSmallSample;
 constexpr int kPlanFlagWords = 3 * kMaxPasses + 1;  // skip, src, iota, final_buf
 
 

@@ -277,6 +277,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
       Tracer t(c, s, SA_KERNEL_OTHER, double(n) * 4.0 + double(active) * 12.0);
       launch_fill_u32(c->isa, n, 0, s);
       launch_isa_scatter_list(c->act_idx, c->act_rank, active, n, c->isa, s);
+      launch_lazy_sample(keys0, n, c->sample, s);
     } else {
       Tracer t(c, s, SA_KERNEL_ISA_SCATTER, double(n) * 12.0);
       launch_isa_scatter_sorted(c->valsA, c->valsB, c->plan, n, c->isa, s);
@@ -303,7 +304,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
       Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
       if (lazy)
         launch_pack_pairs_lazy(c->act_idx, c->act_rank, active, n, h, b, c->isa, text, c->code,
-                               c->counters, keys0, later.kA, later.vA, s);
+                               c->counters, keys0, c->sample, later.kA, later.vA, s);
       else
         launch_pack_pairs(c->act_idx, c->act_rank, active, n, h, b, c->isa, later.kA, later.vA,
                           s);
@@ -321,7 +322,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
     active = c->h_counters[kCtrActive];
   }
   if (d_isa) {
-    if (lazy) launch_isa_complete(c->isa, n, text, c->code, c->counters, keys0, s);
+    if (lazy) launch_isa_complete(c->isa, n, text, c->code, c->counters, keys0, c->sample, s);
     if (hipMemcpyAsync(d_isa, c->isa, n * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess)
       return SA_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return SA_EDEVICE;
@@ -404,6 +405,8 @@ sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
   c->plan = reinterpret_cast<SortPlan*>(p + kSmallHist + kSmallCounters);
   c->present = reinterpret_cast<u32*>(p + kSmallHist + kSmallCounters + kSmallPlan);
   c->code = reinterpret_cast<u16*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent);
+  c->sample = reinterpret_cast<u64*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent +
+                                     kSmallCode);
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_counters), kCtrCount * sizeof(u64)) !=
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_plans),

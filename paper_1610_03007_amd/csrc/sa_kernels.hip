@@ -376,9 +376,15 @@ __global__ __launch_bounds__(kRadix) void radix_plan_kernel(const u32* __restric
   u64 own[kMaxPasses];
 #pragma unroll
   for (int p = 0; p < kMaxPasses; ++p) {
+    // All chunk counts of the pass are requested at once (unrolled, predicated).
+    u32 part[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c)
+      part[c] = (p < npass && u32(c) < nchunks) ? hist_in[(size_t(p) * kChunks + c) * kRadix + d]
+                                                : 0u;
     u64 h = 0;
-    if (p < npass)
-      for (u32 c = 0; c < nchunks; ++c) h += hist_in[(size_t(p) * kChunks + c) * kRadix + d];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) h += part[c];
     own[p] = h;
     sc[p][d] = h;
     if (p < npass && h == count) s_skip[p] = 1;  // one digit holds every key
@@ -984,16 +990,29 @@ void launch_isa_scatter_list(const u32* idx, const u32* rank, u64 count, u64 n, 
 namespace {
 
 // Round-0 name of suffix j: its packed key and a lower-bound search in the
-// round-0 sorted keys.
+// round-0 sorted keys. The search starts in `sample` (kLazySamples keys of the
+// sorted array, sample[i] = keys0[i * n / kLazySamples], staged in LDS), which
+// narrows it to a range of n / kLazySamples keys before the global steps.
 __device__ inline u32 round0_rank(u64 j, const u8* __restrict__ text, u64 n,
                                   const u16* __restrict__ code, u32 w, u32 c,
-                                  const u64* __restrict__ keys0) {
+                                  const u64* __restrict__ keys0, const u64* __restrict__ sample) {
   u64 k = 0;
   for (u32 q = 0; q < c; ++q) {
     const u64 p = j + q;
     k = (k << w) | u64(p < n ? code[text[p]] : u16(0));
   }
-  u64 lo = 0, hi = n;
+  // First sample not below k.
+  u32 slo = 0, shi = kLazySamples;
+  while (slo < shi) {
+    const u32 mid = (slo + shi) >> 1;
+    if (sample[mid] < k)
+      slo = mid + 1;
+    else
+      shi = mid;
+  }
+  // keys0[pos(slo - 1)] < k <= keys0[pos(slo)]: the lower bound lies between.
+  u64 lo = slo ? (u64(slo - 1) * n) / kLazySamples + 1 : 0;
+  u64 hi = slo < kLazySamples ? (u64(slo) * n) / kLazySamples : n;
   while (lo < hi) {
     const u64 mid = (lo + hi) >> 1;
     if (keys0[mid] < k)
@@ -1006,13 +1025,27 @@ __device__ inline u32 round0_rank(u64 j, const u8* __restrict__ text, u64 n,
 
 }  // namespace
 
+__global__ __launch_bounds__(256) void lazy_sample_kernel(const u64* __restrict__ keys0, u64 n,
+                                                          u64* __restrict__ sample) {
+  const u32 i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kLazySamples) sample[i] = keys0[(u64(i) * n) / kLazySamples];
+}
+
+void launch_lazy_sample(const u64* keys0, u64 n, u64* sample, hipStream_t s) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(lazy_sample_kernel, dim3(kLazySamples / 256), dim3(256), 0, s, keys0, n,
+                     sample);
+}
+
 __global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
     const u32* __restrict__ act_idx, const u32* __restrict__ act_rank, u64 count, u64 n, u64 h,
     int b, const u32* __restrict__ isa, const u8* __restrict__ text, const u16* __restrict__ code,
-    const u64* __restrict__ counters, const u64* __restrict__ keys0, u64* __restrict__ keys,
-    u32* __restrict__ vals) {
+    const u64* __restrict__ counters, const u64* __restrict__ keys0,
+    const u64* __restrict__ sample, u64* __restrict__ keys, u32* __restrict__ vals) {
   __shared__ u16 s_code[256];
+  __shared__ u64 s_sample[kLazySamples];
   s_code[threadIdx.x] = code[threadIdx.x];
+  for (u32 i = threadIdx.x; i < kLazySamples; i += 256) s_sample[i] = sample[i];
   __syncthreads();
   u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   if (p >= count) return;
@@ -1024,7 +1057,7 @@ __global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
   u32 r1 = 0;
   if (j < n) {
     r1 = isa[j];
-    if (r1 == 0) r1 = round0_rank(j, text, n, s_code, w, c, keys0);
+    if (r1 == 0) r1 = round0_rank(j, text, n, s_code, w, c, keys0, s_sample);
   }
   keys[p] = (u64(r) << b) | u64(r1);
   vals[p] = i;
@@ -1032,11 +1065,12 @@ __global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
 
 void launch_pack_pairs_lazy(const u32* act_idx, const u32* act_rank, u64 count, u64 n, u64 h,
                             int b, const u32* isa, const u8* text, const u16* code,
-                            const u64* counters, const u64* keys0, u64* keys, u32* vals,
-                            hipStream_t s) {
+                            const u64* counters, const u64* keys0, const u64* sample, u64* keys,
+                            u32* vals, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(pack_pairs_lazy_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
-                     act_idx, act_rank, count, n, h, b, isa, text, code, counters, keys0, keys,
+                     act_idx, act_rank, count, n, h, b, isa, text, code, counters, keys0, sample,
+                     keys,
                      vals);
 }
 
@@ -1044,23 +1078,26 @@ __global__ __launch_bounds__(256) void isa_complete_kernel(u32* __restrict__ isa
                                                            const u8* __restrict__ text,
                                                            const u16* __restrict__ code,
                                                            const u64* __restrict__ counters,
-                                                           const u64* __restrict__ keys0) {
+                                                           const u64* __restrict__ keys0,
+                                                           const u64* __restrict__ sample) {
   __shared__ u16 s_code[256];
+  __shared__ u64 s_sample[kLazySamples];
   s_code[threadIdx.x] = code[threadIdx.x];
+  for (u32 i = threadIdx.x; i < kLazySamples; i += 256) s_sample[i] = sample[i];
   __syncthreads();
   u64 j = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n) return;
   if (isa[j] != 0) return;
   const u32 w = u32(counters[kCtrCodeBits]);
   const u32 c = u32(counters[kCtrChars]);
-  isa[j] = round0_rank(j, text, n, s_code, w, c, keys0);
+  isa[j] = round0_rank(j, text, n, s_code, w, c, keys0, s_sample);
 }
 
 void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const u64* counters,
-                         const u64* keys0, hipStream_t s) {
+                         const u64* keys0, const u64* sample, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(isa_complete_kernel, dim3(u32(ceil_div(n, 256))), dim3(256), 0, s, isa, n,
-                     text, code, counters, keys0);
+                     text, code, counters, keys0, sample);
 }
 
 // ---------------------------------------------------------------------------
