@@ -912,7 +912,10 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
       bad = true;
       continue;
     }
-    if (scatter) isa[gb + v[r]] = u32(nr);
+    // The ISA already holds every active suffix's previous name, so a name
+    // that did not change (a group that did not split, or the first sub-group
+    // of one that did) is not written again.
+    if (scatter && (first_round || nr != r0)) isa[gb + v[r]] = u32(nr);
     if (write_ranks) ranks_out[e] = u32(nr);
     if (uniq) {
       sa_out[gb + nr - 1] = v[r];
