@@ -55,7 +55,6 @@ constexpr int kRadix = 1 << kRadixBits;
 constexpr int kMaxPasses = 64 / kRadixBits;
 
 struct SortPlan {
-  u64 offsets[kMaxPasses][kRadix];  // exclusive global start of each digit
   u32 skip[kMaxPasses];             // pass p is skipped (its digit is constant)
   u32 src[kMaxPasses];              // buffer pass p reads (0 = A, 1 = B)
   u32 iota[kMaxPasses];             // pass p generates values = input index
@@ -68,7 +67,8 @@ struct SortPlan {
 // independent look-back chains. The digit counts of every chunk are known
 // before the sweep starts (for the first sweep from the up-front histogram,
 // for later ones accumulated by the sweep before), so a chunk's first tile
-// never waits on another chunk.
+// never waits on another chunk; summed over the chunks they also give the
+// sweep its global digit offsets.
 constexpr int kChunks = 32;
 
 // Workgroup and tile shapes.
@@ -84,12 +84,13 @@ constexpr int kRerankTile = kRerankBlock * kRerankRows;  // 4096 elements
 // Device-side 64-bit counters shared by one build (slot indices).
 enum CounterSlot : int {
   kCtrSortTiles = 0,                 // kMaxPasses slots: tile tickets per pass
-  kCtrRerankTiles = kMaxPasses,      // spare (cleared with the sort tickets)
-  kCtrActive = kMaxPasses + 1,       // survivors written by the last re-rank (atomic sum)
-  kCtrError = kMaxPasses + 2,        // error bits (kErr*)
-  kCtrSigma = kMaxPasses + 3,        // distinct bytes in the text
-  kCtrCodeBits = kMaxPasses + 4,     // w: bits per character code
-  kCtrChars = kMaxPasses + 5,        // c: characters packed in a round-0 key
+  kCtrKeyOr = kMaxPasses,            // OR of the keys being sorted
+  kCtrKeyNot = kMaxPasses + 1,       // OR of their complements (a digit varies where both are set)
+  kCtrActive = kMaxPasses + 2,       // survivors written by the last re-rank (atomic sum)
+  kCtrError = kMaxPasses + 3,        // error bits (kErr*)
+  kCtrSigma = kMaxPasses + 4,        // distinct bytes in the text
+  kCtrCodeBits = kMaxPasses + 5,     // w: bits per character code
+  kCtrChars = kMaxPasses + 6,        // c: characters packed in a round-0 key
   kCtrCount = kMaxPasses + 8,
 };
 

@@ -38,14 +38,19 @@ struct SortGeom {
   u32 ct_log2;
   u32 nchunks;
 };
-// hist_in [kMaxPasses][kChunks][kRadix] must be zero on entry; it receives the
-// digit counts of every pass per chunk of the input.
-void launch_radix_histogram(const u64* keys, const SortGeom& geo, int npass, u32* hist_in,
+// hist_in [kMaxPasses][kChunks][kRadix] must be zero on entry, and
+// counters[kCtrKeyOr], counters[kCtrKeyNot] zero. Receives the per-chunk
+// counts of digits 0 and 1 and the OR of the keys and of their complements.
+void launch_radix_histogram(const u64* keys, const SortGeom& geo, u32* hist_in, u64* counters,
                             hipStream_t s);
-// Offsets, skipped passes and the buffer schedule. With vals_present == 0 the
-// first sweep generates the values (input index).
-void launch_radix_plan(const u32* hist_in, const SortGeom& geo, int npass, int vals_present,
-                       SortPlan* plan, hipStream_t s);
+// Skipped passes (constant digits, from the two ORs) and the buffer schedule.
+// With vals_present == 0 the first sweep generates the values (input index).
+void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPlan* plan,
+                       hipStream_t s);
+// Per-chunk counts of the first sweep's digit when it is above digit 1 (a
+// no-op otherwise, decided on the device from the plan).
+void launch_radix_histogram_first(const u64* keys, const SortGeom& geo, const SortPlan* plan,
+                                  u32* hist_in, hipStream_t s);
 // One sweep. hist_run [kMaxPasses][kChunks][kRadix] and tickets
 // [kMaxPasses][kChunks] must be zero before the first sweep of a sort. `items`
 // per thread (8, 12, 16, 20 or 24 with 256-thread workgroups; 4, 8 or 12 with

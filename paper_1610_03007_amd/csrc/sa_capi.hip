@@ -135,17 +135,21 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
   const SortGeom geo = make_geom(count, c->sort_items, c->sort_block);
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    // Chunk histograms and tickets; the survivor count the re-rank adds to.
+    // Chunk histograms and tickets; tile tickets, the key ORs and the
+    // survivor count the re-rank adds to.
+    static_assert(kCtrSortTiles < kCtrActive && kCtrKeyOr < kCtrActive && kCtrKeyNot < kCtrActive,
+                  "one fill clears the sort's counters");
     launch_fill_u32(c->hist_in, 2 * kChunkHistWords + kTicketWords, 0, s);
     launch_fill_u64(c->counters, kCtrActive + 1, 0, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_HISTOGRAM, double(count) * 8.0);
-    launch_radix_histogram(bf.kA, geo, npass, c->hist_in, s);
+    launch_radix_histogram(bf.kA, geo, c->hist_in, c->counters, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    launch_radix_plan(c->hist_in, geo, npass, vals_present, c->plan, s);
+    launch_radix_plan(c->counters, npass, vals_present, c->plan, s);
+    launch_radix_histogram_first(bf.kA, geo, c->plan, c->hist_in, s);
   }
   (void)hipMemcpyAsync(c->h_plans + size_t(slot) * kPlanFlagWords, c->plan->skip,
                        kPlanFlagWords * sizeof(u32), hipMemcpyDeviceToHost, s);

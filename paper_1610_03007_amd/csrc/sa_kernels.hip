@@ -29,6 +29,16 @@ __device__ inline u32 wave_inclusive_sum(u32 v) {
   return v;
 }
 
+__device__ inline u64 wave_inclusive_sum64(u64 v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    u64 t = __shfl_up(v, off, kWave);
+    if (lane >= off) v += t;
+  }
+  return v;
+}
+
 // Look back over earlier tiles of a single-pass scan and return the exclusive
 // prefix for `tile` (tile > 0). `op_max` selects max instead of sum. Publishes
 // the inclusive prefix. Bounded: on time-out raises kErrLookbackTimeout and
@@ -298,14 +308,19 @@ void launch_pack_pairs(const u32* act_idx, const u32* act_rank, u64 count, u64 n
 
 constexpr int kHistItems = 8;
 
-// Up-front digit histograms of every planned pass, per chunk of the input
-// (chunk c = tiles [c << ct_log2, (c + 1) << ct_log2)). Block b counts a
-// contiguous share of chunk b / per_chunk.
+// Up-front counts of a sort, per chunk of the input (chunk c = tiles
+// [c << ct_log2, (c + 1) << ct_log2)): the digit counts of passes 0 and 1 (the
+// first sweep's digit whenever one of them varies) and, over all keys, the OR
+// of the keys and of their complements, which tell the plan which digits are
+// constant. Later sweeps get their chunk counts from the sweep before them.
+// Block b counts a contiguous share of chunk b / per_chunk.
 __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
-    const u64* __restrict__ keys, u64 count, int npass, u64 chunk_elems, u32 nchunks,
-    u32 per_chunk, u32* __restrict__ hist_in) {
-  __shared__ u32 lh[kMaxPasses * kRadix];
-  for (int i = threadIdx.x; i < kMaxPasses * kRadix; i += kHistBlock) lh[i] = 0;
+    const u64* __restrict__ keys, u64 count, u64 chunk_elems, u32 nchunks, u32 per_chunk,
+    u32* __restrict__ hist_in, u64* __restrict__ counters) {
+  constexpr int NP = 2;
+  __shared__ u32 lh[NP * kRadix];
+  __shared__ u64 s_or[kHistBlock / kWave], s_not[kHistBlock / kWave];
+  for (int i = threadIdx.x; i < NP * kRadix; i += kHistBlock) lh[i] = 0;
   __syncthreads();
   const u32 c = blockIdx.x / per_chunk;
   const u32 g = blockIdx.x % per_chunk;
@@ -314,6 +329,7 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
   if (ce > count) ce = count;
   const int lane = lane_id();
   const u64 step = u64(kHistBlock) * kHistItems;
+  u64 kor = 0, knot = 0;
   for (u64 base = cs + u64(g) * step; base < ce; base += u64(per_chunk) * step) {
     u64 key[kHistItems];
     bool valid[kHistItems];
@@ -322,12 +338,17 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
       const u64 e = base + u64(j) * kHistBlock + threadIdx.x;
       valid[j] = e < ce;
       key[j] = valid[j] ? keys[e] : 0;
+      if (valid[j]) {
+        kor |= key[j];
+        knot |= ~key[j];
+      }
     }
 #pragma unroll
     for (int j = 0; j < kHistItems; ++j) {
       const u64 vmask = __ballot(valid[j]);
       if (vmask == 0) continue;  // wave-uniform
-      for (int p = 0; p < npass; ++p) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
         const u32 d = u32(key[j] >> (p * kRadixBits)) & (kRadix - 1);
         // Valid lanes form a prefix of the wave, so lane 0 is valid here.
         const u32 d0 = __shfl(d, 0, kWave);
@@ -340,101 +361,134 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
       }
     }
   }
+#pragma unroll
+  for (int off = kWave / 2; off >= 1; off >>= 1) {
+    kor |= __shfl_xor(kor, off, kWave);
+    knot |= __shfl_xor(knot, off, kWave);
+  }
+  if (lane == 0) {
+    s_or[threadIdx.x / kWave] = kor;
+    s_not[threadIdx.x / kWave] = knot;
+  }
   __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 o = 0, n = 0;
+    for (int w = 0; w < kHistBlock / kWave; ++w) {
+      o |= s_or[w];
+      n |= s_not[w];
+    }
+    if (o) atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrKeyOr),
+                    (unsigned long long)o);
+    if (n) atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrKeyNot),
+                    (unsigned long long)n);
+  }
   if (c >= nchunks) return;
-  for (int i = threadIdx.x; i < npass * kRadix; i += kHistBlock) {
+  for (int i = threadIdx.x; i < NP * kRadix; i += kHistBlock) {
     const u32 v = lh[i];
     const int p = i / kRadix, d = i % kRadix;
     if (v) atomicAdd(&hist_in[(size_t(p) * kChunks + c) * kRadix + d], v);
   }
 }
 
-void launch_radix_histogram(const u64* keys, const SortGeom& geo, int npass, u32* hist_in,
-                            hipStream_t s) {
-  if (geo.count == 0) return;
-  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
+// Per-chunk counts of digit plan->first_run when it is 2 or above (keys whose
+// two lowest digits are constant); returns at once otherwise.
+__global__ __launch_bounds__(kHistBlock) void radix_histogram_first_kernel(
+    const u64* __restrict__ keys, u64 count, u64 chunk_elems, u32 nchunks, u32 per_chunk,
+    const SortPlan* __restrict__ plan, u32* __restrict__ hist_in) {
+  const u32 p = plan->first_run;
+  if (p < 2) return;
+  __shared__ u32 lh[kRadix];
+  for (int i = threadIdx.x; i < kRadix; i += kHistBlock) lh[i] = 0;
+  __syncthreads();
+  const u32 c = blockIdx.x / per_chunk;
+  const u32 g = blockIdx.x % per_chunk;
+  const u64 cs = u64(c) * chunk_elems;
+  u64 ce = cs + chunk_elems;
+  if (ce > count) ce = count;
+  const u64 step = u64(kHistBlock) * kHistItems;
+  for (u64 base = cs + u64(g) * step; base < ce; base += u64(per_chunk) * step) {
+#pragma unroll
+    for (int j = 0; j < kHistItems; ++j) {
+      const u64 e = base + u64(j) * kHistBlock + threadIdx.x;
+      if (e < ce) atomicAdd(&lh[u32(keys[e] >> (p * kRadixBits)) & (kRadix - 1)], 1u);
+    }
+  }
+  __syncthreads();
+  if (c >= nchunks) return;
+  for (int d = threadIdx.x; d < kRadix; d += kHistBlock) {
+    const u32 v = lh[d];
+    if (v) atomicAdd(&hist_in[(size_t(p) * kChunks + c) * kRadix + d], v);
+  }
+}
+
+namespace {
+
+// Blocks of a histogram launch: a few per chunk, at most about 2048 in all.
+u64 hist_blocks_per_chunk(const SortGeom& geo, u64 chunk_elems) {
   u64 per = ceil_div(chunk_elems, u64(kHistBlock) * kHistItems * 4);
   const u64 cap = ceil_div(2048, geo.nchunks);
   if (per > cap) per = cap;
   if (per < 1) per = 1;
+  return per;
+}
+
+}  // namespace
+
+void launch_radix_histogram(const u64* keys, const SortGeom& geo, u32* hist_in, u64* counters,
+                            hipStream_t s) {
+  if (geo.count == 0) return;
+  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
+  const u64 per = hist_blocks_per_chunk(geo, chunk_elems);
   hipLaunchKernelGGL(radix_histogram_kernel, dim3(u32(per * geo.nchunks)), dim3(kHistBlock), 0, s,
-                     keys, geo.count, npass, chunk_elems, geo.nchunks, u32(per), hist_in);
+                     keys, geo.count, chunk_elems, geo.nchunks, u32(per), hist_in, counters);
 }
 
-// Global digit offsets per pass (sums of the chunk histograms), constant-digit
-// passes marked skipped, and the ping-pong schedule of the passes that run.
-// One workgroup, one thread per digit value.
-__global__ __launch_bounds__(kRadix) void radix_plan_kernel(const u32* __restrict__ hist_in,
-                                                            u32 nchunks, u64 count, int npass,
-                                                            int vals_present,
-                                                            SortPlan* __restrict__ plan) {
-  __shared__ u64 sc[kMaxPasses][kRadix];
-  __shared__ u32 s_skip[kMaxPasses];
-  const int d = threadIdx.x;
-  if (d < kMaxPasses) s_skip[d] = 0;
-  __syncthreads();
-  u64 own[kMaxPasses];
-#pragma unroll
+void launch_radix_histogram_first(const u64* keys, const SortGeom& geo, const SortPlan* plan,
+                                  u32* hist_in, hipStream_t s) {
+  if (geo.count == 0) return;
+  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
+  const u64 per = hist_blocks_per_chunk(geo, chunk_elems);
+  hipLaunchKernelGGL(radix_histogram_first_kernel, dim3(u32(per * geo.nchunks)), dim3(kHistBlock),
+                     0, s, keys, geo.count, chunk_elems, geo.nchunks, u32(per), plan, hist_in);
+}
+
+// The sort plan: which digits vary (the others are skipped), which buffer each
+// pass reads, where values are generated and where the output ends.
+__global__ void radix_plan_kernel(const u64* __restrict__ counters, int npass, int vals_present,
+                                  SortPlan* __restrict__ plan) {
+  if (threadIdx.x != 0) return;
+  const u64 varying = counters[kCtrKeyOr] & counters[kCtrKeyNot];
+  u32 run[kMaxPasses];
+  u32 nrun = 0;
   for (int p = 0; p < kMaxPasses; ++p) {
-    // All chunk counts of the pass are requested at once (unrolled, predicated).
-    u32 part[kChunks];
-#pragma unroll
-    for (int c = 0; c < kChunks; ++c)
-      part[c] = (p < npass && u32(c) < nchunks) ? hist_in[(size_t(p) * kChunks + c) * kRadix + d]
-                                                : 0u;
-    u64 h = 0;
-#pragma unroll
-    for (int c = 0; c < kChunks; ++c) h += part[c];
-    own[p] = h;
-    sc[p][d] = h;
-    if (p < npass && h == count) s_skip[p] = 1;  // one digit holds every key
+    run[p] = (p < npass && ((varying >> (p * kRadixBits)) & (kRadix - 1)) != 0) ? 1u : 0u;
+    nrun += run[p];
   }
-  __syncthreads();
-  // Hillis-Steele inclusive scans over the digits of every pass at once.
-  for (int off = 1; off < kRadix; off <<= 1) {
-    u64 add[kMaxPasses];
-#pragma unroll
-    for (int p = 0; p < kMaxPasses; ++p) add[p] = (d >= off) ? sc[p][d - off] : 0;
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < kMaxPasses; ++p) sc[p][d] += add[p];
-    __syncthreads();
-  }
-#pragma unroll
-  for (int p = 0; p < kMaxPasses; ++p) plan->offsets[p][d] = sc[p][d] - own[p];
-  if (d == 0) {
-    u32 run[kMaxPasses];
-    u32 nrun = 0;
-    for (int p = 0; p < kMaxPasses; ++p) {
-      run[p] = (p < npass && !s_skip[p]) ? 1u : 0u;
-      nrun += run[p];
+  if (nrun == 0) run[npass - 1] = 1;  // all keys equal: one stable copy pass
+  u32 cur = 0;
+  bool first = true;
+  int prev = -1;
+  for (int p = 0; p < kMaxPasses; ++p) {
+    plan->skip[p] = run[p] ? 0u : 1u;
+    plan->src[p] = cur;
+    plan->iota[p] = 0;
+    plan->next_run[p] = -1;
+    if (run[p]) {
+      plan->iota[p] = (!vals_present && first) ? 1u : 0u;
+      if (first) plan->first_run = u32(p);
+      if (prev >= 0) plan->next_run[prev] = p;
+      first = false;
+      prev = p;
+      cur ^= 1u;
     }
-    if (nrun == 0) run[npass - 1] = 1;  // all keys equal: one stable copy pass
-    u32 cur = 0;
-    bool first = true;
-    int prev = -1;
-    for (int p = 0; p < kMaxPasses; ++p) {
-      plan->skip[p] = run[p] ? 0u : 1u;
-      plan->src[p] = cur;
-      plan->iota[p] = 0;
-      plan->next_run[p] = -1;
-      if (run[p]) {
-        plan->iota[p] = (!vals_present && first) ? 1u : 0u;
-        if (first) plan->first_run = u32(p);
-        if (prev >= 0) plan->next_run[prev] = p;
-        first = false;
-        prev = p;
-        cur ^= 1u;
-      }
-    }
-    plan->final_buf = cur;
   }
+  plan->final_buf = cur;
 }
 
-void launch_radix_plan(const u32* hist_in, const SortGeom& geo, int npass, int vals_present,
-                       SortPlan* plan, hipStream_t s) {
-  hipLaunchKernelGGL(radix_plan_kernel, dim3(1), dim3(kRadix), 0, s, hist_in, geo.nchunks,
-                     geo.count, npass, vals_present, plan);
+void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPlan* plan,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(radix_plan_kernel, dim3(1), dim3(kWave), 0, s, counters, npass,
+                     vals_present, plan);
 }
 
 // One stable counting sweep over digit `pass`, persistent: workgroup b works on
@@ -470,6 +524,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
   __shared__ u64 s_base[kRadix];
   __shared__ u64 s_cbase[kRadix];
   __shared__ u32 s_wsum[DW];
+  __shared__ u64 s_tsum[DW];
   __shared__ u32 s_ticket;
   __shared__ u32 s_abort;
 
@@ -495,13 +550,32 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
 
   // Start of each digit's output range for this chunk: global digit offset
   // plus that digit's count in the earlier chunks.
+  // Where this chunk's run of each digit starts: the digit's global start (its
+  // count over all chunks, scanned over the digits) plus its count in the
+  // earlier chunks.
   const bool digit_owner = tid < kRadix;  // thread tid owns digit tid
+  u64 total = 0, below = 0, inc64 = 0;
   if (digit_owner) {
     const u32* h = (u32(pass) == plan->first_run ? hist_in : hist_run) +
                    size_t(pass) * kChunks * kRadix;
-    u64 b = plan->offsets[pass][tid];
-    for (u32 c = 0; c < chunk; ++c) b += h[c * kRadix + tid];
-    s_cbase[tid] = b;
+    u32 part[kChunks];
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) part[c] = u32(c) < nchunks ? h[c * kRadix + tid] : 0u;
+#pragma unroll
+    for (int c = 0; c < kChunks; ++c) {
+      total += part[c];
+      if (u32(c) < chunk) below += part[c];
+    }
+    inc64 = wave_inclusive_sum64(total);
+    if (lane == kWave - 1) s_tsum[wave] = inc64;
+  }
+  __syncthreads();
+  if (digit_owner) {
+    u64 woff = 0;
+#pragma unroll
+    for (int w = 0; w < DW; ++w)
+      if (w < wave) woff += s_tsum[w];
+    s_cbase[tid] = woff + inc64 - total + below;
   }
   for (int i = tid; i < kChunks * kRadix; i += BLOCK) s_next[i] = 0;
 
