@@ -230,50 +230,88 @@ void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int tri
 // slides a c-character window over kPackItems consecutive positions.
 
 constexpr int kPackBlock = 256;
-constexpr int kPackItems = 8;
+constexpr int kPackItems = 8;  // multi-text packing: one 2048-position chunk per workgroup
 constexpr int kPackTile = kPackBlock * kPackItems;
 constexpr int kPackHalo = 64;  // c <= 64
+constexpr int kPackTextItems = 16;  // single text
+constexpr int kPackTextTile = kPackBlock * kPackTextItems;
 
+// LDS index of item j of thread t in a [threads][items] key array padded to
+// items + 1 per thread, so that both the per-thread writes (stride items + 1
+// words of 8 bytes) and the coalesced reads spread over the banks.
+template <int ITEMS>
+__device__ inline int pad_out(int t, int j) {
+  return t * (ITEMS + 1) + j;
+}
+
+// Round-0 keys: thread t rolls the keys of kPackTextItems consecutive positions
+// (c codes for the first, one more for each next key) from the tile's codes
+// staged in LDS; the keys leave through LDS in coalesced order. The text is
+// read as 4-byte words when it is 4-byte aligned.
 __global__ __launch_bounds__(kPackBlock) void pack_text_kernel(const u8* __restrict__ text, u64 n,
+                                                               int words,
                                                                const u16* __restrict__ code,
                                                                const u64* __restrict__ counters,
                                                                u64* __restrict__ keys) {
+  constexpr int IT = kPackTextItems;
+  constexpr int TILE = kPackTextTile;
   __shared__ u16 s_code[256];
-  __shared__ u16 s_sym[kPackTile + kPackHalo];
-  __shared__ u64 s_out[kPackTile];
+  __shared__ u16 s_sym[TILE + kPackHalo];
+  __shared__ u64 s_out[kPackBlock * (IT + 1)];
   const int t = threadIdx.x;
-  const u64 base = u64(blockIdx.x) * kPackTile;
+  const u64 base = u64(blockIdx.x) * TILE;
   const u32 w = u32(counters[kCtrCodeBits]);
   const u32 c = u32(counters[kCtrChars]);
   s_code[t] = code[t];
   __syncthreads();
-  for (int i = t; i < kPackTile + kPackHalo; i += kPackBlock) {
-    u64 p = base + u64(i);
-    s_sym[i] = (p < n) ? s_code[text[p]] : u16(0);
+  if (words && base + TILE + kPackHalo <= n) {
+    const u32* tw = reinterpret_cast<const u32*>(text + base);
+    for (int q = t; q < (TILE + kPackHalo) / 4; q += kPackBlock) {
+      const u32 v = tw[q];
+      s_sym[4 * q] = s_code[v & 0xFFu];
+      s_sym[4 * q + 1] = s_code[(v >> 8) & 0xFFu];
+      s_sym[4 * q + 2] = s_code[(v >> 16) & 0xFFu];
+      s_sym[4 * q + 3] = s_code[v >> 24];
+    }
+  } else {
+    for (int i = t; i < TILE + kPackHalo; i += kPackBlock) {
+      const u64 p = base + u64(i);
+      s_sym[i] = (p < n) ? s_code[text[p]] : u16(0);
+    }
   }
   __syncthreads();
   const u64 keymask = (c * w >= 64) ? ~u64(0) : ((u64(1) << (c * w)) - 1);
-  const int first = t * kPackItems;
+  const int first = t * IT;
   u64 key = 0;
   for (u32 j = 0; j < c; ++j) key = (key << w) | u64(s_sym[first + int(j)]);
-  s_out[first] = key;
+  s_out[pad_out<IT>(t, 0)] = key;
 #pragma unroll
-  for (int j = 1; j < kPackItems; ++j) {
+  for (int j = 1; j < IT; ++j) {
     key = ((key << w) | u64(s_sym[first + j + int(c) - 1])) & keymask;
-    s_out[first + j] = key;
+    s_out[pad_out<IT>(t, j)] = key;
   }
   __syncthreads();
-  for (int i = t; i < kPackTile; i += kPackBlock) {
-    u64 p = base + u64(i);
-    if (p < n) keys[p] = s_out[i];
+  // Position i of the tile is item i % IT of thread i / IT.
+  if (base + TILE <= n) {
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const int i = j * kPackBlock + t;
+      keys[base + u64(i)] = s_out[pad_out<IT>(i / IT, i % IT)];
+    }
+  } else {
+    for (int i = t; i < TILE; i += kPackBlock) {
+      const u64 p = base + u64(i);
+      if (p < n) keys[p] = s_out[pad_out<IT>(i / IT, i % IT)];
+    }
   }
 }
 
 void launch_pack_text(const u8* text, u64 n, const u16* code, const u64* counters, u64* keys,
                       hipStream_t s) {
-  u64 blocks = ceil_div(n, kPackTile);
-  hipLaunchKernelGGL(pack_text_kernel, dim3(u32(blocks)), dim3(kPackBlock), 0, s, text, n, code,
-                     counters, keys);
+  u64 blocks = ceil_div(n, kPackTextTile);
+  const int words = (reinterpret_cast<uintptr_t>(text) & 3) == 0 ? 1 : 0;
+  hipLaunchKernelGGL(pack_text_kernel, dim3(u32(blocks)), dim3(kPackBlock), 0, s, text, n, words,
+                     code, counters, keys);
 }
 
 // ---------------------------------------------------------------------------
@@ -1310,7 +1348,7 @@ __global__ __launch_bounds__(kPackBlock) void multi_pack0_kernel(const u8* __res
   static_assert(kNewChunk == kPackTile, "one chunk per packing workgroup");
   __shared__ u16 s_code[256];
   __shared__ u16 s_sym[kPackTile + kPackHalo];
-  __shared__ u64 s_out[kPackTile];
+  __shared__ u64 s_out[kPackBlock * (kPackItems + 1)];
   const int th = threadIdx.x;
   const u64 b = blockIdx.x;
   const u32 i = new_text_of(nl.chunk0, nl.m, b);
@@ -1331,11 +1369,11 @@ __global__ __launch_bounds__(kPackBlock) void multi_pack0_kernel(const u8* __res
   const int first = th * kPackItems;
   u64 key = 0;
   for (u32 j = 0; j < c; ++j) key = (key << w) | u64(s_sym[first + int(j)]);
-  s_out[first] = key;
+  s_out[pad_out<kPackItems>(th, 0)] = key;
 #pragma unroll
   for (int j = 1; j < kPackItems; ++j) {
     key = ((key << w) | u64(s_sym[first + j + int(c) - 1])) & keymask;
-    s_out[first + j] = key;
+    s_out[pad_out<kPackItems>(th, j)] = key;
   }
   __syncthreads();
   const u64 tag = u64(t) << idshift;
@@ -1343,7 +1381,7 @@ __global__ __launch_bounds__(kPackBlock) void multi_pack0_kernel(const u8* __res
   for (int q = th; q < kPackTile; q += kPackBlock) {
     const u64 p = start + u64(q);
     if (p < len) {
-      keys[out + q] = tag | s_out[q];
+      keys[out + q] = tag | s_out[pad_out<kPackItems>(q / kPackItems, q % kPackItems)];
       vals[out + q] = u32(p);
     }
   }
