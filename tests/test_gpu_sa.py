@@ -214,12 +214,34 @@ def test_radix_sort_pairs(builder, bits, count):
     assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals[order])
 
 
-def test_radix_sort_all_equal(builder):
-    keys = np.full(50000, 12345, dtype=np.uint64)
-    vals = np.arange(50000, dtype=np.uint32)
+@pytest.mark.parametrize("low_const_bits", [8, 16, 24, 40])
+@pytest.mark.parametrize("count", [5000, 300001])
+def test_radix_sort_constant_low_digits(builder, low_const_bits, count):
+    """Keys whose lowest digits never vary: the first sweep that runs is above
+    digit 1, so its chunk counts come from the fallback histogram."""
+    rng = np.random.default_rng(low_const_bits + count)
+    tail = np.uint64(0xA5A5A5A5A5A5A5A5) & ((np.uint64(1) << np.uint64(low_const_bits)) -
+                                             np.uint64(1))
+    keys = (rng.integers(0, 2**(64 - low_const_bits), count, dtype=np.uint64)
+            << np.uint64(low_const_bits)) | tail
+    keys[::5] = keys[1]  # ties
+    vals = rng.integers(0, 2**32, count, dtype=np.uint64).astype(np.uint32)
+    order = np.argsort(keys, kind="stable")
     k_t, v_t = dev(keys.view(np.int64)), dev(vals.view(np.int32))
     builder.radix_sort_pairs(k_t, v_t, 64)
     torch.cuda.synchronize()
+    assert np.array_equal(k_t.cpu().numpy().view(np.uint64), keys[order])
+    assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals[order])
+
+
+@pytest.mark.parametrize("bits", [8, 16, 64])
+def test_radix_sort_all_equal(builder, bits):
+    keys = np.full(50000, 0xC5 if bits == 8 else 12345, dtype=np.uint64)
+    vals = np.arange(50000, dtype=np.uint32)
+    k_t, v_t = dev(keys.view(np.int64)), dev(vals.view(np.int32))
+    builder.radix_sort_pairs(k_t, v_t, bits)
+    torch.cuda.synchronize()
+    assert np.array_equal(k_t.cpu().numpy().view(np.uint64), keys)
     assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals)
 
 
@@ -245,6 +267,43 @@ def sampled_direct_check(t: np.ndarray, sa: np.ndarray, samples: int = 2000, see
                 break
             L *= 4
         assert tb[a:a + L] < tb[b:b + L] or (tb[a:a + L] == tb[b:b + L] and n - a < n - b), j
+
+
+def alphabet_text(kind: str, n: int, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    if kind == "all_bytes":      # 256 symbols: 9-bit codes, 6 characters per key
+        return rng.integers(0, 256, n, dtype=np.uint8)
+    if kind == "binary":         # 2 symbols: 2-bit codes, 28 characters per key
+        return rng.integers(0, 2, n, dtype=np.uint8) * np.uint8(0xFF)
+    if kind == "skewed":         # 0x00 most of the time, some rare bytes
+        t = np.zeros(n, np.uint8)
+        hits = rng.random(n) < 0.01
+        t[hits] = rng.integers(1, 256, int(hits.sum()), dtype=np.uint8)
+        return t
+    if kind == "unary":          # every round keeps every suffix active
+        return np.full(n, 0x41, np.uint8)
+    if kind == "dna_repeats":    # 1/8 of the text copied 8 times with rare changes
+        base = W.dna(n // 8, seed=seed)
+        t = np.tile(base, 8)[:n].copy()
+        flips = rng.random(n) < 1e-5
+        t[flips] = np.frombuffer(b"ACGT", np.uint8)[rng.integers(0, 4, int(flips.sum()))]
+        return t
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("kind", ["all_bytes", "binary", "skewed", "unary", "dna_repeats"])
+def test_alphabets_at_scale(builder, kind):
+    """2^22-byte texts over unusual alphabets and structures, element by element
+    against the oracle (unary: against its closed form)."""
+    n = 1 << 22
+    t = alphabet_text(kind, n, seed=11)
+    sa = gpu_sa(builder, t)
+    if kind == "unary":
+        assert np.array_equal(sa, np.arange(n - 1, -1, -1, dtype=np.uint32))
+    else:
+        assert np.array_equal(sa, oracle.sa(t, parallel=True))
+    info = builder.last_info()
+    assert info["n"] == n
 
 
 @pytest.mark.parametrize("kind", ["markov_256m", "repetitive_1g"])
