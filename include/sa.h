@@ -107,9 +107,9 @@ sa_status sa_server_destroy(sa_server* srv);
 sa_status sa_server_submit(sa_server* srv, const uint8_t* h_text, uint64_t n, uint64_t* ticket);
 /* *done = 1 once the request finished: its suffix array is copied to
  * h_sa_out[0, n) and the request is released. h_sa_out may be host memory
- * (pinned memory gets one direct copy) or device memory of the server's GPU; latency_ms (may be NULL)
- * receives the time from submit to the suffix array being complete on the
- * device. *done = 0 while it is queued or running. With h_sa_out NULL a
+ * (pinned memory gets one direct copy) or device memory of the server's GPU.
+ * latency_ms (may be NULL) receives the time from submit to the suffix array
+ * being complete on the device. *done = 0 while it is queued or running. With h_sa_out NULL a
  * finished request reports *done = 2 and stays until polled with a buffer.
  * A failed request returns its error once and is released; an unknown ticket
  * gives SA_EINVAL. */
@@ -162,14 +162,16 @@ sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, u
  * result is the same). Eager: one random 4-byte write per suffix. Lazy: only
  * the suffixes that survive round 0 are written, and a later round that needs
  * the round-0 name of another suffix recomputes it by binary search in the
- * round-0 sorted keys. Auto picks lazy when at most 1/8 of the suffixes
- * survive. Lazy needs the survivors to fit in spare workspace (at most n/3);
- * otherwise eager is used. */
+ * round-0 sorted keys. Auto picks lazy when at most 1/lazy_ratio of the
+ * suffixes survive (sa_tuning; 8 by default). Lazy needs the survivors to fit
+ * in spare workspace (at most n/3); otherwise eager is used. */
 enum { SA_ISA_AUTO = 0, SA_ISA_EAGER = 1, SA_ISA_LAZY = 2 };
 sa_status sa_ctx_set_isa_mode(sa_ctx* ctx, int mode);
 
 /* Tuning knobs (none changes a result). Unknown or unsupported values give
- * SA_EINVAL and leave the context unchanged. */
+ * SA_EINVAL and leave the context unchanged. Defaults: 512-thread sweep
+ * workgroups of 8 items, the workgroups one CU holds, lazy_ratio 8, trimmed
+ * round-0 keys. */
 typedef struct {
   uint32_t sort_items;   /* radix-sort items per thread: 8, 12, 16, 20 or 24 with 256-thread
                             workgroups (tile = sort_block x sort_items) */
