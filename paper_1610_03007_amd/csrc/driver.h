@@ -50,6 +50,7 @@ struct sa_ctx {
   u32* valsA = nullptr;
   u32* valsB = nullptr;
   u32* isa = nullptr;
+  u32* live = nullptr;    // lazy ISA: bitmap of the positions whose ISA entry is set
   u32* act_idx = nullptr;
   u32* act_rank = nullptr;
   u64* act_ti = nullptr;  // batch survivors: (text << 32) | local position

@@ -102,17 +102,17 @@ void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
 void launch_isa_scatter_sorted(const u32* valsA, const u32* valsB, const SortPlan* plan, u64 n,
                                u32* isa, hipStream_t s);
 void launch_isa_scatter_list(const u32* idx, const u32* rank, u64 count, u64 n, u32* isa,
-                             hipStream_t s);
+                             u32* live, hipStream_t s);
 // Lazy ISA: sample[i] = keys0[i * n / kLazySamples] of the round-0 sorted keys,
 // the first step of every round-0 name search.
 constexpr u32 kLazySamples = 4096;
 void launch_lazy_sample(const u64* keys0, u64 n, u64* sample, hipStream_t s);
 void launch_pack_pairs_lazy(const u32* act_idx, const u32* act_rank, u64 count, u64 n, u64 h,
                             int b, const u32* isa, const u8* text, const u16* code,
-                            const u64* counters, const u64* keys0, const u64* sample, u64* keys,
-                            u32* vals, hipStream_t s);
+                            const u64* counters, const u64* keys0, const u64* sample,
+                            const u32* live, u64* keys, u32* vals, hipStream_t s);
 void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const u64* counters,
-                         const u64* keys0, const u64* sample, hipStream_t s);
+                         const u64* keys0, const u64* sample, const u32* live, hipStream_t s);
 void launch_fill_u32(u32* p, u64 count, u32 value, hipStream_t s);
 
 __host__ __device__ inline u64 ceil_div(u64 a, u64 b) { return (a + b - 1) / b; }

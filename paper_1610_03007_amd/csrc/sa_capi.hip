@@ -21,6 +21,7 @@ void free_workspace(sa_ctx* c) {
   (void)hipFree(c->valsA);
   (void)hipFree(c->valsB);
   (void)hipFree(c->isa);
+  (void)hipFree(c->live);
   (void)hipFree(c->act_idx);
   (void)hipFree(c->act_rank);
   (void)hipFree(c->status);
@@ -28,7 +29,7 @@ void free_workspace(sa_ctx* c) {
   c->act_ti = nullptr;
   c->act_ti_cap = 0;
   c->keysA = c->keysB = nullptr;
-  c->valsA = c->valsB = c->isa = c->act_idx = c->act_rank = nullptr;
+  c->valsA = c->valsB = c->isa = c->act_idx = c->act_rank = c->live = nullptr;
   c->status = nullptr;
   c->cap = 0;
 }
@@ -39,6 +40,7 @@ sa_status ensure_workspace(sa_ctx* c, u64 n) {
   u64 cap = std::max<u64>(n, 1 << 16);
   bool ok = dev_alloc(&c->keysA, cap) && dev_alloc(&c->keysB, cap) && dev_alloc(&c->valsA, cap) &&
             dev_alloc(&c->valsB, cap) && dev_alloc(&c->isa, cap) && dev_alloc(&c->act_idx, cap) &&
+            dev_alloc(&c->live, ceil_div(cap, 32)) &&
             dev_alloc(&c->act_rank, cap) && dev_alloc(&c->status, sort_status_words(cap));
   if (!ok) {
     free_workspace(c);
@@ -278,9 +280,9 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   info.lazy_isa = lazy ? 1u : 0u;
   if (active > 0 || d_isa) {
     if (lazy) {
-      Tracer t(c, s, SA_KERNEL_OTHER, double(n) * 4.0 + double(active) * 12.0);
-      launch_fill_u32(c->isa, n, 0, s);
-      launch_isa_scatter_list(c->act_idx, c->act_rank, active, n, c->isa, s);
+      Tracer t(c, s, SA_KERNEL_OTHER, double(n) / 8.0 + double(active) * 12.0);
+      launch_fill_u32(c->live, ceil_div(n, 32), 0, s);
+      launch_isa_scatter_list(c->act_idx, c->act_rank, active, n, c->isa, c->live, s);
       launch_lazy_sample(keys0, n, c->sample, s);
     } else {
       Tracer t(c, s, SA_KERNEL_ISA_SCATTER, double(n) * 12.0);
@@ -308,7 +310,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
       Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
       if (lazy)
         launch_pack_pairs_lazy(c->act_idx, c->act_rank, active, n, h, b, c->isa, text, c->code,
-                               c->counters, keys0, c->sample, later.kA, later.vA, s);
+                               c->counters, keys0, c->sample, c->live, later.kA, later.vA, s);
       else
         launch_pack_pairs(c->act_idx, c->act_rank, active, n, h, b, c->isa, later.kA, later.vA,
                           s);
@@ -326,7 +328,8 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
     active = c->h_counters[kCtrActive];
   }
   if (d_isa) {
-    if (lazy) launch_isa_complete(c->isa, n, text, c->code, c->counters, keys0, c->sample, s);
+    if (lazy)
+      launch_isa_complete(c->isa, n, text, c->code, c->counters, keys0, c->sample, c->live, s);
     if (hipMemcpyAsync(d_isa, c->isa, n * sizeof(u32), hipMemcpyDeviceToDevice, s) != hipSuccess)
       return SA_EDEVICE;
     if (hipStreamSynchronize(s) != hipSuccess) return SA_EDEVICE;
@@ -498,7 +501,7 @@ sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, u
 
 size_t sa_workspace_bytes(uint64_t n) {
   u64 cap = std::max<u64>(n, 1 << 16);
-  return size_t(cap) * (2 * 8 + 5 * 4) + sort_status_words(cap) * 8 +
+  return size_t(cap) * (2 * 8 + 5 * 4) + ceil_div(cap, 32) * 4 + sort_status_words(cap) * 8 +
          kSmallBytes;
 }
 

@@ -1060,10 +1060,10 @@ void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
 //
 // Eager form: ISA[text position] = rank for every sorted position (one random
 // 4-byte write per suffix). Lazy form, used when few suffixes survive round 0:
-// ISA is cleared, only the survivors' ranks are written, and a later gather
-// that finds 0 recomputes the round-0 rank of position j as 1 + the number of
-// round-0 keys below key(j), by binary search in the round-0 sorted keys (the
-// name is the head rank of j's run of equal keys).
+// only the survivors' ranks are written and marked in a bitmap of live
+// positions; a later gather of an unmarked position j recomputes its round-0
+// rank as 1 + the number of round-0 keys below key(j), by binary search in the
+// round-0 sorted keys (the name is the head rank of j's run of equal keys).
 
 __global__ __launch_bounds__(256) void isa_scatter_sorted_kernel(const u32* __restrict__ valsA,
                                                                  const u32* __restrict__ valsB,
@@ -1088,18 +1088,22 @@ void launch_isa_scatter_sorted(const u32* valsA, const u32* valsB, const SortPla
 __global__ __launch_bounds__(256) void isa_scatter_list_kernel(const u32* __restrict__ idx,
                                                                const u32* __restrict__ rank,
                                                                u64 count, u64 n,
-                                                               u32* __restrict__ isa) {
+                                                               u32* __restrict__ isa,
+                                                               u32* __restrict__ live) {
   u64 q = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   if (q >= count) return;
   const u32 v = idx[q];
-  if (v < n) isa[v] = rank[q];
+  if (v < n) {
+    isa[v] = rank[q];
+    atomicOr(&live[v >> 5], 1u << (v & 31u));
+  }
 }
 
 void launch_isa_scatter_list(const u32* idx, const u32* rank, u64 count, u64 n, u32* isa,
-                             hipStream_t s) {
+                             u32* live, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(isa_scatter_list_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
-                     idx, rank, count, n, isa);
+                     idx, rank, count, n, isa, live);
 }
 
 namespace {
@@ -1156,7 +1160,8 @@ __global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
     const u32* __restrict__ act_idx, const u32* __restrict__ act_rank, u64 count, u64 n, u64 h,
     int b, const u32* __restrict__ isa, const u8* __restrict__ text, const u16* __restrict__ code,
     const u64* __restrict__ counters, const u64* __restrict__ keys0,
-    const u64* __restrict__ sample, u64* __restrict__ keys, u32* __restrict__ vals) {
+    const u64* __restrict__ sample, const u32* __restrict__ live, u64* __restrict__ keys,
+    u32* __restrict__ vals) {
   __shared__ u16 s_code[256];
   __shared__ u64 s_sample[kLazySamples];
   s_code[threadIdx.x] = code[threadIdx.x];
@@ -1171,8 +1176,11 @@ __global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
   const u64 j = u64(i) + h;
   u32 r1 = 0;
   if (j < n) {
-    r1 = isa[j];
-    if (r1 == 0) r1 = round0_rank(j, text, n, s_code, w, c, keys0, s_sample);
+    // ISA[j] holds a name only for suffixes that survived round 0.
+    if ((live[j >> 5] >> (j & 31u)) & 1u)
+      r1 = isa[j];
+    else
+      r1 = round0_rank(j, text, n, s_code, w, c, keys0, s_sample);
   }
   keys[p] = (u64(r) << b) | u64(r1);
   vals[p] = i;
@@ -1180,13 +1188,12 @@ __global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
 
 void launch_pack_pairs_lazy(const u32* act_idx, const u32* act_rank, u64 count, u64 n, u64 h,
                             int b, const u32* isa, const u8* text, const u16* code,
-                            const u64* counters, const u64* keys0, const u64* sample, u64* keys,
-                            u32* vals, hipStream_t s) {
+                            const u64* counters, const u64* keys0, const u64* sample,
+                            const u32* live, u64* keys, u32* vals, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(pack_pairs_lazy_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
                      act_idx, act_rank, count, n, h, b, isa, text, code, counters, keys0, sample,
-                     keys,
-                     vals);
+                     live, keys, vals);
 }
 
 __global__ __launch_bounds__(256) void isa_complete_kernel(u32* __restrict__ isa, u64 n,
@@ -1194,7 +1201,8 @@ __global__ __launch_bounds__(256) void isa_complete_kernel(u32* __restrict__ isa
                                                            const u16* __restrict__ code,
                                                            const u64* __restrict__ counters,
                                                            const u64* __restrict__ keys0,
-                                                           const u64* __restrict__ sample) {
+                                                           const u64* __restrict__ sample,
+                                                           const u32* __restrict__ live) {
   __shared__ u16 s_code[256];
   __shared__ u64 s_sample[kLazySamples];
   s_code[threadIdx.x] = code[threadIdx.x];
@@ -1202,17 +1210,17 @@ __global__ __launch_bounds__(256) void isa_complete_kernel(u32* __restrict__ isa
   __syncthreads();
   u64 j = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  if (isa[j] != 0) return;
+  if ((live[j >> 5] >> (j & 31u)) & 1u) return;
   const u32 w = u32(counters[kCtrCodeBits]);
   const u32 c = u32(counters[kCtrChars]);
   isa[j] = round0_rank(j, text, n, s_code, w, c, keys0, s_sample);
 }
 
 void launch_isa_complete(u32* isa, u64 n, const u8* text, const u16* code, const u64* counters,
-                         const u64* keys0, const u64* sample, hipStream_t s) {
+                         const u64* keys0, const u64* sample, const u32* live, hipStream_t s) {
   if (n == 0) return;
   hipLaunchKernelGGL(isa_complete_kernel, dim3(u32(ceil_div(n, 256))), dim3(256), 0, s, isa, n,
-                     text, code, counters, keys0, sample);
+                     text, code, counters, keys0, sample, live);
 }
 
 // ---------------------------------------------------------------------------
