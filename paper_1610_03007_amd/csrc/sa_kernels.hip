@@ -112,59 +112,30 @@ void launch_set_zero_u32(u32* p, hipStream_t s) {
 // to compare below every character) and a round-0 key holds as many
 // characters as fit in 64 bits.
 
-// The set of byte values a lane has seen, as four 64-bit masks in registers:
-// adding a byte costs a few ALU operations and no memory traffic, where a store
-// into a shared LDS table serialises on the few addresses a small alphabet
-// hits.
-struct ByteSet {
-  u64 m0 = 0, m1 = 0, m2 = 0, m3 = 0;
-  __device__ inline void add(u32 b) {
-    const u64 bit = u64(1) << (b & 63u);
-    const u32 hi = b >> 6;
-    m0 |= hi == 0 ? bit : 0;
-    m1 |= hi == 1 ? bit : 0;
-    m2 |= hi == 2 ? bit : 0;
-    m3 |= hi == 3 ? bit : 0;
-  }
-  __device__ inline void add_word(u32 w) {
-#pragma unroll
-    for (int k = 0; k < 4; ++k) add((w >> (8 * k)) & 0xFFu);
-  }
-  // ORs the sets of the wave's lanes and merges the union into an 8-word LDS
-  // bitmap. Every lane of the wave must call it.
-  __device__ inline void flush(u32* lds8) const {
-    const u64 m[4] = {m0, m1, m2, m3};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      u32 v = u32(m[k >> 1] >> (32 * (k & 1)));
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off);
-      if ((threadIdx.x & 63) == 0 && v) atomicOr(&lds8[k], v);
-    }
-  }
-};
-
+// Bytes present: every lane stores 1 into an LDS table entry per byte value it
+// reads (stores of one instruction to the same entry do not serialise), and
+// the table is ORed into the global one.
 __global__ __launch_bounds__(256) void byte_presence_kernel(const u8* __restrict__ text, u64 n,
                                                             int vec_ok, u32* __restrict__ present) {
-  __shared__ u32 seen[8];
-  if (threadIdx.x < 8) seen[threadIdx.x] = 0;
+  __shared__ u32 seen[256];
+  seen[threadIdx.x] = 0;
   __syncthreads();
-  ByteSet bs;
   const u64 nvec = vec_ok ? n / 16 : 0;
   const uint4* v = reinterpret_cast<const uint4*>(text);
   u64 stride = u64(gridDim.x) * blockDim.x;
   for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < nvec; i += stride) {
     const uint4 w = v[i];
-    bs.add_word(w.x);
-    bs.add_word(w.y);
-    bs.add_word(w.z);
-    bs.add_word(w.w);
+    const u32 words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) seen[(words[q] >> (8 * b)) & 0xFFu] = 1;
+    }
   }
   for (u64 i = nvec * 16 + u64(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
-    bs.add(text[i]);
-  bs.flush(seen);
+    seen[text[i]] = 1;
   __syncthreads();
-  if ((seen[threadIdx.x >> 5] >> (threadIdx.x & 31)) & 1u) atomicOr(&present[threadIdx.x], 1u);
+  if (seen[threadIdx.x]) atomicOr(&present[threadIdx.x], 1u);
 }
 
 void launch_byte_presence(const u8* text, u64 n, u32* present, hipStream_t s) {
@@ -1246,12 +1217,12 @@ __device__ inline u32 new_text_of(const u64* __restrict__ chunk0, u32 m, u64 b) 
 }  // namespace
 
 // Each workgroup scans a contiguous range of chunks (chunks of one text are
-// consecutive), accumulating the bytes seen in LDS and flushing them into the
-// text's bitmap whenever the text changes.
+// consecutive), marking the bytes seen in an LDS table and flushing it into
+// the text's bitmap whenever the text changes.
 __global__ __launch_bounds__(256) void multi_presence_kernel(const u8* __restrict__ arena,
                                                              TextTab tab, NewList nl,
                                                              u64 per_block) {
-  __shared__ u32 seen[8];
+  __shared__ u32 seen[256];
   const u64 b0 = u64(blockIdx.x) * per_block;
   u64 b1 = b0 + per_block;
   if (b1 > nl.chunks) b1 = nl.chunks;
@@ -1262,7 +1233,7 @@ __global__ __launch_bounds__(256) void multi_presence_kernel(const u8* __restric
     while (i + 1 < nl.m && nl.chunk0[i + 1] <= b) ++i;
     const u32 t = nl.t[i];
     const u64 bend = (nl.chunk0[i + 1] < b1) ? nl.chunk0[i + 1] : b1;  // this text's chunks
-    if (threadIdx.x < 8) seen[threadIdx.x] = 0;
+    seen[threadIdx.x] = 0;
     __syncthreads();
     const u64 len = tab.len[t];
     const u64 start = (b - nl.chunk0[i]) * kNewChunk;
@@ -1272,22 +1243,28 @@ __global__ __launch_bounds__(256) void multi_presence_kernel(const u8* __restric
     const u64 lo = tab.base[t] + start, hi = tab.base[t] + end;
     u64 alo = (lo + 15) & ~u64(15), ahi = hi & ~u64(15);
     if (alo > ahi) alo = ahi = hi;
-    ByteSet bs;
     const uint4* v = reinterpret_cast<const uint4*>(arena + alo);
     const u64 words = (ahi - alo) / 16;
     for (u64 q = threadIdx.x; q < words; q += 256) {
       const uint4 w = v[q];
-      bs.add_word(w.x);
-      bs.add_word(w.y);
-      bs.add_word(w.z);
-      bs.add_word(w.w);
+      const u32 ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+#pragma unroll
+        for (int by = 0; by < 4; ++by) seen[(ws[k] >> (8 * by)) & 0xFFu] = 1;
+      }
     }
-    for (u64 q = lo + threadIdx.x; q < alo; q += 256) bs.add(arena[q]);
-    for (u64 q = ahi + threadIdx.x; q < hi; q += 256) bs.add(arena[q]);
-    bs.flush(seen);
+    for (u64 q = lo + threadIdx.x; q < alo; q += 256) seen[arena[q]] = 1;
+    for (u64 q = ahi + threadIdx.x; q < hi; q += 256) seen[arena[q]] = 1;
     __syncthreads();
-    if (threadIdx.x < 8 && seen[threadIdx.x])
-      atomicOr(&tab.present[t * 8 + threadIdx.x], seen[threadIdx.x]);
+    // One atomic per 32 byte values: many workgroups flush into the same
+    // eight words of a long text.
+    const u64 m = __ballot(seen[threadIdx.x] != 0);
+    const int lane = lane_id();
+    if (lane == 0 || lane == 32) {
+      const u32 bits = u32(m >> lane);
+      if (bits) atomicOr(&tab.present[t * 8 + threadIdx.x / 32], bits);
+    }
     __syncthreads();
     b = bend;
   }
