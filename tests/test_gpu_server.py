@@ -129,3 +129,64 @@ def test_server_empty_and_tiny(server):
     assert res[tickets[0]][0].tolist() == []
     assert res[tickets[1]][0].tolist() == [0]
     assert res[tickets[2]][0].tolist() == [5, 3, 1, 0, 4, 2]
+
+
+def test_server_concurrent_clients(server):
+    """Several host threads submit and poll at once; every result is exact."""
+    texts = texts_mix(7, 96, 150000)
+    results = {}
+    errors = []
+
+    def client(k):
+        try:
+            mine = texts[k::4]
+            tickets = [server.submit(t) for t in mine]
+            got = drain(server, tickets)
+            for t, text in zip(tickets, mine):
+                results[(k, t)] = (got[t][0], text)
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(k,)) for k in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    assert len(results) == len(texts)
+    for sa, text in results.values():
+        assert np.array_equal(sa, oracle.sa(text))
+
+
+def test_server_poll_into_device_tensor(server):
+    """poll() fills a caller's device tensor instead of host memory."""
+    text = W.markov3(300001, chain_seed=44)
+    t = server.submit(text)
+    out = torch.empty(text.size, dtype=torch.int32, device="cuda:0")
+    t0 = time.time()
+    while True:
+        done, sa, lat = server.poll(t, out=out)
+        if done:
+            break
+        assert time.time() - t0 < 120
+        time.sleep(0.001)
+    assert sa is out
+    assert np.array_equal(out.cpu().numpy().view(np.uint32), oracle.sa(text))
+
+
+def test_server_max_text_boundary():
+    """A text of exactly max_text bytes is accepted; one byte more is refused."""
+    from paper_1610_03007_amd import SAError, SuffixArrayServer
+    max_text = 1 << 18
+    srv = SuffixArrayServer(0, capacity_bytes=64 << 20, max_text=max_text)
+    try:
+        text = W.dna(max_text, seed=8)
+        t = srv.submit(text)
+        res = drain(srv, [t])
+        assert np.array_equal(res[t][0], oracle.sa(text))
+        with pytest.raises(SAError):
+            srv.submit(np.zeros(max_text + 1, np.uint8))
+        st = srv.stats()
+        assert st["completed"] >= 1 and st["failed"] == 0
+    finally:
+        srv.close()
