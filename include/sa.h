@@ -164,7 +164,9 @@ sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, u
  * the round-0 name of another suffix recomputes it by binary search in the
  * round-0 sorted keys. Auto picks lazy when at most 1/lazy_ratio of the
  * suffixes survive (sa_tuning; 8 by default). Lazy needs the survivors to fit
- * in spare workspace (at most n/3); otherwise eager is used. */
+ * in spare workspace (at most n/3); otherwise eager is used. The mode applies
+ * to sa_build, sa_build_rounds and sa_build_batch (n: all texts' suffixes);
+ * the server always forms the ISA eagerly, since its texts join at any round. */
 enum { SA_ISA_AUTO = 0, SA_ISA_EAGER = 1, SA_ISA_LAZY = 2 };
 sa_status sa_ctx_set_isa_mode(sa_ctx* ctx, int mode);
 

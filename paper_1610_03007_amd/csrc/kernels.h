@@ -150,6 +150,16 @@ void launch_multi_pack0(const u8* arena, TextTab tab, NewList nl, int idshift, u
                         u32* vals, hipStream_t s);
 // Later-round keys for survivors (t, i, r): (t << idshift) | (r << b) |
 // (i + h_t < n_t ? ISA[base_t + i + h_t] : 0); values = i.
+// Batched build with a lazy ISA after round 0 (see sa_kernels.hip).
+void launch_multi_isa_scatter_list(const u64* act_ti, const u32* act_rank, const u64* count_ptr,
+                                   u64 bound, TextTab tab, u32* isa, u32* live, hipStream_t s);
+void launch_multi_isa_scatter_sorted(const u64* keys, const u32* vals, const u32* ranks,
+                                     u64 count, TextTab tab, int idshift, u32* isa,
+                                     hipStream_t s);
+void launch_multi_pack_pairs_lazy(const u64* act_ti, const u32* act_rank, u64 count, TextTab tab,
+                                  int b, int idshift, const u32* isa, const u32* live,
+                                  const u8* arena, const u64* keys0, u64* keys, u32* vals,
+                                  hipStream_t s);
 void launch_multi_pack_pairs(const u64* act_ti, const u32* act_rank, u64 count, TextTab tab,
                              int b, int idshift, const u32* isa, u64* keys, u32* vals,
                              hipStream_t s);

@@ -47,6 +47,13 @@ struct Engine {
          o_up_no = 0, o_up_nc = 0;
   u64 active = 0;         // survivors carried into the next round
   std::vector<u32> live;  // slots with elements in the active set or joining now
+  // Batched build only (every text starts round 0 together): round 0 writes
+  // the sorted positions' names instead of scattering the ISA, and the ISA is
+  // then formed eagerly or, when few suffixes survive, lazily.
+  bool batch_round0_ranks = false;
+  bool lazy = false;           // the ISA holds the survivors' names only (live bitmap)
+  const u64* keys0 = nullptr;  // lazy: round-0 sorted keys
+  Bufs later{};                // lazy: later rounds' buffers, carved from the spare keys
 
   ~Engine() { release(); }
   void release() {
@@ -174,14 +181,20 @@ struct Engine {
       Tracer tr(c, s, SA_KERNEL_PACK_TEXT, double(A0) * 13.0);
       launch_multi_pack0(text_arena, tab, nl, idshift, c->keysA, c->valsA, s);
     }
+    if (lazy && m) return SA_EINVAL;  // lazy rounds admit no new texts
+    const Bufs bufs = lazy ? later : full;
     if (active) {
       Tracer tr(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
-      launch_multi_pack_pairs(c->act_ti, c->act_rank, active, tab, B, idshift, c->isa,
-                              c->keysA + A0, c->valsA + A0, s);
+      if (lazy)
+        launch_multi_pack_pairs_lazy(c->act_ti, c->act_rank, active, tab, B, idshift, c->isa,
+                                     c->live, text_arena, keys0, bufs.kA, bufs.vA, s);
+      else
+        launch_multi_pack_pairs(c->act_ti, c->act_rank, active, tab, B, idshift, c->isa,
+                                c->keysA + A0, c->valsA + A0, s);
     }
     const u64 total = A0 + active;
     if (total) {
-      run_sort(c, full, total, kMaxPasses, 1, slot_info, s);
+      run_sort(c, bufs, total, kMaxPasses, 1, slot_info, s);
       RerankArgs a{};
       a.count = total;
       a.n = 0;
@@ -189,11 +202,11 @@ struct Engine {
       a.rshift = B;
       a.rmask = (u64(1) << B) - 1;
       a.idshift = idshift;
-      a.mode = kRerankScatterIsa;
+      a.mode = (batch_round0_ranks && m) ? kRerankWriteRanks : kRerankScatterIsa;
       a.tbase = tab.base;
       a.tlen = tab.len;
       a.tround0 = tab.round0;
-      run_rerank(c, full, a, sa_arena, s);
+      run_rerank(c, bufs, a, sa_arena, s);
       // Survivors per text; their number is read on the device.
       Tracer tr(c, s, SA_KERNEL_OTHER, 0);
       launch_multi_count_survivors(c->act_ti, c->counters + kCtrActive, total, tab.surv, s);
@@ -222,6 +235,41 @@ struct Engine {
     for (u32 t : live) advance(t);
     live.swap(next_live);
     active = next_active;
+    return SA_OK;
+  }
+
+  // Batched build, after round 0 (which ran with batch_round0_ranks): forms the
+  // ISA eagerly from the sorted names, or lazily (survivors only) when at most
+  // 1/lazy_ratio of the n suffixes survive and the later rounds' buffers fit in
+  // the spare keys (the context's ISA mode may force either form).
+  sa_status form_isa_after_round0(u64 n, hipStream_t s) {
+    const u32 f0 = final_buf_of(c, 0);
+    const u64* k0 = f0 ? c->keysB : c->keysA;
+    const u32* vals0 = f0 ? c->valsB : c->valsA;
+    const u32* ranks0 = f0 ? c->valsA : c->valsB;
+    u64* spare = f0 ? c->keysA : c->keysB;
+    const u64 a1 = (std::max<u64>(active, 1) + 63) / 64 * 64;
+    const bool fits = a1 * 24 <= n * 8;
+    if (c->isa_mode == SA_ISA_LAZY)
+      lazy = active > 0 && fits;
+    else if (c->isa_mode == SA_ISA_AUTO)
+      lazy = active > 0 && fits && active * c->lazy_ratio <= n;
+    else
+      lazy = false;
+    if (lazy) {
+      Tracer t(c, s, SA_KERNEL_OTHER, double(n) / 8.0 + double(active) * 16.0);
+      launch_fill_u32(c->live, ceil_div(n, 32), 0, s);
+      launch_multi_isa_scatter_list(c->act_ti, c->act_rank, c->counters + kCtrActive, active,
+                                    tab, c->isa, c->live, s);
+      keys0 = k0;
+      later.kA = spare;
+      later.kB = spare + a1;
+      later.vA = reinterpret_cast<u32*>(spare + 2 * a1);
+      later.vB = later.vA + a1;
+    } else if (active > 0) {
+      Tracer t(c, s, SA_KERNEL_ISA_SCATTER, double(n) * 20.0);
+      launch_multi_isa_scatter_sorted(k0, vals0, ranks0, n, tab, 64 - idbits, c->isa, s);
+    }
     return SA_OK;
   }
 };
@@ -270,6 +318,7 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
   Engine eng;
   st = eng.init(c, T, idbits, B);
   if (st != SA_OK) return st;
+  eng.batch_round0_ranks = true;
   std::vector<u32> joining;
   for (u32 t = 0; t < T; ++t) {
     eng.base[t] = h_off[t];
@@ -289,6 +338,12 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
     info.key_bits[r] = 64;
     info.rounds = u32(r + 1);
     in_round = eng.active;
+    if (r == 0) {
+      st = eng.form_isa_after_round0(N, s);
+      if (st != SA_OK) return st;
+      eng.batch_round0_ranks = false;
+      info.lazy_isa = eng.lazy ? 1u : 0u;
+    }
     if (eng.active == 0) break;
   }
   u32 maxc = 0;

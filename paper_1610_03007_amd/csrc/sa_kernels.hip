@@ -1404,6 +1404,112 @@ void launch_multi_pack_pairs(const u64* act_ti, const u32* act_rank, u64 count, 
                      act_ti, act_rank, count, tab, b, idshift, isa, keys, vals);
 }
 
+// Batched build, lazy ISA after round 0 (as for one text): only the
+// survivors' names are scattered and marked live; a gather of an unmarked
+// position recomputes its round-0 name by a lower-bound search for its key in
+// the text's own range of the round-0 sorted keys, which is contiguous because
+// the text slot leads every key.
+__global__ __launch_bounds__(256) void multi_isa_scatter_list_kernel(
+    const u64* __restrict__ act_ti, const u32* __restrict__ act_rank,
+    const u64* __restrict__ count_ptr, TextTab tab, u32* __restrict__ isa,
+    u32* __restrict__ live) {
+  const u64 count = *count_ptr;
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  for (u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += stride) {
+    const u64 ti = act_ti[p];
+    const u64 t = ti >> 32;
+    const u64 v = u32(ti);
+    if (v >= tab.len[t]) continue;
+    const u64 g = tab.base[t] + v;
+    isa[g] = act_rank[p];
+    atomicOr(&live[g >> 5], 1u << (g & 31u));
+  }
+}
+
+void launch_multi_isa_scatter_list(const u64* act_ti, const u32* act_rank, const u64* count_ptr,
+                                   u64 bound, TextTab tab, u32* isa, u32* live, hipStream_t s) {
+  if (bound == 0) return;
+  u64 blocks = ceil_div(bound, 256);
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(multi_isa_scatter_list_kernel, dim3(u32(blocks)), dim3(256), 0, s, act_ti,
+                     act_rank, count_ptr, tab, isa, live);
+}
+
+// Eager ISA after a batched round 0: every sorted position's name.
+__global__ __launch_bounds__(256) void multi_isa_scatter_sorted_kernel(
+    const u64* __restrict__ keys, const u32* __restrict__ vals, const u32* __restrict__ ranks,
+    u64 count, TextTab tab, int idshift, u32* __restrict__ isa) {
+  const u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const u64 t = keys[p] >> idshift;
+  const u32 v = vals[p];
+  if (v < tab.len[t]) isa[tab.base[t] + v] = ranks[p];
+}
+
+void launch_multi_isa_scatter_sorted(const u64* keys, const u32* vals, const u32* ranks,
+                                     u64 count, TextTab tab, int idshift, u32* isa,
+                                     hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(multi_isa_scatter_sorted_kernel, dim3(u32(ceil_div(count, 256))), dim3(256),
+                     0, s, keys, vals, ranks, count, tab, idshift, isa);
+}
+
+__global__ __launch_bounds__(256) void multi_pack_pairs_lazy_kernel(
+    const u64* __restrict__ act_ti, const u32* __restrict__ act_rank, u64 count, TextTab tab,
+    int b, int idshift, const u32* __restrict__ isa, const u32* __restrict__ live,
+    const u8* __restrict__ arena, const u64* __restrict__ keys0, u64* __restrict__ keys,
+    u32* __restrict__ vals) {
+  const u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const u64 ti = act_ti[p];
+  const u64 t = ti >> 32;
+  const u32 i = u32(ti);
+  const u64 gb = tab.base[t];
+  const u64 nt = tab.len[t];
+  const u64 j = u64(i) + tab.h[t];
+  u32 r1 = 0;
+  if (j < nt) {
+    const u64 g = gb + j;
+    if ((live[g >> 5] >> (g & 31u)) & 1u) {
+      r1 = isa[g];
+    } else {
+      // The text's round-0 key of position j, then its lower bound among the
+      // text's sorted round-0 keys.
+      const u32 wc = tab.wc[t];
+      const u32 w = wc & 0xFFFFu, c = wc >> 16;
+      const u16* code = tab.code + size_t(t) * 256;
+      const u8* txt = arena + gb;
+      u64 k = 0;
+      for (u32 q = 0; q < c; ++q) {
+        const u64 pos = j + q;
+        k = (k << w) | u64(pos < nt ? code[txt[pos]] : u16(0));
+      }
+      k |= t << idshift;
+      u64 lo = gb, hi = gb + nt;
+      while (lo < hi) {
+        const u64 mid = (lo + hi) >> 1;
+        if (keys0[mid] < k)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      r1 = u32(lo - gb + 1);
+    }
+  }
+  keys[p] = (t << idshift) | (u64(act_rank[p]) << b) | u64(r1);
+  vals[p] = i;
+}
+
+void launch_multi_pack_pairs_lazy(const u64* act_ti, const u32* act_rank, u64 count, TextTab tab,
+                                  int b, int idshift, const u32* isa, const u32* live,
+                                  const u8* arena, const u64* keys0, u64* keys, u32* vals,
+                                  hipStream_t s) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(multi_pack_pairs_lazy_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0,
+                     s, act_ti, act_rank, count, tab, b, idshift, isa, live, arena, keys0, keys,
+                     vals);
+}
+
 __global__ __launch_bounds__(256) void multi_count_survivors_kernel(
     const u64* __restrict__ act_ti, const u64* __restrict__ count_ptr, u32* __restrict__ surv) {
   const u64 count = *count_ptr;

@@ -78,6 +78,55 @@ def test_batch_repetitive_and_unary(builder):
     check_each(texts, sa, off)
 
 
+@pytest.mark.parametrize("mode", ["eager", "lazy", "auto"])
+def test_batch_isa_modes(builder, mode):
+    """The ISA after round 0 formed eagerly (every name scattered) or lazily
+    (survivors only; other names recomputed by a search in the text's own
+    range of round-0 sorted keys) gives the same arrays. Repetitive texts keep
+    suffixes alive for many rounds, so lazy gathers reach both forms of name;
+    the empty and one-symbol texts check the text ranges at the edges."""
+    rng = np.random.default_rng(21)
+    # About 20k suffixes, of which about 4.5k survive round 0 (the forced lazy
+    # form needs at most a third).
+    texts = [W.repetitive(copies=6, base_len=300), b"", b"q", b"ab" * 400,
+             W.dna(5000, seed=3), b"a" * 600, rng.integers(0, 3, 4000).astype(np.uint8),
+             W.markov3(7000, chain_seed=5), b"", W.repetitive(copies=20, base_len=60)]
+    texts = [np.frombuffer(bytes(t), np.uint8) if isinstance(t, bytes) else
+             np.ascontiguousarray(t, np.uint8) for t in texts]
+    builder.set_isa_mode(mode)
+    try:
+        sa, off = run_batch(builder, texts)
+        info = builder.last_info()
+    finally:
+        builder.set_isa_mode("auto")
+    check_each(texts, sa, off)
+    assert info["rounds"] >= 3
+    if mode == "eager":
+        assert info["lazy_isa"] == 0
+    elif mode == "lazy":
+        assert info["lazy_isa"] == 1
+
+
+def test_batch_lazy_at_scale(builder):
+    """Many Markov and DNA texts (2^24 suffixes in all): few suffixes survive
+    round 0, so the automatic choice is the lazy ISA."""
+    rng = np.random.default_rng(33)
+    texts, total = [], 0
+    i = 0
+    while total < (1 << 24):
+        n = int(rng.integers(1 << 12, 1 << 18))
+        t = W.markov3(n, chain_seed=100 + i) if i % 2 == 0 else W.dna(n, seed=100 + i)
+        texts.append(np.ascontiguousarray(t, np.uint8))
+        total += n
+        i += 1
+    sa, off = run_batch(builder, texts)
+    info = builder.last_info()
+    assert info["lazy_isa"] == 1
+    for t in range(0, len(texts), 7):
+        got = sa[int(off[t]):int(off[t + 1])]
+        assert np.array_equal(got, oracle.sa(texts[t])), f"text {t}"
+
+
 def test_batch_equals_single_builds(builder):
     """The batched path and one build per text give identical arrays."""
     rng = np.random.default_rng(9)
