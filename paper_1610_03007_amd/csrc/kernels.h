@@ -56,6 +56,9 @@ void launch_radix_histogram_first(const u64* keys, const SortGeom& geo, const So
 // per thread (8, 12, 16, 20 or 24 with 256-thread workgroups; 4, 8 or 12 with
 // 512) and `block` must match geo.tile = block * items.
 // `grid` persistent workgroups (a multiple of geo.nchunks).
+// Workgroups of the sweep of this shape that one CU holds at once (the
+// runtime's occupancy query: registers and LDS), or 0 if the query fails.
+int onesweep_wgs_per_cu(int items, int block);
 void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
                           int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
                           u32* tickets, u64* status, u64* counters, u32 gen, int items,

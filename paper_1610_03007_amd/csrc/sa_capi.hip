@@ -7,6 +7,7 @@
 // suffix is left. One 8-byte readback per round tells the host how many
 // suffixes remain.
 
+#include <atomic>
 #include "driver.h"
 
 namespace drv {
@@ -121,12 +122,24 @@ SortGeom make_geom(u64 count, int items, int block) {
 // Sweep workgroups one CU holds at once for each tile shape (register and LDS
 // limits of the kernel instances).
 int default_wgs_per_cu(int items, int block) {
-  // What one CU's 160 KB of LDS holds: the key tile (8 bytes + 1 digit byte per
-  // item), the per-wave digit counts (16 bits) and the chunk histograms of the
-  // next sweep, plus about 6 KB of small arrays.
-  const int lds = block * items * 9 + (block / kWave / 2) * kRadix * 4 + kChunks * kRadix * 4 + 6144;
-  const int n = (160 * 1024) / lds;
-  return n < 1 ? 1 : n;
+  // The runtime's occupancy figure for the shape, cached per shape; if the
+  // query fails, what one CU's 160 KB of LDS holds: the key tile, the per-wave
+  // digit counts (16 bits), the 16-bit chunk histograms of the next sweep and
+  // about 4 KB of small arrays.
+  static std::atomic<int> cache[2][32];
+  const int bi = block == 2 * kRadix ? 1 : 0;
+  const int ii = items & 31;
+  int n = cache[bi][ii].load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  n = onesweep_wgs_per_cu(items, block);
+  if (n <= 0) {
+    const int lds = block * items * 8 + (block / kWave / 2) * kRadix * 4 + kChunks * kRadix * 2 + 4096;
+    n = (160 * 1024) / lds;
+    if (n < 1) n = 1;
+    return n;
+  }
+  cache[bi][ii].store(n, std::memory_order_relaxed);
+  return n;
 }
 
 // Sorts (kA, vA or generated values) by the low 8*npass bits. The sorted pairs

@@ -19,6 +19,7 @@ namespace {
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
+
 __device__ inline u32 wave_inclusive_sum(u32 v) {
   const int lane = lane_id();
 #pragma unroll
@@ -510,9 +511,15 @@ void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPla
 // the counts of earlier tiles; reorder the keys by digit in LDS and write each
 // digit's run out contiguously, then the values through the same LDS buffer.
 // While writing keys it counts, per output chunk, the digit of the next sweep
-// that runs, so that sweep starts with exact chunk bases as well.
+// that runs, so that sweep starts with exact chunk bases as well. Those counts
+// are 16-bit halves in LDS: whenever the elements counted since the last check
+// could carry a half past 32767 + 32767, the halves at or above 32768 move to
+// the global histogram first.
+// Shapes of at most 8 items per thread are held to 128 registers: 4 waves per
+// SIMD, two 512-thread workgroups per CU.
 template <int ITEMS, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 4 : 1)))
+void onesweep_pass_kernel(
     u64* __restrict__ keysA, u64* __restrict__ keysB, u32* __restrict__ valsA,
     u32* __restrict__ valsB, u64 count, int pass, u32 ct_log2, u32 nchunks,
     const SortPlan* __restrict__ plan, const u32* __restrict__ hist_in,
@@ -522,16 +529,20 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
   constexpr int NW = BLOCK / kWave;
   constexpr int DW = kRadix / kWave;  // waves that own digits
   constexpr int TILE = BLOCK * ITEMS;
+  constexpr int kTileTz = __builtin_ctz(TILE);
+  constexpr u32 kTileOdd = u32(TILE) >> kTileTz;
   __shared__ u64 s_buf[TILE];  // keys, then values (as u32)
-  __shared__ u8 s_dig[TILE];   // digit of each reordered position
   // Per-wave digit counts, two waves per word (16 bits each: a wave ranks at
   // most 64 * ITEMS items and a tile holds at most 6144).
   static_assert(NW % 2 == 0 && TILE < 65536, "16-bit count halves");
   __shared__ u32 s_cnt[NW / 2][kRadix];
-  __shared__ u32 s_next[kChunks * kRadix];
+  // Next-sweep counts per (output chunk, digit), two 16-bit halves per word.
+  constexpr int kNextWords = kChunks * kRadix / 2;
+  constexpr u32 kNextCheck = 32768;  // elements between overflow checks
+  static_assert(TILE <= int(kNextCheck), "a tile fits between two checks");
+  __shared__ u32 s_next[kNextWords];
   __shared__ u32 s_start[kRadix];
   __shared__ u64 s_base[kRadix];
-  __shared__ u64 s_cbase[kRadix];
   __shared__ u32 s_wsum[DW];
   __shared__ u64 s_tsum[DW];
   __shared__ u32 s_ticket;
@@ -563,7 +574,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
   // count over all chunks, scanned over the digits) plus its count in the
   // earlier chunks.
   const bool digit_owner = tid < kRadix;  // thread tid owns digit tid
-  u64 total = 0, below = 0, inc64 = 0;
+  u64 total = 0, below = 0, inc64 = 0, cbase = 0;
   if (digit_owner) {
     const u32* h = (u32(pass) == plan->first_run ? hist_in : hist_run) +
                    size_t(pass) * kChunks * kRadix;
@@ -584,9 +595,11 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
 #pragma unroll
     for (int w = 0; w < DW; ++w)
       if (w < wave) woff += s_tsum[w];
-    s_cbase[tid] = woff + inc64 - total + below;
+    cbase = woff + inc64 - total + below;
   }
-  for (int i = tid; i < kChunks * kRadix; i += BLOCK) s_next[i] = 0;
+  for (int i = tid; i < kNextWords; i += BLOCK) s_next[i] = 0;
+  u32* next_hist = hist_run + size_t(next >= 0 ? next : 0) * kChunks * kRadix;
+  u32 since_check = 0;  // elements counted into s_next since every half was < 32768
 
   for (;;) {
     if (tid == 0) {
@@ -594,6 +607,24 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
       s_abort = 0;
     }
     for (int i = tid; i < (NW / 2) * kRadix; i += BLOCK) (&s_cnt[0][0])[i] = 0;
+    if (next >= 0 && since_check + u32(TILE) > kNextCheck - 1) {
+      // Every half is at most 32767 + since_check afterwards, and since_check
+      // stays below 32768 until the next check: no half carries into the other.
+      for (int i = tid; i < kNextWords; i += BLOCK) {
+        const u32 w = s_next[i];
+        u32 keep = w;
+        if ((w & 0xFFFFu) >= kNextCheck) {
+          atomicAdd(next_hist + 2 * i, w & 0xFFFFu);
+          keep &= 0xFFFF0000u;
+        }
+        if ((w >> 16) >= kNextCheck) {
+          atomicAdd(next_hist + 2 * i + 1, w >> 16);
+          keep &= 0xFFFFu;
+        }
+        if (keep != w) s_next[i] = keep;
+      }
+      since_check = 0;
+    }
     __syncthreads();
     const u64 tile = c_first + s_ticket;
     if (tile >= c_end) break;  // uniform
@@ -605,19 +636,22 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
     const u64* kin_w = kin + wave_base;
 
     // Keys and values are both requested up front: a value load issued after
-    // the key stores would wait behind them.
+    // the key stores would wait behind them. Each input is read once per
+    // sweep, so the loads are non-temporal.
     u64 key[ITEMS];
     u32 val[ITEMS];
     const u32* vin_w = vin + wave_base;
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const u32 e = u32(j * kWave + lane);
-      key[j] = (e < wvalid) ? kin_w[e] : ~u64(0);  // digit 255: after every valid item
+      // Missing items take digit 255: after every valid item.
+      key[j] = (e < wvalid) ? __builtin_nontemporal_load(kin_w + e) : ~u64(0);
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const u32 e = u32(j * kWave + lane);
-      val[j] = (e < wvalid) ? (iota ? u32(wave_base + e) : vin_w[e]) : 0u;
+      val[j] = (e < wvalid) ? (iota ? u32(wave_base + e) : __builtin_nontemporal_load(vin_w + e))
+                            : 0u;
     }
 
     // Rank within the wave, items in (j, lane) order == input order.
@@ -680,7 +714,7 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
       u64 excl = 0;
       if (tile > c_first)
         excl = lookback(status + tid, kRadix, tile, tot, gen, false, counters, &s_abort);
-      s_base[tid] = s_cbase[tid] + excl - u64(start);
+      s_base[tid] = cbase + excl - u64(start);
     }
     __syncthreads();
 
@@ -691,21 +725,34 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
       const u32 d = u32(key[j] >> shift) & (kRadix - 1);
       rank[j] += s_start[d] + ((s_cnt[wave >> 1][d] >> half) & 0xFFFFu);
       s_buf[rank[j]] = key[j];
-      s_dig[rank[j]] = u8(d);
     }
     __syncthreads();
     if (s_abort) return;
 
     const u64 left = count - tile_base;
     const u32 valid = left < u64(TILE) ? u32(left) : u32(TILE);
-    for (u32 q = tid; q < valid; q += BLOCK) {
-      const u64 k = s_buf[q];
-      const u64 o = s_base[s_dig[q]] + q;
-      if (o < count) {
-        kout[o] = k;
-        if (next >= 0) {
-          const u32 oc = u32((o / u64(TILE)) >> ct_log2);
-          atomicAdd(&s_next[oc * kRadix + (u32(k >> nshift) & (kRadix - 1))], 1u);
+    since_check += valid;
+    // Reordered position tid + i * BLOCK: its digit, kept for the value pass.
+    u32 qdig[(ITEMS + 3) / 4];
+#pragma unroll
+    for (int i = 0; i < (ITEMS + 3) / 4; ++i) qdig[i] = 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const u32 q = u32(tid + i * BLOCK);
+      if (q < valid) {
+        const u64 k = s_buf[q];
+        const u32 d = u32(k >> shift) & (kRadix - 1);
+        qdig[i / 4] |= d << (8 * (i % 4));
+        const u64 o = s_base[d] + q;
+        if (o < count) {
+          kout[o] = k;
+          if (next >= 0) {
+            // Output chunk o / (TILE << ct_log2), with TILE = kTileOdd << kTileTz:
+            // a 32-bit division by the odd factor (o < 2^(32 + kTileTz)).
+            const u32 bin = ((u32(o >> kTileTz) / kTileOdd) >> ct_log2) * kRadix +
+                            (u32(k >> nshift) & (kRadix - 1));
+            atomicAdd(&s_next[bin >> 1], 1u << (16 * (bin & 1u)));
+          }
         }
       }
     }
@@ -717,22 +764,27 @@ __global__ __launch_bounds__(BLOCK) void onesweep_pass_kernel(
       if (e < wvalid) s_vals[rank[j]] = val[j];
     }
     __syncthreads();
-    for (u32 q = tid; q < valid; q += BLOCK) {
-      const u64 o = s_base[s_dig[q]] + q;
-      if (o < count) {
-        vout[o] = s_vals[q];
-      } else {
-        atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
-                 (unsigned long long)kErrBounds);
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+      const u32 q = u32(tid + i * BLOCK);
+      if (q < valid) {
+        const u32 d = (qdig[i / 4] >> (8 * (i % 4))) & 0xFFu;
+        const u64 o = s_base[d] + q;
+        if (o < count) {
+          vout[o] = s_vals[q];
+        } else {
+          atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+                   (unsigned long long)kErrBounds);
+        }
       }
     }
     __syncthreads();
   }
   if (next >= 0) {
-    u32* h = hist_run + size_t(next) * kChunks * kRadix;
-    for (int i = tid; i < kChunks * kRadix; i += BLOCK) {
-      const u32 v = s_next[i];
-      if (v) atomicAdd(h + i, v);
+    for (int i = tid; i < kNextWords; i += BLOCK) {
+      const u32 w = s_next[i];
+      if (w & 0xFFFFu) atomicAdd(next_hist + 2 * i, w & 0xFFFFu);
+      if (w >> 16) atomicAdd(next_hist + 2 * i + 1, w >> 16);
     }
   }
 }
@@ -762,6 +814,34 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
     }
   }
 #undef SA_ONESWEEP
+}
+
+int onesweep_wgs_per_cu(int items, int block) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+#define SA_OCC(IT, BL) \
+  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, onesweep_pass_kernel<IT, BL>, BL, 0)
+  if (block == 2 * kRadix) {
+    switch (items) {
+      case 4: SA_OCC(4, 512); break;
+      case 12: SA_OCC(12, 512); break;
+      default: SA_OCC(8, 512); break;
+    }
+  } else {
+    switch (items) {
+      case 8: SA_OCC(8, 256); break;
+      case 12: SA_OCC(12, 256); break;
+      case 20: SA_OCC(20, 256); break;
+      case 24: SA_OCC(24, 256); break;
+      default: SA_OCC(16, 256); break;
+    }
+  }
+#undef SA_OCC
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return n;
 }
 
 // ---------------------------------------------------------------------------

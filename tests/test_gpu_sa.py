@@ -344,6 +344,30 @@ def test_sort_tile_variants(builder, items, block):
         builder.auto_tuning()
 
 
+@pytest.mark.parametrize("items,block", [(8, 512), (8, 256)])
+def test_radix_sort_skewed_next_digit(builder, items, block):
+    """2^26 keys whose low digit is 0 or 1 and whose next digit is almost
+    always 0: each sweep workgroup counts far more than 65535 elements into
+    one (output chunk, next digit) bin, so its 16-bit LDS counts must move to
+    the global histogram before they overflow."""
+    builder.set_tuning(sort_items=items, sort_block=block)
+    try:
+        rng = np.random.default_rng(items * block)
+        count = 1 << 26
+        keys = rng.integers(0, 2, count, dtype=np.uint64)
+        rare = rng.random(count) < 1e-3
+        keys[rare] |= rng.integers(1, 256, int(rare.sum()), dtype=np.uint64) << np.uint64(8)
+        vals = np.arange(count, dtype=np.uint32)
+        order = np.argsort(keys, kind="stable")
+        k_t, v_t = dev(keys.view(np.int64)), dev(vals.view(np.int32))
+        builder.radix_sort_pairs(k_t, v_t, 16)
+        torch.cuda.synchronize()
+        assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals[order])
+        assert np.array_equal(k_t.cpu().numpy().view(np.uint64), keys[order])
+    finally:
+        builder.auto_tuning()
+
+
 def test_tuning_rejects_bad_values(builder):
     from paper_1610_03007_amd import SAError
     with pytest.raises(SAError):
