@@ -663,13 +663,16 @@ void onesweep_pass_kernel(
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const u32 d = u32(key[j] >> shift) & (kRadix - 1);
-      u64 peers = ~u64(0);
+      // Lanes whose digit differs from this lane's in some bit: the OR over
+      // the bits of (ballot of the bit) XOR (this lane's bit, broadcast).
+      u64 diff = 0;
 #pragma unroll
       for (int b = 0; b < kRadixBits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const u64 bal = __ballot(bit);
-        peers &= bit ? bal : ~bal;
+        const u32 m = u32(int(d << (31 - b)) >> 31);  // bit b of d in every bit
+        const u64 bal = __ballot(m != 0u);
+        diff |= bal ^ (u64(m) | (u64(m) << 32));
       }
+      const u64 peers = ~diff;
       const u32 leader = u32(__ffsll((long long)peers) - 1);
       packed[j] = u32(__popcll(peers & lt_mask)) | (leader << 8);
       u32 old = 0;
