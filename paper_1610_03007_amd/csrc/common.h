@@ -70,6 +70,7 @@ struct SortPlan {
 // never waits on another chunk; summed over the chunks they also give the
 // sweep its global digit offsets.
 constexpr int kChunks = 32;
+static_assert(kChunks % 8 == 0, "chunk counts are read eight at a time");
 
 // Workgroup and tile shapes.
 constexpr int kSortBlock = 256;          // the smaller sweep workgroup (one thread per digit)

@@ -578,13 +578,17 @@ void onesweep_pass_kernel(
   if (digit_owner) {
     const u32* h = (u32(pass) == plan->first_run ? hist_in : hist_run) +
                    size_t(pass) * kChunks * kRadix;
-    u32 part[kChunks];
+    // Eight chunk counts in flight at a time.
+    for (int c0 = 0; c0 < kChunks; c0 += 8) {
+      u32 part[8];
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) part[c] = u32(c) < nchunks ? h[c * kRadix + tid] : 0u;
+      for (int c = 0; c < 8; ++c)
+        part[c] = u32(c0 + c) < nchunks ? h[(c0 + c) * kRadix + tid] : 0u;
 #pragma unroll
-    for (int c = 0; c < kChunks; ++c) {
-      total += part[c];
-      if (u32(c) < chunk) below += part[c];
+      for (int c = 0; c < 8; ++c) {
+        total += part[c];
+        if (u32(c0 + c) < chunk) below += part[c];
+      }
     }
     inc64 = wave_inclusive_sum64(total);
     if (lane == kWave - 1) s_tsum[wave] = inc64;
