@@ -669,14 +669,20 @@ void onesweep_pass_kernel(
       const u32 d = u32(key[j] >> shift) & (kRadix - 1);
       // Lanes whose digit differs from this lane's in some bit: the OR over
       // the bits of (ballot of the bit) XOR (this lane's bit, broadcast).
-      u64 diff = 0;
+      // Each step is one three-input bitwise operation per 32-lane half
+      // (diff | (ballot ^ m), truth table 0xF6).
+      u32 dlo = 0, dhi = 0;
 #pragma unroll
       for (int b = 0; b < kRadixBits; ++b) {
-        const u32 m = u32(int(d << (31 - b)) >> 31);  // bit b of d in every bit
+        u32 m = u32(int(d << (31 - b)) >> 31);  // bit b of d in every bit
+        // Opaque to the optimiser, so that the ballot compares m itself
+        // instead of shifting d once more.
+        asm("" : "+v"(m));
         const u64 bal = __ballot(m != 0u);
-        diff |= bal ^ (u64(m) | (u64(m) << 32));
+        dlo = __builtin_amdgcn_bitop3_b32(dlo, u32(bal), m, 0xF6);
+        dhi = __builtin_amdgcn_bitop3_b32(dhi, u32(bal >> 32), m, 0xF6);
       }
-      const u64 peers = ~diff;
+      const u64 peers = ~(u64(dlo) | (u64(dhi) << 32));
       const u32 leader = u32(__ffsll((long long)peers) - 1);
       packed[j] = u32(__popcll(peers & lt_mask)) | (leader << 8);
       u32 old = 0;
