@@ -642,20 +642,36 @@ void onesweep_pass_kernel(
     // Keys and values are both requested up front: a value load issued after
     // the key stores would wait behind them. Each input is read once per
     // sweep, so the loads are non-temporal.
+    // A wave whose items all exist (every wave but those of the last tile)
+    // loads without per-item tests: one address and immediate offsets.
     u64 key[ITEMS];
     u32 val[ITEMS];
     const u32* vin_w = vin + wave_base;
+    if (wvalid == u32(ITEMS * kWave)) {
+      const u64* kl = kin_w + lane;
+      const u32* vl = vin_w + lane;
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 e = u32(j * kWave + lane);
-      // Missing items take digit 255: after every valid item.
-      key[j] = (e < wvalid) ? __builtin_nontemporal_load(kin_w + e) : ~u64(0);
-    }
+      for (int j = 0; j < ITEMS; ++j) key[j] = __builtin_nontemporal_load(kl + j * kWave);
+      if (iota) {
 #pragma unroll
-    for (int j = 0; j < ITEMS; ++j) {
-      const u32 e = u32(j * kWave + lane);
-      val[j] = (e < wvalid) ? (iota ? u32(wave_base + e) : __builtin_nontemporal_load(vin_w + e))
-                            : 0u;
+        for (int j = 0; j < ITEMS; ++j) val[j] = u32(wave_base) + u32(j * kWave + lane);
+      } else {
+#pragma unroll
+        for (int j = 0; j < ITEMS; ++j) val[j] = __builtin_nontemporal_load(vl + j * kWave);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const u32 e = u32(j * kWave + lane);
+        // Missing items take digit 255: after every valid item.
+        key[j] = (e < wvalid) ? __builtin_nontemporal_load(kin_w + e) : ~u64(0);
+      }
+#pragma unroll
+      for (int j = 0; j < ITEMS; ++j) {
+        const u32 e = u32(j * kWave + lane);
+        val[j] = (e < wvalid) ? (iota ? u32(wave_base + e) : __builtin_nontemporal_load(vin_w + e))
+                              : 0u;
+      }
     }
 
     // Rank within the wave, items in (j, lane) order == input order.
