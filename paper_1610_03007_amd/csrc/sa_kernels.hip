@@ -268,7 +268,8 @@ __global__ __launch_bounds__(kPackBlock) void pack_text_kernel(const u8* __restr
 #pragma unroll
     for (int j = 0; j < IT; ++j) {
       const int i = j * kPackBlock + t;
-      keys[base + u64(i)] = s_out[pad_out<IT>(i / IT, i % IT)];
+      // Written once and read by the next kernel: non-temporal.
+      __builtin_nontemporal_store(s_out[pad_out<IT>(i / IT, i % IT)], keys + base + u64(i));
     }
   } else {
     for (int i = t; i < TILE; i += kPackBlock) {
@@ -347,7 +348,7 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
     for (int j = 0; j < kHistItems; ++j) {
       const u64 e = base + u64(j) * kHistBlock + threadIdx.x;
       valid[j] = e < ce;
-      key[j] = valid[j] ? keys[e] : 0;
+      key[j] = valid[j] ? __builtin_nontemporal_load(keys + e) : 0;
       if (valid[j]) {
         kor |= key[j];
         knot |= ~key[j];
@@ -1475,8 +1476,9 @@ __global__ __launch_bounds__(kPackBlock) void multi_pack0_kernel(const u8* __res
   for (int q = th; q < kPackTile; q += kPackBlock) {
     const u64 p = start + u64(q);
     if (p < len) {
-      keys[out + q] = tag | s_out[pad_out<kPackItems>(q / kPackItems, q % kPackItems)];
-      vals[out + q] = u32(p);
+      __builtin_nontemporal_store(tag | s_out[pad_out<kPackItems>(q / kPackItems, q % kPackItems)],
+                                  keys + out + q);
+      __builtin_nontemporal_store(u32(p), vals + out + q);
     }
   }
 }
