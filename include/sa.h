@@ -184,7 +184,11 @@ typedef struct {
                                (0 = what one CU holds for the tile shape; at most 16) */
   uint32_t sort_block;   /* radix-sweep workgroup size: 256 (0 means 256) or 512; with 512,
                             sort_items is 4, 8 or 12 */
-  uint32_t reserved[3];  /* must be zero */
+  uint32_t sort_match;   /* how a sweep wave finds the lanes that hold the same digit:
+                            0 (default) = eight ballots, whose cost does not depend on the
+                            digits; 1 = an LDS table (fewer instructions, but lanes of
+                            equal digits collide in its atomics) */
+  uint32_t reserved[2];  /* must be zero */
 } sa_tuning;
 /* Sets an explicit tuning, used by every later build of the context. t = NULL
  * goes back to automatic choice: the cache entry for each input, else the
@@ -201,7 +205,8 @@ sa_status sa_ctx_tuning_source(const sa_ctx* ctx, int* source);
  * floor(log2 of the total length), bits per character code of the input):
  *   stage 1: (sort_items, sort_block) in {8, 12, 16, 20, 24} x 256 and
  *            {4, 8, 12} x 512, x sort_wgs_per_cu in {default, 1, 2, 3, 4};
- *   stage 2: round0_full flipped; stage 3: lazy_ratio in {3, 4, 8, 16, 64}.
+ *   stage 2: sort_match 1 (the LDS table);
+ *   stage 3: round0_full flipped; stage 4: lazy_ratio in {3, 4, 8, 16, 64}.
  * Each candidate is one warm-up build plus the best of `reps` timed builds
  * (0 = 3) on `stream`, measured with HIP events. d_texts / h_offsets /
  * num_texts / d_sas are as sa_build_batch (num_texts = 1 tunes sa_build,

@@ -172,9 +172,9 @@ class SuffixArrayBuilder:
         return ("default", "cache", "explicit")[v.value]
 
     def set_tuning(self, **kw) -> None:
-        """Set tuning knobs (sort_items, sort_block, lazy_ratio, round0_full,
-        sort_wgs_per_cu); results never change. Unset knobs keep their current
-        values."""
+        """Set tuning knobs (sort_items, sort_block, sort_match, lazy_ratio,
+        round0_full, sort_wgs_per_cu); results never change. Unset knobs keep
+        their current values."""
         cur = self.tuning()
         unknown = set(kw) - set(cur)
         if unknown:

@@ -70,10 +70,12 @@ class BuildInfo(ctypes.Structure):
 class Tuning(ctypes.Structure):
     _fields_ = [("sort_items", ctypes.c_uint32), ("lazy_ratio", ctypes.c_uint32),
                 ("round0_full", ctypes.c_uint32), ("sort_wgs_per_cu", ctypes.c_uint32),
-                ("sort_block", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("sort_block", ctypes.c_uint32), ("sort_match", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32 * 2)]
 
 
-TUNING_KNOBS = ("sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu", "sort_block")
+TUNING_KNOBS = ("sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu", "sort_block",
+                "sort_match")
 
 
 def tuning_dict(t: "Tuning") -> dict:

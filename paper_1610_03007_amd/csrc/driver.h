@@ -76,6 +76,7 @@ struct sa_ctx {
   int sort_items = kSortItemsDefault;  // radix-sort items per thread (tile size)
   int sort_block = kSortBlockDefault;  // radix-sort workgroup size (256 or 512)
   int sort_wgs_per_cu = 0;             // persistent sweep workgroups per CU (0 = by tile size)
+  int sort_match = 0;                  // sweep digit matching: 0 ballots, 1 LDS table
   int num_cus = 256;
   u64 lazy_ratio = kLazyRatioDefault;
   int round0_trim = 1;  // round-0 keys fill whole radix digits
@@ -171,7 +172,7 @@ struct Bufs {
 
 Bufs full_bufs(sa_ctx* c);
 SortGeom make_geom(u64 count, int items, int block);
-int default_wgs_per_cu(int items, int block);
+int default_wgs_per_cu(int items, int block, bool table);
 void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
               hipStream_t s);
 void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s);

@@ -58,11 +58,13 @@ void launch_radix_histogram_first(const u64* keys, const SortGeom& geo, const So
 // `grid` persistent workgroups (a multiple of geo.nchunks).
 // Workgroups of the sweep of this shape that one CU holds at once (the
 // runtime's occupancy query: registers and LDS), or 0 if the query fails.
-int onesweep_wgs_per_cu(int items, int block);
+int onesweep_wgs_per_cu(int items, int block, bool table);
+// table: digit matching through an LDS table (true) or through ballots (false);
+// both give the same result.
 void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
                           int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
                           u32* tickets, u64* status, u64* counters, u32 gen, int items,
-                          int block, u32 grid, hipStream_t s);
+                          int block, bool table, u32 grid, hipStream_t s);
 
 // Re-rank the sorted active set, scatter the ISA, finalize unique suffixes into
 // the SA and compact the survivors.

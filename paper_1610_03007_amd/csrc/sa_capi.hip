@@ -121,24 +121,26 @@ SortGeom make_geom(u64 count, int items, int block) {
 
 // Sweep workgroups one CU holds at once for each tile shape (register and LDS
 // limits of the kernel instances).
-int default_wgs_per_cu(int items, int block) {
+int default_wgs_per_cu(int items, int block, bool table) {
   // The runtime's occupancy figure for the shape, cached per shape; if the
   // query fails, what one CU's 160 KB of LDS holds: the key tile, the per-wave
-  // digit counts (16 bits), the 16-bit chunk histograms of the next sweep and
-  // about 4 KB of small arrays.
-  static std::atomic<int> cache[2][32];
+  // digit counts (16 bits), the 16-bit chunk histograms of the next sweep, the
+  // match table if any and about 4 KB of small arrays.
+  static std::atomic<int> cache[2][2][32];
   const int bi = block == 2 * kRadix ? 1 : 0;
   const int ii = items & 31;
-  int n = cache[bi][ii].load(std::memory_order_relaxed);
+  const int ti = table ? 1 : 0;
+  int n = cache[ti][bi][ii].load(std::memory_order_relaxed);
   if (n > 0) return n;
-  n = onesweep_wgs_per_cu(items, block);
+  n = onesweep_wgs_per_cu(items, block, table);
   if (n <= 0) {
-    const int lds = block * items * 8 + (block / kWave / 2) * kRadix * 4 + kChunks * kRadix * 2 + 4096;
+    const int lds = block * items * 8 + (block / kWave / 2) * kRadix * 4 + kChunks * kRadix * 2 +
+                    (table ? (block / kWave) * kRadix * 8 : 0) + 4096;
     n = (160 * 1024) / lds;
     if (n < 1) n = 1;
     return n;
   }
-  cache[bi][ii].store(n, std::memory_order_relaxed);
+  cache[ti][bi][ii].store(n, std::memory_order_relaxed);
   return n;
 }
 
@@ -148,6 +150,7 @@ int default_wgs_per_cu(int items, int block) {
 void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
               hipStream_t s) {
   const SortGeom geo = make_geom(count, c->sort_items, c->sort_block);
+  const bool table = c->sort_match == 1;
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
     // Chunk histograms and tickets; tile tickets, the key ORs and the
@@ -169,8 +172,9 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
   (void)hipMemcpyAsync(c->h_plans + size_t(slot) * kPlanFlagWords, c->plan->skip,
                        kPlanFlagWords * sizeof(u32), hipMemcpyDeviceToHost, s);
   const u64 tiles = ceil_div(count, geo.tile);
-  const int per_cu = c->sort_wgs_per_cu > 0 ? c->sort_wgs_per_cu
-                                            : default_wgs_per_cu(c->sort_items, c->sort_block);
+  const int per_cu = c->sort_wgs_per_cu > 0
+                         ? c->sort_wgs_per_cu
+                         : default_wgs_per_cu(c->sort_items, c->sort_block, table);
   const u64 want = std::min<u64>(tiles, u64(c->num_cus) * u64(per_cu));
   const u32 grid = u32(std::max<u64>(1, want / geo.nchunks) * geo.nchunks);
   for (int p = 0; p < npass; ++p) {
@@ -178,7 +182,7 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
     Tracer t(c, s, SA_KERNEL_SORT_PASS, 0, slot, p, count);
     launch_onesweep_pass(bf.kA, bf.kB, bf.vA, bf.vB, geo, p, c->plan, c->hist_in, c->hist_run,
                          c->tickets, c->status, c->counters, gen, c->sort_items,
-                         c->sort_block, grid, s);
+                         c->sort_block, table, grid, s);
   }
 }
 

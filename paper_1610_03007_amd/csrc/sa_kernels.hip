@@ -517,8 +517,9 @@ void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPla
 // could carry a half past 32767 + 32767, the halves at or above 32768 move to
 // the global histogram first.
 // Shapes of at most 8 items per thread are held to 128 registers: 4 waves per
-// SIMD, two 512-thread workgroups per CU.
-template <int ITEMS, int BLOCK>
+// SIMD, two 512-thread workgroups per CU. TABLE selects how a wave finds the
+// lanes that hold the same digit (see the ranking below).
+template <int ITEMS, int BLOCK, bool TABLE>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 4 : 1)))
 void onesweep_pass_kernel(
     u64* __restrict__ keysA, u64* __restrict__ keysB, u32* __restrict__ valsA,
@@ -537,6 +538,8 @@ void onesweep_pass_kernel(
   // most 64 * ITEMS items and a tile holds at most 6144).
   static_assert(NW % 2 == 0 && TILE < 65536, "16-bit count halves");
   __shared__ u32 s_cnt[NW / 2][kRadix];
+  // With TABLE, per wave: the lanes of each digit (zero between uses).
+  __shared__ u64 s_match[TABLE ? NW : 1][kRadix];
   // Next-sweep counts per (output chunk, digit), two 16-bit halves per word.
   constexpr int kNextWords = kChunks * kRadix / 2;
   constexpr u32 kNextCheck = 32768;  // elements between overflow checks
@@ -603,6 +606,8 @@ void onesweep_pass_kernel(
     cbase = woff + inc64 - total + below;
   }
   for (int i = tid; i < kNextWords; i += BLOCK) s_next[i] = 0;
+  if (TABLE)
+    for (int i = tid; i < NW * kRadix; i += BLOCK) (&s_match[0][0])[i] = 0;
   u32* next_hist = hist_run + size_t(next >= 0 ? next : 0) * kChunks * kRadix;
   u32 since_check = 0;  // elements counted into s_next since every half was < 32768
 
@@ -679,27 +684,41 @@ void onesweep_pass_kernel(
     u32* cnt = &s_cnt[wave >> 1][0];
     const int half = 16 * (wave & 1);
     const u64 lt_mask = (u64(1) << lane) - 1;
+    const u64 my_bit = u64(1) << lane;
+    u64* mt = &s_match[TABLE ? wave : 0][0];
     u32 rank[ITEMS];
     u32 packed[ITEMS];  // below | leader << 8
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
       const u32 d = u32(key[j] >> shift) & (kRadix - 1);
-      // Lanes whose digit differs from this lane's in some bit: the OR over
-      // the bits of (ballot of the bit) XOR (this lane's bit, broadcast).
-      // Each step is one three-input bitwise operation per 32-lane half
-      // (diff | (ballot ^ m), truth table 0xF6).
-      u32 dlo = 0, dhi = 0;
+      u64 peers;
+      if constexpr (TABLE) {
+        // Every lane ORs its bit into the wave's table entry of its digit,
+        // reads the entry back and clears it (a wave's LDS operations run in
+        // order). Few vector instructions, but lanes of the same digit
+        // collide in the LDS atomic unit.
+        __hip_atomic_fetch_or(mt + d, my_bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        peers = mt[d];
+        mt[d] = 0;
+      } else {
+        // Lanes whose digit differs from this lane's in some bit: the OR over
+        // the bits of (ballot of the bit) XOR (this lane's bit, broadcast).
+        // Each step is one three-input bitwise operation per 32-lane half
+        // (diff | (ballot ^ m), truth table 0xF6). The cost does not depend on
+        // the digits.
+        u32 dlo = 0, dhi = 0;
 #pragma unroll
-      for (int b = 0; b < kRadixBits; ++b) {
-        u32 m = u32(int(d << (31 - b)) >> 31);  // bit b of d in every bit
-        // Opaque to the optimiser, so that the ballot compares m itself
-        // instead of shifting d once more.
-        asm("" : "+v"(m));
-        const u64 bal = __ballot(m != 0u);
-        dlo = __builtin_amdgcn_bitop3_b32(dlo, u32(bal), m, 0xF6);
-        dhi = __builtin_amdgcn_bitop3_b32(dhi, u32(bal >> 32), m, 0xF6);
+        for (int b = 0; b < kRadixBits; ++b) {
+          u32 m = u32(int(d << (31 - b)) >> 31);  // bit b of d in every bit
+          // Opaque to the optimiser, so that the ballot compares m itself
+          // instead of shifting d once more.
+          asm("" : "+v"(m));
+          const u64 bal = __ballot(m != 0u);
+          dlo = __builtin_amdgcn_bitop3_b32(dlo, u32(bal), m, 0xF6);
+          dhi = __builtin_amdgcn_bitop3_b32(dhi, u32(bal >> 32), m, 0xF6);
+        }
+        peers = ~(u64(dlo) | (u64(dhi) << 32));
       }
-      const u64 peers = ~(u64(dlo) | (u64(dhi) << 32));
       const u32 leader = u32(__ffsll((long long)peers) - 1);
       packed[j] = u32(__popcll(peers & lt_mask)) | (leader << 8);
       u32 old = 0;
@@ -822,12 +841,19 @@ void onesweep_pass_kernel(
 void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
                           int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
                           u32* tickets, u64* status, u64* counters, u32 gen, int items,
-                          int block, u32 grid, hipStream_t s) {
+                          int block, bool table, u32 grid, hipStream_t s) {
   if (geo.count == 0) return;
 #define SA_ONESWEEP(IT, BL)                                                                   \
-  hipLaunchKernelGGL((onesweep_pass_kernel<IT, BL>), dim3(grid), dim3(BL), 0, s, keysA, keysB, \
-                     valsA, valsB, geo.count, pass, geo.ct_log2, geo.nchunks, plan, hist_in,   \
-                     hist_run, tickets, status, counters, gen)
+  do {                                                                                        \
+    if (table)                                                                                \
+      hipLaunchKernelGGL((onesweep_pass_kernel<IT, BL, true>), dim3(grid), dim3(BL), 0, s,    \
+                         keysA, keysB, valsA, valsB, geo.count, pass, geo.ct_log2,            \
+                         geo.nchunks, plan, hist_in, hist_run, tickets, status, counters, gen); \
+    else                                                                                      \
+      hipLaunchKernelGGL((onesweep_pass_kernel<IT, BL, false>), dim3(grid), dim3(BL), 0, s,   \
+                         keysA, keysB, valsA, valsB, geo.count, pass, geo.ct_log2,            \
+                         geo.nchunks, plan, hist_in, hist_run, tickets, status, counters, gen); \
+  } while (0)
   if (block == 2 * kRadix) {
     switch (items) {
       case 4: SA_ONESWEEP(4, 512); break;
@@ -846,11 +872,14 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
 #undef SA_ONESWEEP
 }
 
-int onesweep_wgs_per_cu(int items, int block) {
+int onesweep_wgs_per_cu(int items, int block, bool table) {
   int n = 0;
   hipError_t e = hipSuccess;
-#define SA_OCC(IT, BL) \
-  e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, onesweep_pass_kernel<IT, BL>, BL, 0)
+#define SA_OCC(IT, BL)                                                                         \
+  e = table ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, onesweep_pass_kernel<IT, BL, true>, \
+                                                           BL, 0)                              \
+            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, onesweep_pass_kernel<IT, BL, false>, \
+                                                           BL, 0)
   if (block == 2 * kRadix) {
     switch (items) {
       case 4: SA_OCC(4, 512); break;

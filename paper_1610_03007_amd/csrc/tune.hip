@@ -168,7 +168,8 @@ bool tuning_valid(const sa_tuning& t) {
   } else {
     return false;
   }
-  if (t.lazy_ratio < 3 || t.round0_full > 1 || t.sort_wgs_per_cu > 16) return false;
+  if (t.lazy_ratio < 3 || t.round0_full > 1 || t.sort_wgs_per_cu > 16 || t.sort_match > 1)
+    return false;
   for (u32 r : t.reserved)
     if (r != 0) return false;
   return true;
@@ -224,6 +225,11 @@ sa_status tune_parse(const std::string& text, TuneTable& out) {
     te.t.lazy_ratio = u32(v);
     if (!num_field(e, "round0_full", 0, 1, &v)) return SA_EINVAL;
     te.t.round0_full = u32(v);
+    te.t.sort_match = 0;  // entries without the field predate the match choice
+    if (e.get("sort_match")) {
+      if (!num_field(e, "sort_match", 0, 1, &v)) return SA_EINVAL;
+      te.t.sort_match = u32(v);
+    }
     if (!tuning_valid(te.t)) return SA_EINVAL;
     te.ms = num_field(e, "ms", 0, 1e12, &v) ? v : 0.0;
     out.entries.push_back(te);
@@ -252,6 +258,7 @@ std::string tune_format(const TuneTable& t) {
       << "\", \"log2n\": " << e.log2n << ", \"code_bits\": " << e.code_bits
       << ", \"sort_items\": " << e.t.sort_items << ", \"sort_wgs_per_cu\": "
       << e.t.sort_wgs_per_cu << ", \"sort_block\": " << e.t.sort_block
+      << ", \"sort_match\": " << e.t.sort_match
       << ", \"lazy_ratio\": " << e.t.lazy_ratio
       << ", \"round0_full\": " << e.t.round0_full << ", \"ms\": " << ms << "}";
   }
@@ -311,6 +318,7 @@ void apply_tuning(sa_ctx* c, const sa_tuning& t) {
   c->lazy_ratio = t.lazy_ratio;
   c->round0_trim = t.round0_full ? 0 : 1;
   c->sort_wgs_per_cu = int(t.sort_wgs_per_cu);
+  c->sort_match = int(t.sort_match);
 }
 
 sa_tuning current_tuning(const sa_ctx* c) {
@@ -321,6 +329,7 @@ sa_tuning current_tuning(const sa_ctx* c) {
   t.lazy_ratio = u32(c->lazy_ratio);
   t.round0_full = c->round0_trim ? 0u : 1u;
   t.sort_wgs_per_cu = u32(c->sort_wgs_per_cu);
+  t.sort_match = u32(c->sort_match);
   return t;
 }
 
@@ -425,9 +434,10 @@ sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets
     if (e != SA_OK) return e;
     if (log) {
       std::fprintf(stderr,
-                   "sa_tune: items %u block %u wgs/cu %u round0_full %u lazy_ratio %u: %.3f ms\n",
-                   t.sort_items, t.sort_block, t.sort_wgs_per_cu, t.round0_full, t.lazy_ratio,
-                   ms);
+                   "sa_tune: items %u block %u wgs/cu %u match %u round0_full %u lazy_ratio %u: "
+                   "%.3f ms\n",
+                   t.sort_items, t.sort_block, t.sort_wgs_per_cu, t.sort_match, t.round0_full,
+                   t.lazy_ratio, ms);
       std::fflush(stderr);
     }
     if (best_t == 0 || ms < best_t) {
@@ -451,12 +461,18 @@ sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets
       t.sort_items = sh.items;
       t.sort_block = sh.block;
       t.sort_wgs_per_cu = w;
-      if (w != 0 && int(w) == default_wgs_per_cu(int(sh.items), int(sh.block)))
+      if (w != 0 && int(w) == default_wgs_per_cu(int(sh.items), int(sh.block), false))
         continue;  // same as w = 0
       st = trial(t);
     }
   }
-  // Stage 2: round-0 key width; stage 3: the lazy-ISA threshold.
+  // Stage 2: digit matching of the sweep; stage 3: round-0 key width;
+  // stage 4: the lazy-ISA threshold.
+  if (st == SA_OK) {
+    sa_tuning t = best;
+    t.sort_match = 1;
+    st = trial(t);
+  }
   if (st == SA_OK) {
     sa_tuning t = best;
     t.round0_full = 1 - best.round0_full;

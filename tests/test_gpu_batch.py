@@ -107,6 +107,20 @@ def test_batch_isa_modes(builder, mode):
         assert info["lazy_isa"] == 1
 
 
+@pytest.mark.parametrize("match", [0, 1])
+def test_batch_digit_match(builder, match):
+    """Both sweep digit matches on multi-text keys (slot bits on top)."""
+    rng = np.random.default_rng(40 + match)
+    texts = mixed_texts(rng, 200, 5000)
+    builder.set_tuning(sort_match=match)
+    try:
+        sa, off = run_batch(builder, texts)
+        assert builder.tuning()["sort_match"] == match
+    finally:
+        builder.auto_tuning()
+    check_each(texts, sa, off)
+
+
 def test_batch_lazy_at_scale(builder):
     """Many Markov and DNA texts (2^24 suffixes in all): few suffixes survive
     round 0, so the automatic choice is the lazy ISA."""

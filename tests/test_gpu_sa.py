@@ -321,11 +321,13 @@ def test_full_size(builder, kind):
     sampled_direct_check(t, sa)
 
 
+@pytest.mark.parametrize("match", [0, 1])
 @pytest.mark.parametrize("items,block", [(8, 256), (12, 256), (16, 256), (20, 256), (24, 256),
                                          (4, 512), (8, 512), (12, 512)])
-def test_sort_tile_variants(builder, items, block):
-    """Every radix-sort tile shape sorts stably and builds the same SA."""
-    builder.set_tuning(sort_items=items, sort_block=block)
+def test_sort_tile_variants(builder, items, block, match):
+    """Every radix-sort tile shape, with either digit match, sorts stably and
+    builds the same SA."""
+    builder.set_tuning(sort_items=items, sort_block=block, sort_match=match)
     try:
         rng = np.random.default_rng(items)
         count = 100003
@@ -344,13 +346,13 @@ def test_sort_tile_variants(builder, items, block):
         builder.auto_tuning()
 
 
-@pytest.mark.parametrize("items,block", [(8, 512), (8, 256)])
-def test_radix_sort_skewed_next_digit(builder, items, block):
+@pytest.mark.parametrize("items,block,match", [(8, 512, 0), (8, 512, 1), (8, 256, 0)])
+def test_radix_sort_skewed_next_digit(builder, items, block, match):
     """2^26 keys whose low digit is 0 or 1 and whose next digit is almost
     always 0: each sweep workgroup counts far more than 65535 elements into
     one (output chunk, next digit) bin, so its 16-bit LDS counts must move to
     the global histogram before they overflow."""
-    builder.set_tuning(sort_items=items, sort_block=block)
+    builder.set_tuning(sort_items=items, sort_block=block, sort_match=match)
     try:
         rng = np.random.default_rng(items * block)
         count = 1 << 26

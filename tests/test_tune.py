@@ -66,9 +66,10 @@ def test_knobs_round_trip(tmp_path):
     found, t = _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)
     assert found
     assert t == {"sort_items": 12, "sort_wgs_per_cu": 6, "lazy_ratio": 64, "round0_full": 1,
-                 "sort_block": 256}
-    p = write(tmp_path, [entry(sort_items=8, sort_block=512)])
-    assert _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)[1]["sort_block"] == 512
+                 "sort_block": 256, "sort_match": 0}
+    p = write(tmp_path, [entry(sort_items=8, sort_block=512, sort_match=1)])
+    t = _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)[1]
+    assert t["sort_block"] == 512 and t["sort_match"] == 1
 
 
 @pytest.mark.parametrize("bad", [
@@ -86,7 +87,7 @@ def test_malformed_files_are_rejected(tmp_path, bad):
 @pytest.mark.parametrize("knob", [{"sort_items": 10}, {"lazy_ratio": 2}, {"round0_full": 2},
                                   {"sort_wgs_per_cu": 17}, {"log2n": 64}, {"mode": "serve"},
                                   {"sort_block": 384}, {"sort_block": 512, "sort_items": 16},
-                                  {"sort_items": 4}])
+                                  {"sort_items": 4}, {"sort_match": 2}])
 def test_invalid_knobs_are_rejected(tmp_path, knob):
     p = write(tmp_path, [entry(**knob)])
     with pytest.raises(SAError):
