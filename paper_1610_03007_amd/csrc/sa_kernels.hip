@@ -505,9 +505,9 @@ void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPla
 // One stable counting sweep over digit `pass`, persistent: workgroup b works on
 // chunk b % nchunks and takes that chunk's tiles in order from a ticket. Per
 // tile of BLOCK * ITEMS pairs: load ITEMS items per thread in
-// wave-striped order; rank every item among the equal digits of its wave (an
-// eight-ballot match mask, and one LDS fetch-add per match group issued back
-// to back for all items, which a wave executes in program order); combine the
+// wave-striped order; rank every item among the equal digits of its wave (a
+// match mask of the lanes with its digit, and one LDS fetch-add per match group
+// issued back to back for all items, which a wave executes in program order); combine the
 // waves; publish the tile's digit counts and look back (inside the chunk) for
 // the counts of earlier tiles; reorder the keys by digit in LDS and write each
 // digit's run out contiguously, then the values through the same LDS buffer.
