@@ -68,11 +68,12 @@ void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const 
 
 // Re-rank the sorted active set, scatter the ISA, finalize unique suffixes into
 // the SA and compact the survivors.
-// mode: kRerankScatterIsa writes ISA[text position] = new rank for every element;
-// kRerankWriteRanks writes the new rank of sorted position p into the value
-// buffer the sort did not end in.
+// mode: kRerankScatterIsa writes ISA[text position] = new rank for every element
+// (in rounds after a text's round 0, only where the rank changed);
+// kRerankIsaOnly, with it, writes nothing else (no SA entries, no survivors,
+// no survivor count): the eager ISA after a round 0 that ran without it.
 constexpr int kRerankScatterIsa = 1;
-constexpr int kRerankWriteRanks = 2;
+constexpr int kRerankIsaOnly = 4;
 // Key layout of the sorted set:
 //   group     = key >> gshift (64: one group, round 0 of a single text)
 //   old rank  = (key >> rshift) & rmask (rmask 0: every element has rank 1)
@@ -100,12 +101,10 @@ void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            u32* isa, u32* sa_out, u32* act_idx, u64* act_ti, u32* act_rank,
                            u64* counters, hipStream_t s);
 
-// ISA after round 0. Eager: ISA[vals[p]] = ranks[p] over the sorted pairs (the
-// ranks written by the re-rank with kRerankWriteRanks). Lazy: ISA cleared,
-// survivors scattered from the active list, and zero entries resolved on
-// demand by a binary search in the round-0 sorted keys `keys0`.
-void launch_isa_scatter_sorted(const u32* valsA, const u32* valsB, const SortPlan* plan, u64 n,
-                               u32* isa, hipStream_t s);
+// ISA after round 0. Eager: the round-0 re-rank again, with kRerankIsaOnly.
+// Lazy: survivors scattered from the active list and marked in the live-position
+// bitmap; other names resolved on demand by a binary search in the round-0
+// sorted keys `keys0`.
 void launch_isa_scatter_list(const u32* idx, const u32* rank, u64 count, u64 n, u32* isa,
                              u32* live, hipStream_t s);
 // Lazy ISA: sample[i] = keys0[i * n / kLazySamples] of the round-0 sorted keys,
@@ -158,9 +157,6 @@ void launch_multi_pack0(const u8* arena, TextTab tab, NewList nl, int idshift, u
 // Batched build with a lazy ISA after round 0 (see sa_kernels.hip).
 void launch_multi_isa_scatter_list(const u64* act_ti, const u32* act_rank, const u64* count_ptr,
                                    u64 bound, TextTab tab, u32* isa, u32* live, hipStream_t s);
-void launch_multi_isa_scatter_sorted(const u64* keys, const u32* vals, const u32* ranks,
-                                     u64 count, TextTab tab, int idshift, u32* isa,
-                                     hipStream_t s);
 void launch_multi_pack_pairs_lazy(const u64* act_ti, const u32* act_rank, u64 count, TextTab tab,
                                   int b, int idshift, const u32* isa, const u32* live,
                                   const u8* arena, const u64* keys0, u64* keys, u32* vals,

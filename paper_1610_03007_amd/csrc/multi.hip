@@ -47,13 +47,14 @@ struct Engine {
          o_up_no = 0, o_up_nc = 0;
   u64 active = 0;         // survivors carried into the next round
   std::vector<u32> live;  // slots with elements in the active set or joining now
-  // Batched build only (every text starts round 0 together): round 0 writes
-  // the sorted positions' names instead of scattering the ISA, and the ISA is
-  // then formed eagerly or, when few suffixes survive, lazily.
+  // Batched build only (every text starts round 0 together): round 0 writes no
+  // ISA; it is then formed eagerly (an ISA-only second pass of the round-0
+  // re-rank) or, when few suffixes survive, lazily.
   bool batch_round0_ranks = false;
   bool lazy = false;           // the ISA holds the survivors' names only (live bitmap)
   const u64* keys0 = nullptr;  // lazy: round-0 sorted keys
   Bufs later{};                // lazy: later rounds' buffers, carved from the spare keys
+  RerankArgs last_args{};      // the last round's re-rank
 
   ~Engine() { release(); }
   void release() {
@@ -202,11 +203,12 @@ struct Engine {
       a.rshift = B;
       a.rmask = (u64(1) << B) - 1;
       a.idshift = idshift;
-      a.mode = (batch_round0_ranks && m) ? kRerankWriteRanks : kRerankScatterIsa;
+      a.mode = (batch_round0_ranks && m) ? 0 : kRerankScatterIsa;
       a.tbase = tab.base;
       a.tlen = tab.len;
       a.tround0 = tab.round0;
       run_rerank(c, bufs, a, sa_arena, s);
+      last_args = a;
       // Survivors per text; their number is read on the device.
       Tracer tr(c, s, SA_KERNEL_OTHER, 0);
       launch_multi_count_survivors(c->act_ti, c->counters + kCtrActive, total, tab.surv, s);
@@ -239,14 +241,12 @@ struct Engine {
   }
 
   // Batched build, after round 0 (which ran with batch_round0_ranks): forms the
-  // ISA eagerly from the sorted names, or lazily (survivors only) when at most
+  // ISA eagerly (every name), or lazily (survivors only) when at most
   // 1/lazy_ratio of the n suffixes survive and the later rounds' buffers fit in
   // the spare keys (the context's ISA mode may force either form).
   sa_status form_isa_after_round0(u64 n, hipStream_t s) {
     const u32 f0 = final_buf_of(c, 0);
     const u64* k0 = f0 ? c->keysB : c->keysA;
-    const u32* vals0 = f0 ? c->valsB : c->valsA;
-    const u32* ranks0 = f0 ? c->valsA : c->valsB;
     u64* spare = f0 ? c->keysA : c->keysB;
     const u64 a1 = (std::max<u64>(active, 1) + 63) / 64 * 64;
     const bool fits = a1 * 24 <= n * 8;
@@ -267,8 +267,11 @@ struct Engine {
       later.vA = reinterpret_cast<u32*>(spare + 2 * a1);
       later.vB = later.vA + a1;
     } else if (active > 0) {
-      Tracer t(c, s, SA_KERNEL_ISA_SCATTER, double(n) * 20.0);
-      launch_multi_isa_scatter_sorted(k0, vals0, ranks0, n, tab, 64 - idbits, c->isa, s);
+      // The round-0 re-rank again (same sorted pairs, same per-text tables),
+      // writing only the ISA.
+      RerankArgs a = last_args;
+      a.mode = kRerankScatterIsa | kRerankIsaOnly;
+      run_rerank(c, full_bufs(c), a, nullptr, s);
     }
     return SA_OK;
   }

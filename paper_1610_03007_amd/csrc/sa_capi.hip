@@ -188,9 +188,11 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
 
 void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s) {
   const double count = double(args.count);
-  double bytes = count * 16.0 + ((args.mode & kRerankWriteRanks) ? 4.0 * count : 0.0) -
-                 ((args.mode & kRerankScatterIsa) ? 0.0 : 4.0 * count);
-  Tracer t(c, s, SA_KERNEL_RERANK, bytes);
+  // 12 bytes read per element; 4 written (ISA, SA or survivor name) plus 4 for a
+  // survivor's position, counted as 4 per element either way.
+  double bytes = count * 16.0 - ((args.mode & kRerankScatterIsa) ? 0.0 : 4.0 * count);
+  if (args.mode & kRerankIsaOnly) bytes = count * 16.0;
+  Tracer t(c, s, (args.mode & kRerankIsaOnly) ? SA_KERNEL_ISA_SCATTER : SA_KERNEL_RERANK, bytes);
   launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->isa, d_sa,
                         args.tbase ? nullptr : c->act_idx, args.tbase ? c->act_ti : nullptr,
                         c->act_rank, c->counters, s);
@@ -265,7 +267,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
     launch_pack_text(text, n, c->code, c->counters, c->keysA, s);
   }
   run_sort(c, full, n, kMaxPasses, 0, 0, s);
-  run_rerank(c, full, single_args(n, n, 0, kRerankWriteRanks), d_sa, s);
+  run_rerank(c, full, single_args(n, n, 0, 0), d_sa, s);
   st = readback(c, s);
   if (st != SA_OK) return st;
 
@@ -302,8 +304,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
       launch_isa_scatter_list(c->act_idx, c->act_rank, active, n, c->isa, c->live, s);
       launch_lazy_sample(keys0, n, c->sample, s);
     } else {
-      Tracer t(c, s, SA_KERNEL_ISA_SCATTER, double(n) * 12.0);
-      launch_isa_scatter_sorted(c->valsA, c->valsB, c->plan, n, c->isa, s);
+      run_rerank(c, full, single_args(n, n, 0, kRerankScatterIsa | kRerankIsaOnly), d_sa, s);
     }
   }
   // Later rounds sort at most `active` pairs; in lazy mode their buffers are

@@ -991,11 +991,8 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const u32 fb = plan->final_buf;
   const u64* keys = fb ? keysB : keysA;
   const u32* vals = fb ? valsB : valsA;
-  // The other value buffer is free after the sort: it receives the new rank
-  // of every sorted position when kRerankWriteRanks is set.
-  u32* ranks_out = const_cast<u32*>(fb ? valsA : valsB);
   const bool scatter = (mode & kRerankScatterIsa) != 0;
-  const bool write_ranks = (mode & kRerankWriteRanks) != 0;
+  const bool isa_only = (mode & kRerankIsaOnly) != 0;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
@@ -1079,7 +1076,8 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     u32 tts = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) tts += s_ws[w];
-    s_prefix[2] = tts ? atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
+    s_prefix[2] = (tts && !isa_only)
+                      ? atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
                                   (unsigned long long)tts)
                       : 0;
   }
@@ -1138,7 +1136,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     // that did not change (a group that did not split, or the first sub-group
     // of one that did) is not written again.
     if (scatter && (first_round || nr != r0)) isa[gb + v[r]] = u32(nr);
-    if (write_ranks) ranks_out[e] = u32(nr);
+    if (isa_only) continue;
     if (uniq) {
       sa_out[gb + nr - 1] = v[r];
     } else {
@@ -1169,31 +1167,13 @@ void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
 // Inverse suffix array after round 0.
 //
 // Eager form: ISA[text position] = rank for every sorted position (one random
-// 4-byte write per suffix). Lazy form, used when few suffixes survive round 0:
+// 4-byte write per suffix), written by a second pass of the round-0 re-rank.
+// Round 0 itself writes no ISA, so that the lazy form, used when few suffixes
+// survive round 0, pays for no rank array either:
 // only the survivors' ranks are written and marked in a bitmap of live
 // positions; a later gather of an unmarked position j recomputes its round-0
 // rank as 1 + the number of round-0 keys below key(j), by binary search in the
 // round-0 sorted keys (the name is the head rank of j's run of equal keys).
-
-__global__ __launch_bounds__(256) void isa_scatter_sorted_kernel(const u32* __restrict__ valsA,
-                                                                 const u32* __restrict__ valsB,
-                                                                 const SortPlan* __restrict__ plan,
-                                                                 u64 n, u32* __restrict__ isa) {
-  const u32 fb = plan->final_buf;
-  const u32* vals = fb ? valsB : valsA;
-  const u32* ranks = fb ? valsA : valsB;
-  u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= n) return;
-  const u32 v = vals[p];
-  if (v < n) isa[v] = ranks[p];
-}
-
-void launch_isa_scatter_sorted(const u32* valsA, const u32* valsB, const SortPlan* plan, u64 n,
-                               u32* isa, hipStream_t s) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(isa_scatter_sorted_kernel, dim3(u32(ceil_div(n, 256))), dim3(256), 0, s,
-                     valsA, valsB, plan, n, isa);
-}
 
 __global__ __launch_bounds__(256) void isa_scatter_list_kernel(const u32* __restrict__ idx,
                                                                const u32* __restrict__ rank,
@@ -1573,25 +1553,6 @@ void launch_multi_isa_scatter_list(const u64* act_ti, const u32* act_rank, const
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(multi_isa_scatter_list_kernel, dim3(u32(blocks)), dim3(256), 0, s, act_ti,
                      act_rank, count_ptr, tab, isa, live);
-}
-
-// Eager ISA after a batched round 0: every sorted position's name.
-__global__ __launch_bounds__(256) void multi_isa_scatter_sorted_kernel(
-    const u64* __restrict__ keys, const u32* __restrict__ vals, const u32* __restrict__ ranks,
-    u64 count, TextTab tab, int idshift, u32* __restrict__ isa) {
-  const u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-  const u64 t = keys[p] >> idshift;
-  const u32 v = vals[p];
-  if (v < tab.len[t]) isa[tab.base[t] + v] = ranks[p];
-}
-
-void launch_multi_isa_scatter_sorted(const u64* keys, const u32* vals, const u32* ranks,
-                                     u64 count, TextTab tab, int idshift, u32* isa,
-                                     hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(multi_isa_scatter_sorted_kernel, dim3(u32(ceil_div(count, 256))), dim3(256),
-                     0, s, keys, vals, ranks, count, tab, idshift, isa);
 }
 
 __global__ __launch_bounds__(256) void multi_pack_pairs_lazy_kernel(
