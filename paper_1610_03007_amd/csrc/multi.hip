@@ -50,7 +50,7 @@ struct Engine {
   // Batched build only (every text starts round 0 together): round 0 writes no
   // ISA; it is then formed eagerly (an ISA-only second pass of the round-0
   // re-rank) or, when few suffixes survive, lazily.
-  bool batch_round0_ranks = false;
+  bool defer_round0_isa = false;
   bool lazy = false;           // the ISA holds the survivors' names only (live bitmap)
   const u64* keys0 = nullptr;  // lazy: round-0 sorted keys
   Bufs later{};                // lazy: later rounds' buffers, carved from the spare keys
@@ -203,7 +203,7 @@ struct Engine {
       a.rshift = B;
       a.rmask = (u64(1) << B) - 1;
       a.idshift = idshift;
-      a.mode = (batch_round0_ranks && m) ? 0 : kRerankScatterIsa;
+      a.mode = (defer_round0_isa && m) ? 0 : kRerankScatterIsa;
       a.tbase = tab.base;
       a.tlen = tab.len;
       a.tround0 = tab.round0;
@@ -240,7 +240,7 @@ struct Engine {
     return SA_OK;
   }
 
-  // Batched build, after round 0 (which ran with batch_round0_ranks): forms the
+  // Batched build, after round 0 (which ran with defer_round0_isa): forms the
   // ISA eagerly (every name), or lazily (survivors only) when at most
   // 1/lazy_ratio of the n suffixes survive and the later rounds' buffers fit in
   // the spare keys (the context's ISA mode may force either form).
@@ -321,7 +321,7 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
   Engine eng;
   st = eng.init(c, T, idbits, B);
   if (st != SA_OK) return st;
-  eng.batch_round0_ranks = true;
+  eng.defer_round0_isa = true;
   std::vector<u32> joining;
   for (u32 t = 0; t < T; ++t) {
     eng.base[t] = h_off[t];
@@ -344,7 +344,7 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
     if (r == 0) {
       st = eng.form_isa_after_round0(N, s);
       if (st != SA_OK) return st;
-      eng.batch_round0_ranks = false;
+      eng.defer_round0_isa = false;
       info.lazy_isa = eng.lazy ? 1u : 0u;
     }
     if (eng.active == 0) break;

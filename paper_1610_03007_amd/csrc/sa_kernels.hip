@@ -517,10 +517,12 @@ void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPla
 // could carry a half past 32767 + 32767, the halves at or above 32768 move to
 // the global histogram first.
 // Shapes of at most 8 items per thread are held to 128 registers: 4 waves per
-// SIMD, two 512-thread workgroups per CU. TABLE selects how a wave finds the
-// lanes that hold the same digit (see the ranking below).
+// SIMD, two 512-thread workgroups per CU (the 256-thread table variant, which
+// LDS limits to three workgroups per CU anyway, to 168). TABLE selects how a
+// wave finds the lanes that hold the same digit (see the ranking below).
 template <int ITEMS, int BLOCK, bool TABLE>
-__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(ITEMS <= 8 ? 4 : 1)))
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
+    ITEMS <= 8 ? ((TABLE && BLOCK == 256) ? 3 : 4) : 1)))
 void onesweep_pass_kernel(
     u64* __restrict__ keysA, u64* __restrict__ keysB, u32* __restrict__ valsA,
     u32* __restrict__ valsB, u64 count, int pass, u32 ct_log2, u32 nchunks,
