@@ -301,6 +301,9 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
   const u64 N = h_off[T];
   c->info.n = N;
   if (max_n >= (u64(1) << 32)) return SA_ETOOBIG;
+  // The radix sweep forms output chunk indices in 32 bits from positions
+  // shifted right by at least 10 bits; no batch that fits in memory comes near.
+  if (N >= (u64(1) << 40)) return SA_ETOOBIG;
   if (N == 0) return SA_OK;
   if (!text || !d_sa) return SA_EINVAL;
   if (T == 1) return build_rounds(c, text, N, 0, d_sa, nullptr, s);
