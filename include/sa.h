@@ -76,9 +76,10 @@ sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigm
  *   d_sas:     device u32[offsets[num_texts]]; text t's suffix array (local
  *              positions, values < n_t) is written to d_sas[offsets[t] ..).
  * Errors: SA_EINVAL for null pointers, num_texts = 0, offsets[0] != 0 or
- * decreasing offsets; SA_ETOOBIG if a text has 2^32 or more bytes, or if
- * bits(num_texts - 1) + 2 * bits(longest text) > 64 (the key layout).
- * The total may exceed 2^32. Workspace: about 45 bytes per byte of all texts. */
+ * decreasing offsets; SA_ETOOBIG if a text has 2^32 or more bytes, if
+ * bits(num_texts - 1) + 2 * bits(longest text) > 64 (the key layout), or if
+ * the total reaches 2^40 bytes. The total may exceed 2^32. Workspace: about 45
+ * bytes per byte of all texts. */
 sa_status sa_build_batch(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets,
                          uint32_t num_texts, uint32_t* d_sas, void* stream);
 
