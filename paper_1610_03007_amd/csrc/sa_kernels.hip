@@ -19,6 +19,13 @@ namespace {
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// The 8-bit digit at bit `shift` (a multiple of 8, the same in every lane) of a
+// key, with 32-bit operations: the word that holds it, then a bit-field extract.
+__device__ inline u32 digit_of(u64 k, int shift) {
+  const u32 word = shift >= 32 ? u32(k >> 32) : u32(k);
+  return __builtin_amdgcn_ubfe(word, u32(shift & 31), 8u);
+}
+
 
 __device__ inline u32 wave_inclusive_sum(u32 v) {
   const int lane = lane_id();
@@ -692,7 +699,7 @@ void onesweep_pass_kernel(
     u32 packed[ITEMS];  // below | leader << 8
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const u32 d = u32(key[j] >> shift) & (kRadix - 1);
+      const u32 d = digit_of(key[j], shift);
       u64 peers;
       if constexpr (TABLE) {
         // Every lane ORs its bit into the wave's table entry of its digit,
@@ -773,7 +780,7 @@ void onesweep_pass_kernel(
     // offset in that run, its rank in the wave.
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const u32 d = u32(key[j] >> shift) & (kRadix - 1);
+      const u32 d = digit_of(key[j], shift);
       rank[j] += s_start[d] + ((s_cnt[wave >> 1][d] >> half) & 0xFFFFu);
       s_buf[rank[j]] = key[j];
     }
@@ -792,7 +799,7 @@ void onesweep_pass_kernel(
       const u32 q = u32(tid + i * BLOCK);
       if (q < valid) {
         const u64 k = s_buf[q];
-        const u32 d = u32(k >> shift) & (kRadix - 1);
+        const u32 d = digit_of(k, shift);
         qdig[i / 4] |= d << (8 * (i % 4));
         const u64 o = s_base[d] + q;
         if (o < count) {
@@ -801,7 +808,7 @@ void onesweep_pass_kernel(
             // Output chunk o / (TILE << ct_log2), with TILE = kTileOdd << kTileTz:
             // a 32-bit division by the odd factor (o < 2^(32 + kTileTz)).
             const u32 bin = ((u32(o >> kTileTz) / kTileOdd) >> ct_log2) * kRadix +
-                            (u32(k >> nshift) & (kRadix - 1));
+                            digit_of(k, nshift);
             atomicAdd(&s_next[bin >> 1], 1u << (16 * (bin & 1u)));
           }
         }
