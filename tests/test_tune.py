@@ -27,6 +27,22 @@ def write(tmp_path, entries, fmt=FORMAT):
     return str(p)
 
 
+def test_tuning_struct_layout():
+    """The binding's sa_tuning mirror has the header's eight 32-bit fields, in
+    order (the library writes the whole struct)."""
+    import ctypes
+    names = [f[0] for f in _native.Tuning._fields_]
+    assert names == ["sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu", "sort_block",
+                     "sort_match", "reserved"]
+    assert ctypes.sizeof(_native.Tuning) == 32
+    header = open(os.path.join(os.path.dirname(__file__), "..", "include", "sa.h")).read()
+    body = header[header.index("typedef struct {\n  uint32_t sort_items;"):]
+    body = body[:body.index("} sa_tuning;")]
+    fields = [line.split()[1].rstrip(";").split("[")[0] for line in body.splitlines()[1:]
+              if line.strip().startswith("uint32_t")]
+    assert fields == names
+
+
 def test_missing_file_gives_defaults(tmp_path):
     found, t = _native.tune_lookup(str(tmp_path / "none.json"), "gfx950", "single", 1 << 20)
     assert not found
