@@ -1,14 +1,26 @@
 #!/usr/bin/env python3
-"""Benchmark: suffix-array construction throughput on one MI355X.
+"""Benchmark: suffix-array construction on one MI355X.
 
-One step = one complete sa_build (every doubling round: key packing, radix
-sort, re-rank / ISA scatter / discard) of the 256 MiB order-3 Markov text over
-96 printable bytes, with the text already resident in HBM. Prints one JSON line
-with Msuffixes/s, the HBM roofline of the dominant kernel (the radix-sort
-sweep) measured with HIP events inside the timed steps, and the CPU oracle
-timed on a bounded sample on the host cores.
+The default run measures every workload of the suffix-array hot path and prints
+one JSON line. Its headline (``value``) is the largest single-GPU workload: one
+batched build of 4096 texts (4.46e9 bytes in all). One step is one complete
+``sa_build_batch`` (every doubling round: key packing, radix sort, re-rank / ISA
+scatter / discard) with the texts already resident in HBM. ``configs`` carries
+a record per workload:
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+* ``batch_4096`` -- batched vs per-text (one ``sa_build`` per text, same GPU);
+* ``repetitive_1g``, ``markov_256m``, ``dna_1m`` -- one text per ``sa_build``;
+* ``serve`` -- a Poisson request stream through the continuous-batching server
+  and through one ``sa_build`` per request: p50/p99 latency, sustained
+  throughput, and capacity with a burst of requests.
+
+Every build record has Msuffixes/s, the whole-build HBM roofline (algorithmic
+bytes of the method over the build time, against 8 TB/s), the radix-sort sweep's
+roofline from HIP events around each launch, a per-kernel table, and the CPU
+oracle (plain prefix doubling) timed on a bounded sample at one thread and on
+all host cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload all|NAME]
 """
 
 from __future__ import annotations
@@ -17,6 +29,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -24,19 +37,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = "Msuffixes/s on 1 GPU + HBM roofline %; batched vs per-text; p50/p99 latency"
 WORKLOADS = {
-    "markov_256m": "order-3 Markov text, 96 printable bytes, Dirichlet(0.1) rows, n=2^28",
-    "dna_1m": "uniform ACGT text, seed 0, n=2^20",
-    "repetitive_1g": "256 KiB base x 4096 copies, 1e-4 substitutions, n=2^30",
     "batch_4096": "4096 texts, lengths log-uniform in [4 KiB, 8 MiB], half ACGT, half "
                   "order-3 Markov (96 bytes); one batched build",
+    "repetitive_1g": "256 KiB base x 4096 copies, 1e-4 substitutions, n=2^30",
+    "markov_256m": "order-3 Markov text, 96 printable bytes, Dirichlet(0.1) rows, n=2^28",
+    "dna_1m": "uniform ACGT text, seed 0, n=2^20",
     "serve": "Poisson arrivals at 330.5 req/s (2 GB/s of text), lengths log-uniform in "
              "[1 KiB, 64 MiB], ACGT or Markov slices; continuous-batching server",
 }
+BUILD_ORDER = ("batch_4096", "repetitive_1g", "markov_256m", "dna_1m")
 SERVE_RATE = 330.5
 SERVE_LO, SERVE_HI = 1024, 1 << 26
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1610_03007_amd", "csrc", "sa_kernels.hip")
+
+# Bounded CPU-oracle samples (bytes): (one thread, all cores).
+CPU_SAMPLES = {
+    "batch_4096": (1 << 24, 1 << 26),
+    "repetitive_1g": (1 << 23, 1 << 25),
+    "markov_256m": (1 << 24, 1 << 28),
+    "dna_1m": (1 << 20, 1 << 20),
+}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def make_text(name: str):
@@ -44,17 +71,12 @@ def make_text(name: str):
     import workloads as W
     if name == "batch_4096":
         return W.batch()
-    return make_single(name), None
-
-
-def make_single(name: str):
-    import workloads as W
     if name == "markov_256m":
-        return W.markov3(1 << 28, chain_seed=2)
+        return W.markov3(1 << 28, chain_seed=2), None
     if name == "dna_1m":
-        return W.dna(1 << 20, seed=0)
+        return W.dna(1 << 20, seed=0), None
     if name == "repetitive_1g":
-        return W.repetitive()
+        return W.repetitive(), None
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -76,22 +98,50 @@ def measured_traffic(workload: str):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(text, sample: int, offsets=None):
+def algorithmic_bytes(info: dict) -> float:
+    """Bytes the method must move for one build (whole-build roofline):
+    13 per suffix for the round-0 keys (text, key, value), 4 per suffix for the
+    SA, and per round k with A_k suffixes sorted in P_k radix passes:
+    A_k * (24 P_k + 24) (sweeps, the up-front histogram and the re-rank),
+    24 A_k for the pair build (k >= 1) and 8 A_{k+1} for the survivors."""
+    A, P, n = info["active"], info["passes_run"], info["n"]
+    b = 17.0 * n
+    for k, a in enumerate(A):
+        b += a * (24.0 * P[k] + 24.0)
+        if k >= 1:
+            b += 24.0 * a
+        if k + 1 < len(A):
+            b += 8.0 * A[k + 1]
+    return b
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def time_oracle(text, offsets, sample: int, parallel: bool) -> dict:
+    """The CPU oracle on the first `sample` bytes (one text) or on whole texts
+    of a batch in order until `sample` bytes."""
     import oracle
     if offsets is None:
         s = text[:sample].copy()
         t0 = time.perf_counter()
-        oracle.sa(s, parallel=True)
+        oracle.sa(s, parallel=parallel)
         dt = time.perf_counter() - t0
-        total = s.size
-        what = f"first {s.size} bytes of the same text"
+        total, what = s.size, f"first {s.size} bytes of the text"
     else:
-        # Whole texts of the batch, in order, until the sample size is reached.
         t0 = time.perf_counter()
         total = ntexts = 0
         for t in range(offsets.size - 1):
             a, b = int(offsets[t]), int(offsets[t + 1])
-            oracle.sa(text[a:b], parallel=True)
+            oracle.sa(text[a:b], parallel=parallel)
             total += b - a
             ntexts += 1
             if total >= sample:
@@ -101,11 +151,145 @@ def cpu_baseline(text, sample: int, offsets=None):
     return {
         "value": round(total / dt / 1e6, 3),
         "unit": "Msuffixes/s",
-        "cores": oracle.num_threads(parallel=True),
+        "cores": oracle.num_threads(parallel=parallel),
         "kind": "oracle",
-        "sample": f"{what}, plain prefix doubling (GNU parallel std::sort), {dt:.2f} s",
+        "sample": f"{what}; plain prefix doubling, "
+                  f"{'GNU parallel std::sort' if parallel else 'std::sort, one thread'}; "
+                  f"{dt:.2f} s",
     }
 
+
+def cpu_rows(name: str, text, offsets) -> dict:
+    one, alln = CPU_SAMPLES[name]
+    log(f"{name}: CPU oracle, one thread on {one} bytes, all cores on {alln} bytes")
+    par = time_oracle(text, offsets, min(alln, text.size), parallel=True)
+    seq = time_oracle(text, offsets, min(one, text.size), parallel=False)
+    par["single_thread"] = seq
+    par["cpu_model"] = cpu_model()
+    par["nproc"] = os.cpu_count()
+    return par
+
+
+def kernel_table(stats: dict, steps: int) -> dict:
+    out = {}
+    for k, v in stats.items():
+        if v["launches"] == 0:
+            continue
+        gbs = v["bytes"] / (v["ms"] / 1e3) / 1e9 if v["ms"] > 0 else 0.0
+        out[k] = {"ms_per_step": round(v["ms"] / steps, 4), "launches": v["launches"],
+                  "gb_s": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
+
+
+def run_build(name: str, steps: int, warmup: int, cpu: bool, sort_items: int = 0) -> dict:
+    """Times `steps` builds of one workload (HIP events on the build stream)."""
+    import torch
+
+    from paper_1610_03007_amd import SuffixArrayBuilder
+
+    t_gen = time.perf_counter()
+    text, offsets = make_text(name)
+    n = int(text.size)
+    log(f"{name}: n={n} generated in {time.perf_counter() - t_gen:.1f}s")
+    dev = torch.device("cuda", 0)
+    d_text = torch.from_numpy(text).to(dev)
+    d_sa = torch.empty(n, dtype=torch.int32, device=dev)
+    b = SuffixArrayBuilder(0)
+    if sort_items:
+        b.set_tuning(sort_items=sort_items)
+
+    def step():
+        if offsets is None:
+            b.build(d_text, out=d_sa)
+        else:
+            b.build_batch(d_text, offsets, out=d_sa)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    b.reset_stats()
+    b.set_trace(True)
+    stream = torch.cuda.current_stream(dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    b.set_trace(False)
+    gpu_ms = ev0.elapsed_time(ev1)
+    info = b.last_info()
+    stats = b.kernel_stats()
+    ms = gpu_ms / steps
+    value = n / (ms / 1e3) / 1e6
+    balg = algorithmic_bytes(info)
+    whole = balg / (ms / 1e3) / 1e9
+    sweep = stats["sort_pass"]
+    achieved = sweep["bytes"] / (sweep["ms"] / 1e3) / 1e9 if sweep["ms"] > 0 else 0.0
+    rec = {
+        "workload": name,
+        "description": WORKLOADS[name],
+        "n": n,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_build": round(ms, 4),
+        "msuffixes_s": round(value, 2),
+        "whole_build_roofline": {
+            "bound": "hbm", "algorithmic_bytes": round(balg), "achieved": round(whole, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(whole / HBM_PEAK_GBS, 4)},
+        "sweep_roofline": {
+            "bound": "hbm", "kernel": "onesweep_pass_kernel", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(name),
+            "algorithmic_bytes_per_launch": round(sweep["bytes"] / max(1, sweep["launches"])),
+            "launches": sweep["launches"],
+            "avg_launch_us": round(sweep["ms"] * 1e3 / max(1, sweep["launches"]), 2)},
+        "rounds": info["rounds"],
+        "active_per_round": info["active"],
+        "passes_per_round": info["passes_run"],
+        "sigma": info["sigma"],
+        "chars_round0": info["chars0"],
+        "lazy_isa": info["lazy_isa"],
+        "tuning": b.tuning(),
+        "tuning_source": b.tuning_source(),
+        "kernels": kernel_table(stats, steps),
+        "wall_s": round(wall, 3),
+    }
+    log(f"{name}: {ms:.3f} ms/build, {value:.1f} Msuffixes/s, whole-build "
+        f"{rec['whole_build_roofline']['frac']:.3f} of peak, sweep "
+        f"{rec['sweep_roofline']['frac']:.3f}")
+    if offsets is not None:
+        # Per-text baseline on the same GPU: one sa_build per text, in order.
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for t in range(offsets.size - 1):
+            a, z = int(offsets[t]), int(offsets[t + 1])
+            if z > a:
+                b.build(d_text[a:z], out=d_sa[a:z])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per_text_ms = e0.elapsed_time(e1)
+        per_text = n / (per_text_ms / 1e3) / 1e6
+        rec["texts"] = int(offsets.size - 1)
+        rec["per_text"] = {"msuffixes_s": round(per_text, 2), "ms": round(per_text_ms, 2)}
+        rec["batched_vs_per_text"] = round(value / per_text, 3)
+        log(f"{name}: per-text {per_text:.1f} Msuffixes/s -> batched x{value / per_text:.2f}")
+    b.close()
+    del d_text, d_sa
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    rec["cpu_baseline"] = cpu_rows(name, text, offsets) if cpu else None
+    return rec
+
+
+# ---------------------------------------------------------------------------
+# Serving.
 
 def serve_stream(seconds: float, seed: int = 6):
     """Arrival times, lengths and generators of a Poisson request stream."""
@@ -126,16 +310,18 @@ def serve_pools():
     """1 GiB of each source; requests are slices at random offsets (the sources
     are stationary, so a slice stands for a fresh draw)."""
     import workloads as W
-    return [W.dna(1 << 30, seed=600), W.markov3(1 << 30, chain_seed=601)]
+    return [W.dna_long(1 << 30, seed=600), W.markov3(1 << 30, chain_seed=601)]
 
 
-def run_server_load(pools, stream, warm: float, mode: str):
+def run_server_load(pools, stream, warm: float, mode: str, digests: dict | None = None):
     """Replays the stream in real time. mode 'server': the continuous-batching
     server; 'per_text': one sa_build per request, first come first served.
     Returns (latencies of requests arriving after `warm` in ms, suffixes done in
-    the window, window seconds)."""
+    the window, window seconds, server stats). With `digests`, the SA of every
+    16th request is hashed into it (key: request index) or compared with it."""
     import queue
     import threading
+
     import numpy as np
     import torch
     t_arr, lens, kind, off = stream
@@ -146,7 +332,17 @@ def run_server_load(pools, stream, warm: float, mode: str):
         texts.append(pool[a:a + int(n)])
     lat = {}
     done_sufs = [0]
-    t_end = float(t_arr[-1]) if len(t_arr) else 0.0
+    mismatches = [0]
+
+    def digest(i, sa_host):
+        if digests is None or i % 16:
+            return
+        h = hashlib.sha256(np.ascontiguousarray(sa_host).view(np.uint8)).hexdigest()
+        if i in digests:
+            mismatches[0] += digests[i] != h
+        else:
+            digests[i] = h
+
     start = time.perf_counter() + 0.05
     if mode == "server":
         from paper_1610_03007_amd import SuffixArrayServer
@@ -176,6 +372,7 @@ def run_server_load(pools, stream, warm: float, mode: str):
                     with lock:
                         del tickets[tk]
                     lat[i] = ms
+                    digest(i, sa)
                     if t_arr[i] >= warm:
                         done_sufs[0] += int(lens[i])
             if finished.is_set() and not pending:
@@ -215,6 +412,7 @@ def run_server_load(pools, stream, warm: float, mode: str):
             lat[i] = (time.perf_counter() - t_sub) * 1e3
             host = torch.empty(sa.numel(), dtype=torch.int32, pin_memory=True)
             host.copy_(sa)
+            digest(i, host.numpy())
             del sa, host
             if t_arr[i] >= warm:
                 done_sufs[0] += int(lens[i])
@@ -223,21 +421,21 @@ def run_server_load(pools, stream, warm: float, mode: str):
         b.close()
     window = max(1e-9, (time.perf_counter() - start) - warm)
     ls = np.array([lat[i] for i in range(len(t_arr)) if t_arr[i] >= warm])
-    return ls, done_sufs[0], window, stats
+    return ls, done_sufs[0], window, stats, mismatches[0]
 
 
-def serve_main(args) -> int:
+def run_serve(seconds: float) -> dict:
     import numpy as np
     t0 = time.perf_counter()
     pools = serve_pools()
-    stream = serve_stream(args.serve_seconds)
-    print(f"[bench] serve: {len(stream[0])} requests over {args.serve_seconds}s, "
-          f"{stream[1].sum() / 1e9:.2f} GB of text; pools in {time.perf_counter() - t0:.1f}s",
-          file=sys.stderr, flush=True)
-    warm = min(2.0, args.serve_seconds / 4)
+    stream = serve_stream(seconds)
+    log(f"serve: {len(stream[0])} requests over {seconds}s, {stream[1].sum() / 1e9:.2f} GB "
+        f"of text; pools in {time.perf_counter() - t0:.1f}s")
+    warm = min(2.0, seconds / 4)
     res = {}
+    digests: dict = {}
     for mode in ("server", "per_text"):
-        ls, sufs, window, stats = run_server_load(pools, stream, warm, mode)
+        ls, sufs, window, stats, bad = run_server_load(pools, stream, warm, mode, digests)
         res[mode] = {
             "requests": int(ls.size),
             "msuffixes_s": round(sufs / window / 1e6, 2),
@@ -248,46 +446,70 @@ def serve_main(args) -> int:
         if stats:
             res[mode]["rounds"] = int(stats["rounds"])
             res[mode]["busy_ms"] = round(float(stats["busy_ms"]), 1)
-        print(f"[bench] {mode}: {res[mode]}", file=sys.stderr, flush=True)
+        if mode == "per_text":
+            res["served_equals_per_text"] = {"compared": len(digests), "mismatches": int(bad)}
+        log(f"serve {mode}: {res[mode]}")
     # Capacity: the first requests of the stream all submitted at once.
-    cap_n = int(np.searchsorted(stream[0], min(4.0, args.serve_seconds)))
+    cap_n = int(np.searchsorted(stream[0], min(3.0, seconds)))
     sat = (np.zeros(cap_n), stream[1][:cap_n], stream[2][:cap_n], stream[3][:cap_n])
     for mode in ("server", "per_text"):
-        ls, sufs, window, _ = run_server_load(pools, sat, 0.0, mode)
+        ls, sufs, window, _, _ = run_server_load(pools, sat, 0.0, mode)
         res[mode]["capacity_msuffixes_s"] = round(sufs / window / 1e6, 2)
         res[mode]["capacity_requests"] = cap_n
-        print(f"[bench] {mode} capacity: {res[mode]['capacity_msuffixes_s']} Msuffixes/s",
-              file=sys.stderr, flush=True)
-    offered = float(stream[1][stream[0] >= warm].sum()) / (args.serve_seconds - warm) / 1e6
-    result = {
-        "metric": "Msuffixes/s on 1 GPU + HBM roofline %; batched vs per-text; p50/p99 latency",
-        "value": res["server"]["msuffixes_s"],
+        log(f"serve {mode} capacity: {res[mode]['capacity_msuffixes_s']} Msuffixes/s")
+    offered = float(stream[1][stream[0] >= warm].sum()) / (seconds - warm) / 1e6
+    return {
+        "workload": "serve",
+        "description": WORKLOADS["serve"],
+        "seconds": seconds,
+        "warmup_s": warm,
+        "offered_msuffixes_s": round(offered, 2),
+        "msuffixes_s": res["server"]["msuffixes_s"],
+        "p50_ms": res["server"]["p50_ms"],
+        "p99_ms": res["server"]["p99_ms"],
+        "server": res["server"],
+        "per_text": res["per_text"],
+        "served_equals_per_text": res["served_equals_per_text"],
+        "p99_per_text_over_server": (round(res["per_text"]["p99_ms"] / res["server"]["p99_ms"], 3)
+                                     if res["server"]["p99_ms"] else None),
+        "capacity_server_over_per_text": round(
+            res["server"]["capacity_msuffixes_s"] / res["per_text"]["capacity_msuffixes_s"], 3),
+    }
+
+
+# ---------------------------------------------------------------------------
+
+def headline(rec: dict, steps: int, warmup: int, workload: str) -> dict:
+    """The driver's JSON line for a build record."""
+    sweep = rec["sweep_roofline"]
+    config = {"workload": workload, "description": rec["description"], "n": rec["n"],
+              "rounds": rec["rounds"], "active_per_round": rec["active_per_round"],
+              "parallelism": "single GPU", "tuning": rec["tuning"],
+              "tuning_source": rec["tuning_source"]}
+    if "texts" in rec:
+        config["texts"] = rec["texts"]
+    return {
+        "metric": METRIC,
+        "value": rec["msuffixes_s"],
         "unit": "Msuffixes/s",
         "n_gpus": 1,
-        "steps": 1,
-        "warmup": 0,
-        "ms_per_step": round(args.serve_seconds * 1e3, 1),
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": rec["ms_per_build"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u64",
         "data": "synthetic",
-        "config": {"workload": "serve", "description": WORKLOADS["serve"],
-                   "seconds": args.serve_seconds, "warmup_s": warm,
-                   "offered_msuffixes_s": round(offered, 2), "parallelism": "single GPU"},
-        "serve": {
-            "p50_ms": res["server"]["p50_ms"], "p99_ms": res["server"]["p99_ms"],
-            "server": res["server"], "per_text": res["per_text"],
-            "p99_per_text_over_server": (round(res["per_text"]["p99_ms"] / res["server"]["p99_ms"], 3)
-                                         if res["server"]["p99_ms"] else None),
-            "capacity_server_over_per_text": round(
-                res["server"]["capacity_msuffixes_s"] / res["per_text"]["capacity_msuffixes_s"], 3),
-        },
-        "roofline": None,
-        "cpu_baseline": None,
+        "config": config,
+        "roofline": {k: sweep[k] for k in ("bound", "achieved", "peak", "unit", "frac",
+                                          "traffic")} | {
+            "kernel": sweep["kernel"], "launches": sweep["launches"],
+            "avg_launch_us": sweep["avg_launch_us"],
+            "algorithmic_bytes_per_launch": sweep["algorithmic_bytes_per_launch"]},
+        "whole_build_roofline": rec["whole_build_roofline"],
+        "cpu_baseline": rec["cpu_baseline"],
     }
-    print(json.dumps(result), flush=True)
-    return 0
 
 
 def tune_main(args) -> int:
@@ -319,13 +541,11 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="markov_256m", choices=sorted(WORKLOADS))
-    ap.add_argument("--cpu-sample", type=int, default=1 << 28,
-                    help="bytes of the text the CPU oracle is timed on (0 = skip; batches "
-                         "are sampled by whole texts)")
+    ap.add_argument("--workload", default="all", choices=["all"] + sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle rows")
     ap.add_argument("--sort-items", type=int, default=0,
                     help="radix-sort items per thread (0 = library default)")
-    ap.add_argument("--serve-seconds", type=float, default=20.0,
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed request stream (serve workload)")
     ap.add_argument("--tune", metavar="OUT_JSON", default="",
                     help="run the autotuner on --tune-workloads and write the cache table "
@@ -338,147 +558,65 @@ def main() -> int:
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(a single text does not shard without an all-to-all exchange step).",
+              f"(the texts of a batch would shard across GPUs without any exchange, but a "
+              f"single text needs an all-to-all exchange per round, which is not built).",
               file=sys.stderr)
         return 2
-
-    if args.workload == "serve":
-        return serve_main(args)
     if args.tune:
         return tune_main(args)
+    cpu = not args.no_cpu
 
-    import numpy as np
-    import torch
+    if args.workload == "serve":
+        rec = run_serve(args.serve_seconds)
+        out = {"metric": METRIC, "value": rec["msuffixes_s"], "unit": "Msuffixes/s",
+               "n_gpus": 1, "steps": 1, "warmup": 0,
+               "ms_per_step": round(args.serve_seconds * 1e3, 1), "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+               "config": {"workload": "serve", "parallelism": "single GPU"},
+               "roofline": None, "cpu_baseline": None, "serve": rec}
+        print(json.dumps(out), flush=True)
+        return 0
 
-    from paper_1610_03007_amd import SuffixArrayBuilder
-
-    t_gen = time.perf_counter()
-    text, offsets = make_text(args.workload)
-    n = int(text.size)
-    print(f"[bench] workload {args.workload} n={n} generated in "
-          f"{time.perf_counter() - t_gen:.1f}s", file=sys.stderr, flush=True)
-
-    dev = torch.device("cuda", 0)
-    d_text = torch.from_numpy(text).to(dev)
-    d_sa = torch.empty(n, dtype=torch.int32, device=dev)
-    b = SuffixArrayBuilder(0)
-    if args.sort_items:
-        b.set_tuning(sort_items=args.sort_items)
-
-    def step():
-        if offsets is None:
-            b.build(d_text, out=d_sa)
-        else:
-            b.build_batch(d_text, offsets, out=d_sa)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"[bench] warmup done: {b.last_info()}", file=sys.stderr, flush=True)
-
-    b.reset_stats()
-    b.set_trace(True)
-    stream = torch.cuda.current_stream(dev)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    b.set_trace(False)
-    gpu_ms = ev0.elapsed_time(ev1)
-    info = b.last_info()
-    stats = b.kernel_stats()
-
-    ms_per_step = gpu_ms / args.steps
-    value = n * args.steps / (gpu_ms / 1e3) / 1e6
-
-    sweep = stats["sort_pass"]
-    achieved = sweep["bytes"] / (sweep["ms"] / 1e3) / 1e9 if sweep["ms"] > 0 else 0.0
-    per_launch = sweep["bytes"] / max(1, sweep["launches"])
-    traffic = measured_traffic(args.workload)
-
-    result = {
-        "metric": "Msuffixes/s on 1 GPU + HBM roofline %; batched vs per-text; p50/p99 latency",
-        "value": round(value, 2),
-        "unit": "Msuffixes/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u64",
-        "data": "synthetic",
-        "config": {
-            "workload": args.workload,
-            "description": WORKLOADS[args.workload],
-            "n": n,
-            "rounds": info["rounds"],
-            "active_per_round": info["active"],
-            "sigma": info["sigma"],
-            "chars_round0": info["chars0"],
-            "parallelism": "single GPU",
-            "tuning": b.tuning(),
-            "tuning_source": b.tuning_source(),
-        },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "onesweep_pass_kernel",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "algorithmic_bytes_per_launch": round(per_launch),
-            "launches": sweep["launches"],
-            "avg_launch_us": round(sweep["ms"] * 1e3 / max(1, sweep["launches"]), 2),
-        },
-        "kernels_ms_per_step": {k: round(v["ms"] / args.steps, 4) for k, v in stats.items()},
-        "wall_s": round(wall, 3),
-    }
-    if offsets is not None:
-        # Per-text baseline on the same GPU: one sa_build per text, in order.
-        torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for t in range(offsets.size - 1):
-            a, z = int(offsets[t]), int(offsets[t + 1])
-            if z > a:
-                b.build(d_text[a:z], out=d_sa[a:z])
-        e1.record(stream)
-        torch.cuda.synchronize()
-        per_text_ms = e0.elapsed_time(e1)
-        per_text = n / (per_text_ms / 1e3) / 1e6
-        result["batch"] = {
-            "texts": int(offsets.size - 1),
-            "batched_msuffixes_s": round(value, 2),
-            "per_text_msuffixes_s": round(per_text, 2),
-            "per_text_ms": round(per_text_ms, 2),
-            "batched_vs_per_text": round(value / per_text, 3),
-        }
-    if args.cpu_sample > 0:
-        result["cpu_baseline"] = cpu_baseline(text, min(args.cpu_sample, n), offsets)
-    else:
-        result["cpu_baseline"] = None
+    names = BUILD_ORDER if args.workload == "all" else (args.workload,)
+    records = {}
+    for name in names:
+        # The headline workload takes the driver's step counts; the others are
+        # bounded so that the whole run stays within a few minutes.
+        steps, warmup = args.steps, args.warmup
+        if name != names[0]:
+            if name == "repetitive_1g":
+                steps, warmup = min(steps, 3), min(warmup, 1)
+            elif name == "dna_1m":
+                steps = max(steps, 20)
+        records[name] = run_build(name, steps, warmup, cpu, args.sort_items)
+    head = names[0]
+    out = headline(records[head], args.steps, args.warmup, head)
+    if args.workload == "all":
+        records["serve"] = run_serve(args.serve_seconds)
+    out["configs"] = {k: v for k, v in records.items() if k != head}
+    out["batch"] = ({"texts": records[head]["texts"],
+                     "batched_msuffixes_s": records[head]["msuffixes_s"],
+                     "per_text_msuffixes_s": records[head]["per_text"]["msuffixes_s"],
+                     "batched_vs_per_text": records[head]["batched_vs_per_text"]}
+                    if "per_text" in records[head] else None)
+    if "serve" in records:
+        s = records["serve"]
+        out["serve"] = {"p50_ms": s["p50_ms"], "p99_ms": s["p99_ms"],
+                        "msuffixes_s": s["msuffixes_s"],
+                        "capacity_server_over_per_text": s["capacity_server_over_per_text"]}
+    out["kernels"] = records[head]["kernels"]
 
     if args.calibrate_copy > 0:
+        import torch
         nbytes = args.calibrate_copy << 20
+        dev = torch.device("cuda", 0)
         src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
-        result["calibrate_copy_bytes"] = nbytes
-
-    b.close()
-    print(json.dumps(result), flush=True)
+        out["calibrate_copy_bytes"] = nbytes
+    print(json.dumps(out), flush=True)
     return 0
 
 

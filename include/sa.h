@@ -232,8 +232,12 @@ sa_status sa_tune_save(const sa_ctx* ctx, const char* path);
 sa_status sa_tune_lookup(const char* path, const char* arch, const char* mode, uint64_t n,
                          uint32_t code_bits, sa_tuning* out, int* found);
 
-/* Device workspace a context needs for a text of n bytes. */
-size_t sa_workspace_bytes(uint64_t n);
+/* Device workspace (bytes) a context needs to build `num_texts` texts of
+ * `total_n` bytes in all: sa_build when num_texts <= 1 (about 37 bytes per text
+ * byte), sa_build_batch otherwise (about 45 bytes per byte of all texts, plus
+ * a table row of about 600 bytes per text). Host-only; for admission and
+ * planning. The caller's text and SA buffers are not included. */
+size_t sa_workspace_bytes(uint64_t total_n, uint32_t num_texts);
 
 /* Per-kernel timing. With tracing on, every kernel launch of a build is
  * bracketed by HIP events on the build's stream; the totals accumulate until

@@ -33,9 +33,10 @@ def _stream_handle(device: torch.device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def workspace_bytes(n: int) -> int:
-    """Device workspace (bytes) a build of an n-byte text needs."""
-    return int(_native.lib().sa_workspace_bytes(n))
+def workspace_bytes(total_n: int, num_texts: int = 1) -> int:
+    """Device workspace (bytes) a build of ``num_texts`` texts of ``total_n``
+    bytes in all needs (one text: ``sa_build``; more: ``sa_build_batch``)."""
+    return int(_native.lib().sa_workspace_bytes(total_n, num_texts))
 
 
 class SuffixArrayBuilder:

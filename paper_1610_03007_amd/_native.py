@@ -123,7 +123,7 @@ def _declare(lib: ctypes.CDLL) -> None:
         "sa_last_build_info": ([vp, ctypes.POINTER(BuildInfo)], i32),
         "sa_build_rounds": ([vp, vp, u64, u32, vp, vp, vp], i32),
         "sa_radix_sort_pairs": ([vp, vp, vp, u64, u32, vp], i32),
-        "sa_workspace_bytes": ([u64], ctypes.c_size_t),
+        "sa_workspace_bytes": ([u64, u32], ctypes.c_size_t),
         "sa_ctx_set_trace": ([vp, i32], i32),
         "sa_ctx_set_isa_mode": ([vp, i32], i32),
         "sa_ctx_set_tuning": ([vp, ctypes.POINTER(Tuning)], i32),

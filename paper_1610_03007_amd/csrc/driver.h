@@ -187,6 +187,15 @@ void settle_trace(sa_ctx* c, sa_status st);
 sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u32* d_sa,
                            hipStream_t s);
 
+// Per-slot tables of the multi-text engine (multi.hip), in one allocation.
+struct TableLayout {
+  size_t o_base, o_len, o_h, o_r0, o_nt, o_no, o_nc;  // uploaded each round
+  size_t up_bytes;                                     // extent of the uploaded part
+  size_t o_code, o_pres, o_wc, o_surv;
+  size_t bytes;
+};
+TableLayout table_layout(u32 nslots);
+
 // Tuning (tune.hip).
 bool tuning_valid(const sa_tuning& t);
 sa_tuning default_tuning();

@@ -25,6 +25,42 @@ using namespace drv;
 
 namespace {
 
+}  // namespace
+
+namespace drv {
+
+// Byte offsets of the per-slot device tables in the engine's one allocation.
+// The tables written by the host each round come first, contiguous, so that
+// one copy from a pinned mirror uploads them all.
+TableLayout table_layout(u32 nslots) {
+  TableLayout L{};
+  const size_t S = nslots;
+  size_t bytes = 0;
+  auto take = [&](size_t b) {
+    const size_t at = bytes;
+    bytes += (b + 255) / 256 * 256;
+    return at;
+  };
+  L.o_base = take(S * 8);
+  L.o_len = take(S * 8);
+  L.o_h = take(S * 8);
+  L.o_r0 = take(S);
+  L.o_nt = take(S * 4);
+  L.o_no = take((S + 1) * 8);
+  L.o_nc = take((S + 1) * 8);
+  L.up_bytes = bytes;
+  L.o_code = take(S * 256 * 2);
+  L.o_pres = take(S * 32);
+  L.o_wc = take(S * 4);
+  L.o_surv = take(S * 4);
+  L.bytes = bytes;
+  return L;
+}
+
+}  // namespace drv
+
+namespace {
+
 // Device tables and host mirrors of the text slots.
 struct Engine {
   sa_ctx* c = nullptr;
@@ -72,22 +108,15 @@ struct Engine {
     slots = nslots;
     idbits = id_bits;
     B = rank_bits;
+    const TableLayout L = table_layout(nslots);
     const size_t S = nslots;
-    size_t bytes = 0;
-    auto take = [&](size_t b) {
-      const size_t at = bytes;
-      bytes += (b + 255) / 256 * 256;
-      return at;
-    };
-    // The tables written by the host each round come first, contiguous, so
-    // that one copy from a pinned mirror uploads them all.
-    const size_t o_base = take(S * 8), o_len = take(S * 8), o_h = take(S * 8), o_r0 = take(S),
-                 o_nt = take(S * 4), o_no = take((S + 1) * 8), o_nc = take((S + 1) * 8);
-    up_bytes = bytes;
+    const size_t bytes = L.bytes;
+    const size_t o_base = L.o_base, o_len = L.o_len, o_h = L.o_h, o_r0 = L.o_r0, o_nt = L.o_nt,
+                 o_no = L.o_no, o_nc = L.o_nc, o_code = L.o_code, o_pres = L.o_pres,
+                 o_wc = L.o_wc, o_surv = L.o_surv;
+    up_bytes = L.up_bytes;
     o_up_base = o_base, o_up_len = o_len, o_up_h = o_h, o_up_r0 = o_r0, o_up_nt = o_nt,
     o_up_no = o_no, o_up_nc = o_nc;
-    const size_t o_code = take(S * 256 * 2), o_pres = take(S * 32), o_wc = take(S * 4),
-                 o_surv = take(S * 4);
     if (hipMalloc(&dev, bytes) != hipSuccess) {
       dev = nullptr;
       (void)hipGetLastError();
@@ -129,6 +158,13 @@ struct Engine {
   sa_status round_step(const u8* text_arena, u32* sa_arena, const std::vector<u32>& joining,
                        std::vector<u32>& finished, int slot_info, hipStream_t s) {
     finished.clear();
+    // A lazy ISA holds only the survivors' names and the round-0 sorted keys
+    // of the texts already running; a text joining now would overwrite those
+    // keys. Refused before anything is enqueued.
+    if (lazy) {
+      for (u32 t : joining)
+        if (len[t] != 0) return SA_EINVAL;
+    }
     const Bufs full = full_bufs(c);
     const int idshift = 64 - idbits;
     // Work list of the joining texts.
@@ -182,7 +218,6 @@ struct Engine {
       Tracer tr(c, s, SA_KERNEL_PACK_TEXT, double(A0) * 13.0);
       launch_multi_pack0(text_arena, tab, nl, idshift, c->keysA, c->valsA, s);
     }
-    if (lazy && m) return SA_EINVAL;  // lazy rounds admit no new texts
     const Bufs bufs = lazy ? later : full;
     if (active) {
       Tracer tr(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
@@ -625,7 +660,10 @@ sa_status lane_create(std::unique_ptr<Lane>& out, int device, u64 capacity_bytes
   }
   L->free_ranges[0] = L->arena_cap;
   L->slot_ticket.assign(slots, 0);
-  for (u32 k = slots; k-- > 0;) L->free_slots.push_back(k);
+  // Slots are handed out from the highest down (free_slots is used as a
+  // stack), so the top bits of the slot field, and with them the highest key
+  // bits, take part from the first request on.
+  for (u32 k = 0; k < slots; ++k) L->free_slots.push_back(k);
   try {
     L->worker = std::thread([L] { L->run(); });
   } catch (...) {

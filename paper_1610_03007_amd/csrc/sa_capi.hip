@@ -517,10 +517,18 @@ sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, u
   return SA_OK;
 }
 
-size_t sa_workspace_bytes(uint64_t n) {
-  u64 cap = std::max<u64>(n, 1 << 16);
-  return size_t(cap) * (2 * 8 + 5 * 4) + ceil_div(cap, 32) * 4 + sort_status_words(cap) * 8 +
-         kSmallBytes;
+size_t sa_workspace_bytes(uint64_t total_n, uint32_t num_texts) {
+  const u64 cap = std::max<u64>(total_n, 1 << 16);
+  // keys A/B (u64), values A/B, ISA, active positions and ranks (u32), the
+  // live-position bitmap, the sort look-back statuses and the control block.
+  u64 bytes = cap * (2 * 8 + 5 * 4) + ceil_div(cap, 32) * 4 + sort_status_words(cap) * 8 +
+              kSmallBytes;
+  if (num_texts > 1) {
+    // A batch also keeps its survivors as (text << 32 | position) and one
+    // table row per text.
+    bytes += cap * 8 + table_layout(num_texts).bytes;
+  }
+  return size_t(bytes);
 }
 
 sa_status sa_ctx_set_trace(sa_ctx* ctx, int on) {

@@ -39,8 +39,13 @@ def test_host_only_entry_points():
     assert lib.sa_strerror(0).decode() == "ok"
     assert "2^32" in lib.sa_strerror(3).decode()
     n = 1 << 20
-    ws = lib.sa_workspace_bytes(n)
+    ws = lib.sa_workspace_bytes(n, 1)
     assert 36 * n <= ws <= 40 * n
+    assert lib.sa_workspace_bytes(n, 0) == ws
+    # A batch adds 8 bytes per position for its survivors and a table row per text.
+    wb = lib.sa_workspace_bytes(n, 4096)
+    assert ws + 8 * n + 4096 * 597 <= wb <= ws + 8 * n + 4096 * 700
+    assert 44 * n <= lib.sa_workspace_bytes(n, 2) <= 46 * n
 
 
 def test_null_context_is_rejected():

@@ -196,3 +196,27 @@ def test_batch_full_size(builder):
     for t in rng.choice(small, 16, replace=False):
         a, b = int(off[t]), int(off[t + 1])
         assert np.array_equal(sa[a:b], oracle.sa(texts[a:b])), t
+
+
+@pytest.mark.parametrize("mode", ["auto", "eager"])
+def test_batch_full_64bit_keys(builder, mode):
+    """4096 texts whose longest has 2^25..2^26 bytes: 12 slot bits plus two
+    26-bit ranks fill all 64 key bits, and the long text takes the last slot
+    (every slot bit set)."""
+    rng = np.random.default_rng(64)
+    texts = []
+    for i in range(4095):
+        n = int(rng.integers(0, 300))
+        texts.append(W.dna(n, seed=i) if i % 2 else
+                     rng.integers(0, 256, n).astype(np.uint8))
+    big = W.markov3((1 << 25) + 12345, chain_seed=64)
+    big[-4096:] = big[:4096]  # a repeat: the long text needs more rounds
+    texts.append(big)
+    builder.set_isa_mode(mode)
+    try:
+        sa, off = run_batch(builder, texts)
+    finally:
+        builder.set_isa_mode("auto")
+    assert len(texts) == 4096 and 12 + 2 * 26 == 64
+    assert np.array_equal(sa[int(off[-2]):int(off[-1])], oracle.sa(big, parallel=True))
+    check_each(texts[:-1], sa, off)

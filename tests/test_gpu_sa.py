@@ -379,3 +379,21 @@ def test_tuning_rejects_bad_values(builder):
     with pytest.raises(SAError):
         builder.set_tuning(lazy_ratio=1)
     assert builder.tuning()["sort_items"] in (8, 12, 16, 20, 24)
+
+
+def test_above_2_31(builder):
+    """A text of 2^31 + 4097 bytes: 32-bit ranks, so round keys use all 64
+    bits and SA values pass 2^31. The last MiB repeats the first, which keeps
+    about 2^21 suffixes active for about 17 rounds. Checked by the oracle's
+    linear-time check and sampled direct suffix comparisons."""
+    n = (1 << 31) + 4097
+    t = W.dna_long(n, seed=31)
+    t[-(1 << 20):] = t[:1 << 20]
+    sa = gpu_sa(builder, t)
+    info = builder.last_info()
+    print(f"n={n} rounds={info['rounds']} active={info['active'][:4]}...", flush=True)
+    assert info["n"] == n and info["rounds"] >= 17
+    assert int(sa.max()) == n - 1
+    status, where = oracle.check_sa(t, sa)
+    assert status == 0, (status, where, info)
+    sampled_direct_check(t, sa, samples=500)

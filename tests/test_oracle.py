@@ -233,3 +233,25 @@ def test_mutant_is_caught(name, tmp_path):
     subprocess.run(["g++", "-O1", "-std=c++17", "-shared", "-fPIC", "-o", str(so), str(mpath)],
                    check=True)
     assert not _run_pins(so, timeout=15), f"mutant {name} survived the pins"
+
+
+def test_parallel_build_pins_pass():
+    """The GNU-parallel build of the oracle (the CPU baseline, and the checker
+    of some large GPU tests) passes the same pins as the sequential build."""
+    if not os.path.exists(oracle.LIB_PAR):
+        oracle.build(parallel=True)
+    assert _run_pins(oracle.LIB_PAR)
+
+
+def test_parallel_build_at_scale():
+    """Above the parallel sort's thresholds the parallel build equals the
+    pinned sequential build, and the closed forms hold."""
+    n = 1 << 22
+    t = np.frombuffer(b"ACGT", np.uint8)[np.random.default_rng(21).integers(0, 4, n)]
+    assert np.array_equal(oracle.sa(t, parallel=True), oracle.sa(t))
+    m = 1 << 20
+    assert np.array_equal(oracle.sa(np.full(m, 97, np.uint8), parallel=True),
+                          np.arange(m - 1, -1, -1, dtype=np.uint32))
+    ab = np.frombuffer(b"ab" * (m // 2), np.uint8)
+    want = np.concatenate([np.arange(m - 2, -1, -2), np.arange(m - 1, 0, -2)]).astype(np.uint32)
+    assert np.array_equal(oracle.sa(ab, parallel=True), want)

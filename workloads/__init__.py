@@ -19,6 +19,7 @@ SplitMix64, Marsaglia-Tsang gamma variates, 16-bit cumulative thresholds).
 
 from __future__ import annotations
 
+import concurrent.futures as cf
 import ctypes
 import os
 import subprocess
@@ -162,6 +163,33 @@ def batch(num_texts: int = 4096, lo: int = 4096, hi: int = 8388608, seed: int = 
         mk, mk_off = markov3_many(lengths[odd], 2000 + odd, matrix_seed)
         for j, t in enumerate(odd):
             out[offsets[t]:offsets[t + 1]] = mk[mk_off[j]:mk_off[j + 1]]
-    for t in range(0, num_texts, 2):
+    def fill_dna(t: int) -> None:
         out[offsets[t]:offsets[t + 1]] = dna(int(lengths[t]), 1000 + t)
+
+    # numpy draws without holding the interpreter lock: texts in parallel.
+    with cf.ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(fill_dna, range(0, num_texts, 2)))
     return out, offsets
+
+
+def _workers() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+DNA_CHUNK = 1 << 24
+
+
+def dna_long(n: int, seed: int = 0) -> np.ndarray:
+    """n bytes iid uniform over ACGT, drawn in 16 MiB chunks: chunk k from
+    ``default_rng(seed * 2^20 + k)`` (chunks generated in parallel)."""
+    out = np.empty(n, dtype=np.uint8)
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+
+    def fill(k: int) -> None:
+        a = k * DNA_CHUNK
+        b = min(n, a + DNA_CHUNK)
+        out[a:b] = acgt[np.random.default_rng((seed << 20) + k).integers(0, 4, b - a)]
+
+    with cf.ThreadPoolExecutor(max_workers=_workers()) as ex:
+        list(ex.map(fill, range((n + DNA_CHUNK - 1) // DNA_CHUNK)))
+    return out

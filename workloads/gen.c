@@ -105,25 +105,65 @@ void gen_markov_table(uint64_t seed, int k, int order, double alpha, uint16_t* c
  * symbol index #{ j < k - 1 : cdf16[row][j] <= v }, mapped to its byte by
  * `symbols`. Job j first runs `burn_in` steps whose output is dropped, then
  * writes lengths[j] bytes at out + offsets[j]; it draws from seed seeds[j].
- * Jobs run in parallel under OpenMP. */
+ * Every job is its own chain, so the bytes do not depend on scheduling: jobs
+ * run in parallel under OpenMP, and each thread steps kLanes jobs in turn so
+ * that the table-row reads of different chains overlap. */
+enum { kLanes = 8 };
+
+typedef struct {
+  rng_t r;
+  uint8_t* o;
+  uint64_t p, end;
+  const uint16_t* row;  /* thresholds of the current context (s0, s1, s2) */
+  uint32_t last2, last; /* s1 * k + s2 and s2 */
+} chain_t;
+
 void gen_markov3(const uint16_t* cdf16, int k, const uint8_t* symbols, uint8_t* out,
                  const uint64_t* offsets, const uint64_t* lengths, const uint64_t* seeds,
                  int64_t njobs, uint64_t burn_in) {
+  const int64_t groups = (njobs + kLanes - 1) / kLanes;
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int64_t j = 0; j < njobs; ++j) {
-    rng_t r;
-    rng_seed(&r, seeds[j]);
-    uint8_t* o = out + offsets[j];
-    uint64_t len = lengths[j];
-    uint64_t kk = (uint64_t)k, rows = kk * kk * kk;
-    uint64_t ctx = 0;
-    for (uint64_t p = 0; p < burn_in + len; ++p) {
-      const uint16_t* row = cdf16 + ctx * (kk - 1);
-      uint32_t v = (uint32_t)(rng_next(&r) >> 48);
-      int idx = 0;
-      for (int q = 0; q < k - 1; ++q) idx += (row[q] <= v);
-      if (p >= burn_in) o[p - burn_in] = symbols[idx];
-      ctx = (ctx * kk + (uint64_t)idx) % rows;
+  for (int64_t g = 0; g < groups; ++g) {
+    chain_t ch[kLanes];
+    int live = 0;
+    for (int64_t j = g * kLanes; j < njobs && j < (g + 1) * kLanes; ++j) {
+      chain_t* c = &ch[live++];
+      rng_seed(&c->r, seeds[j]);
+      c->o = out + offsets[j];
+      c->p = 0;
+      c->end = burn_in + lengths[j];
+      c->row = cdf16; /* context (0, 0, 0) */
+      c->last2 = 0;
+      c->last = 0;
+    }
+    const uint64_t kk = (uint64_t)k;
+    const int m = k - 1; /* thresholds per row */
+    while (live > 0) {
+      for (int q = 0; q < live;) {
+        chain_t* c = &ch[q];
+        if (c->p >= c->end) {
+          ch[q] = ch[--live];
+          continue;
+        }
+        uint32_t v = (uint32_t)(rng_next(&c->r) >> 48);
+        const uint16_t* b = c->row;
+        /* The thresholds of a row never decrease, so the number of them <= v
+         * is found by halving (branch-free upper bound). */
+        int len = m;
+        while (len > 1) {
+          const int half = len >> 1;
+          b = (b[half] <= v) ? b + half : b;
+          len -= half;
+        }
+        const uint32_t idx = (uint32_t)(b - c->row) + (m > 0 && *b <= v);
+        if (c->p >= burn_in) c->o[c->p - burn_in] = symbols[idx];
+        /* Next context (s1, s2, idx): row (s1 * k + s2) * k + idx. */
+        c->row = cdf16 + ((uint64_t)c->last2 * kk + idx) * (uint64_t)m;
+        c->last2 = c->last * (uint32_t)k + idx;
+        c->last = idx;
+        c->p += 1;
+        ++q;
+      }
     }
   }
 }
