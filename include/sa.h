@@ -38,7 +38,8 @@ typedef enum {
   SA_OK = 0,
   SA_EINVAL = 1,   /* null pointer, bad size or flag, sigma outside [1, 256] */
   SA_ENOMEM = 2,   /* a workspace allocation failed */
-  SA_ETOOBIG = 3,  /* n >= 2^32 (ranks and SA entries are 32-bit) */
+  SA_ETOOBIG = 3,  /* n >= 2^32 (ranks and SA entries are 32-bit), or above an entry
+                      point's stated maximum */
   SA_EDEVICE = 4,  /* a HIP call failed or a kernel reported an error */
   SA_EBUSY = 5     /* the resource is in use */
 } sa_status;
@@ -66,6 +67,22 @@ sa_status sa_ctx_destroy(sa_ctx* ctx);
  * Needs about 37 bytes of device workspace per text byte. */
 sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
                    uint32_t* d_sa, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): sa_build
+ * with no allocation of any kind. The workspace is a fixed device array built
+ * into the library, SA_NOALLOC_MAX_N suffixes in size (about 40 MB; every GPU
+ * the library runs on holds its own copy until the process ends), instead of
+ * the context's workspace; the context supplies its tuning and its pinned
+ * readback buffers, allocated when it was created. Arguments and result as
+ * sa_build. n above SA_NOALLOC_MAX_N gives SA_ETOOBIG before anything is
+ * enqueued. Every call on one GPU shares that GPU's array, whichever context
+ * makes it: calls that overlap on one GPU (from several host threads or
+ * several streams) race and must be serialised by the caller. Kernel tracing
+ * is off for the call. */
+#define SA_NOALLOC_MAX_N (1u << 20)
+sa_status sa_build_noalloc(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
+                           uint32_t* d_sa, void* stream);
 
 /* Suffix arrays of many texts in one batched build: every doubling round runs
  * one sort and one re-rank launch for all texts together (the text id sits in

@@ -16,6 +16,7 @@ from . import build_ext
 
 SA_OK, SA_EINVAL, SA_ENOMEM, SA_ETOOBIG, SA_EDEVICE, SA_EBUSY = range(6)
 SA_MAX_ROUNDS = 64
+SA_NOALLOC_MAX_N = 1 << 20
 KERNEL_KINDS = {
     "sort_pass": 0,
     "histogram": 1,
@@ -28,7 +29,8 @@ KERNEL_KINDS = {
 ISA_MODES = {"auto": 0, "eager": 1, "lazy": 2}
 
 EXPORTED = [
-    "sa_ctx_create", "sa_ctx_destroy", "sa_build", "sa_build_batch", "sa_last_build_info",
+    "sa_ctx_create", "sa_ctx_destroy", "sa_build", "sa_build_noalloc", "sa_build_batch",
+    "sa_last_build_info",
     "sa_build_rounds",
     "sa_radix_sort_pairs", "sa_workspace_bytes", "sa_ctx_set_trace", "sa_ctx_reset_stats",
     "sa_ctx_set_isa_mode", "sa_ctx_set_tuning", "sa_ctx_get_tuning", "sa_ctx_tuning_source",
@@ -119,6 +121,7 @@ def _declare(lib: ctypes.CDLL) -> None:
         "sa_ctx_create": ([ctypes.POINTER(vp), i32, ctypes.c_char_p], i32),
         "sa_ctx_destroy": ([vp], i32),
         "sa_build": ([vp, vp, u64, u32, vp, vp], i32),
+        "sa_build_noalloc": ([vp, vp, u64, u32, vp, vp], i32),
         "sa_build_batch": ([vp, vp, vp, u32, vp, vp], i32),
         "sa_last_build_info": ([vp, ctypes.POINTER(BuildInfo)], i32),
         "sa_build_rounds": ([vp, vp, u64, u32, vp, vp, vp], i32),

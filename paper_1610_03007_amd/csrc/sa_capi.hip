@@ -8,6 +8,7 @@
 // suffixes remain.
 
 #include <atomic>
+#include <mutex>
 #include "driver.h"
 
 namespace drv {
@@ -374,6 +375,135 @@ sa_status build_impl(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_sa
   return st;
 }
 
+// Carves the control block (histograms, tickets, counters, plan, alphabet
+// tables, lazy-ISA sample) out of kSmallBytes at p.
+void bind_small(sa_ctx* c, char* p) {
+  c->hist_in = reinterpret_cast<u32*>(p);
+  c->hist_run = c->hist_in + kChunkHistWords;
+  c->tickets = c->hist_run + kChunkHistWords;
+  c->counters = reinterpret_cast<u64*>(p + kSmallHist);
+  c->plan = reinterpret_cast<SortPlan*>(p + kSmallHist + kSmallCounters);
+  c->present = reinterpret_cast<u32*>(p + kSmallHist + kSmallCounters + kSmallPlan);
+  c->code = reinterpret_cast<u16*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent);
+  c->sample = reinterpret_cast<u64*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent +
+                                     kSmallCode);
+}
+
+// ---------------------------------------------------------------------------
+// Workspace of sa_build_noalloc: a file-scope device array holding everything a
+// build of up to SA_NOALLOC_MAX_N suffixes needs, so that the call allocates
+// nothing. Each GPU holds its own copy from the library's load until the
+// process ends. In host code `scratch` only names the symbol; its device
+// address comes from hipGetSymbolAddress, once per device.
+constexpr u64 kNoAllocCap = SA_NOALLOC_MAX_N;
+
+struct ScratchLayout {
+  size_t keysA, keysB, valsA, valsB, isa, act_idx, act_rank, live, status, small, bytes;
+};
+
+constexpr size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+constexpr ScratchLayout scratch_layout() {
+  ScratchLayout L{};
+  size_t at = 0;
+  L.keysA = at, at += align256(kNoAllocCap * 8);
+  L.keysB = at, at += align256(kNoAllocCap * 8);
+  L.valsA = at, at += align256(kNoAllocCap * 4);
+  L.valsB = at, at += align256(kNoAllocCap * 4);
+  L.isa = at, at += align256(kNoAllocCap * 4);
+  L.act_idx = at, at += align256(kNoAllocCap * 4);
+  L.act_rank = at, at += align256(kNoAllocCap * 4);
+  L.live = at, at += align256((kNoAllocCap + 31) / 32 * 4);
+  L.status = at, at += align256((kNoAllocCap + kSortTileMin - 1) / kSortTileMin * kRadix * 8);
+  L.small = at, at += align256(kSmallBytes);
+  L.bytes = at;
+  return L;
+}
+constexpr ScratchLayout kScratch = scratch_layout();
+
+static __device__ __align__(256) unsigned char scratch[kScratch.bytes];
+
+// Per device: the array's device address and the look-back generation of its
+// status words (the array is shared by every context on the device).
+struct NoAllocDevice {
+  unsigned char* ptr = nullptr;
+  u32 gen = 0;
+};
+std::mutex g_noalloc_mu;
+std::vector<NoAllocDevice> g_noalloc;
+
+// Called by sa_ctx_create with `device` current: looks the array's address up
+// on this device the first time and clears its status words once.
+sa_status noalloc_setup(int device) {
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (device < 0) return SA_EINVAL;
+  if (size_t(device) >= g_noalloc.size()) g_noalloc.resize(size_t(device) + 1);
+  NoAllocDevice& d = g_noalloc[size_t(device)];
+  if (d.ptr) return SA_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return SA_EDEVICE;
+  }
+  unsigned char* base = static_cast<unsigned char*>(p);
+  if (hipMemset(base + kScratch.status, 0, sort_status_words(kNoAllocCap) * sizeof(u64)) !=
+          hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    return SA_EDEVICE;
+  }
+  d.ptr = base;
+  d.gen = 0;
+  return SA_OK;
+}
+
+// Everything a build reads from the context's workspace, swapped out while the
+// scratch array stands in for it.
+struct WorkspaceView {
+  u64 cap;
+  u64 *keysA, *keysB;
+  u32 *valsA, *valsB, *isa, *live, *act_idx, *act_rank;
+  u64* status;
+  u32 *hist_in, *hist_run, *tickets;
+  u64* counters;
+  SortPlan* plan;
+  u32* present;
+  u16* code;
+  u64* sample;
+  u32 gen;
+  bool trace;
+};
+
+WorkspaceView save_view(const sa_ctx* c) {
+  return WorkspaceView{c->cap,      c->keysA,   c->keysB,    c->valsA,    c->valsB,
+                       c->isa,      c->live,    c->act_idx,  c->act_rank, c->status,
+                       c->hist_in,  c->hist_run, c->tickets, c->counters, c->plan,
+                       c->present,  c->code,    c->sample,   c->gen,      c->trace};
+}
+
+void restore_view(sa_ctx* c, const WorkspaceView& v) {
+  c->cap = v.cap;
+  c->keysA = v.keysA;
+  c->keysB = v.keysB;
+  c->valsA = v.valsA;
+  c->valsB = v.valsB;
+  c->isa = v.isa;
+  c->live = v.live;
+  c->act_idx = v.act_idx;
+  c->act_rank = v.act_rank;
+  c->status = v.status;
+  c->hist_in = v.hist_in;
+  c->hist_run = v.hist_run;
+  c->tickets = v.tickets;
+  c->counters = v.counters;
+  c->plan = v.plan;
+  c->present = v.present;
+  c->code = v.code;
+  c->sample = v.sample;
+  c->gen = v.gen;
+  c->trace = v.trace;
+}
+
 }  // namespace drv
 
 using namespace drv;
@@ -422,16 +552,11 @@ sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
     delete c;
     return SA_ENOMEM;
   }
-  char* p = static_cast<char*>(c->small);
-  c->hist_in = reinterpret_cast<u32*>(p);
-  c->hist_run = c->hist_in + kChunkHistWords;
-  c->tickets = c->hist_run + kChunkHistWords;
-  c->counters = reinterpret_cast<u64*>(p + kSmallHist);
-  c->plan = reinterpret_cast<SortPlan*>(p + kSmallHist + kSmallCounters);
-  c->present = reinterpret_cast<u32*>(p + kSmallHist + kSmallCounters + kSmallPlan);
-  c->code = reinterpret_cast<u16*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent);
-  c->sample = reinterpret_cast<u64*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent +
-                                     kSmallCode);
+  bind_small(c, static_cast<char*>(c->small));
+  if (noalloc_setup(device) != SA_OK) {
+    sa_ctx_destroy(c);
+    return SA_EDEVICE;
+  }
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_counters), kCtrCount * sizeof(u64)) !=
           hipSuccess ||
       hipHostMalloc(reinterpret_cast<void**>(&c->h_plans),
@@ -465,6 +590,51 @@ sa_status sa_build(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigm
   const sa_status st =
       build_impl(ctx, d_text, n, 0, d_sa, nullptr, static_cast<hipStream_t>(stream));
   ctx->sigma_hint = 0;
+  return st;
+}
+
+sa_status sa_build_noalloc(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
+                           uint32_t* d_sa, void* stream) {
+  if (!ctx) return SA_EINVAL;
+  if (sigma == 0 || sigma > 256) return SA_EINVAL;
+  if (n > SA_NOALLOC_MAX_N) return SA_ETOOBIG;
+  unsigned char* base = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    if (size_t(ctx->device) < g_noalloc.size()) base = g_noalloc[size_t(ctx->device)].ptr;
+  }
+  if (!base) return SA_EDEVICE;
+  // The build runs on the scratch array in place of the context's workspace:
+  // a capacity of SA_NOALLOC_MAX_N means no growth, and tracing (which
+  // creates events) is off for the call.
+  const WorkspaceView saved = save_view(ctx);
+  WorkspaceView v = saved;
+  v.cap = kNoAllocCap;
+  v.keysA = reinterpret_cast<u64*>(base + kScratch.keysA);
+  v.keysB = reinterpret_cast<u64*>(base + kScratch.keysB);
+  v.valsA = reinterpret_cast<u32*>(base + kScratch.valsA);
+  v.valsB = reinterpret_cast<u32*>(base + kScratch.valsB);
+  v.isa = reinterpret_cast<u32*>(base + kScratch.isa);
+  v.act_idx = reinterpret_cast<u32*>(base + kScratch.act_idx);
+  v.act_rank = reinterpret_cast<u32*>(base + kScratch.act_rank);
+  v.live = reinterpret_cast<u32*>(base + kScratch.live);
+  v.status = reinterpret_cast<u64*>(base + kScratch.status);
+  v.trace = false;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    v.gen = g_noalloc[size_t(ctx->device)].gen;
+  }
+  restore_view(ctx, v);
+  bind_small(ctx, reinterpret_cast<char*>(base + kScratch.small));
+  ctx->sigma_hint = sigma;
+  const sa_status st =
+      build_impl(ctx, d_text, n, 0, d_sa, nullptr, static_cast<hipStream_t>(stream));
+  ctx->sigma_hint = 0;
+  {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    g_noalloc[size_t(ctx->device)].gen = ctx->gen;
+  }
+  restore_view(ctx, saved);
   return st;
 }
 
@@ -586,7 +756,7 @@ const char* sa_strerror(sa_status s) {
     case SA_OK: return "ok";
     case SA_EINVAL: return "invalid argument";
     case SA_ENOMEM: return "out of device memory";
-    case SA_ETOOBIG: return "input too large (n must be < 2^32)";
+    case SA_ETOOBIG: return "input too large (n must be < 2^32 and within the entry point's maximum)";
     case SA_EDEVICE: return "device error";
     case SA_EBUSY: return "busy";
   }
