@@ -15,6 +15,9 @@ compiles it with g++ on demand and wraps it with ctypes over numpy arrays:
 * :func:`brute_sa` -- the definition: sort all suffixes lexicographically.
 * :func:`check_sa` -- linear-time suffix-array check (permutation plus an
   adjacent-pair test against the inverse of the array under test).
+* :func:`lcp`, :func:`bwt`, :func:`sa_interval` -- index structures from a
+  suffix array, each by its definition: adjacent-suffix common prefixes, the
+  Burrows-Wheeler column of text$, and the suffix-array range of a pattern.
 """
 
 from __future__ import annotations
@@ -58,8 +61,12 @@ def configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_prefix_ranks.argtypes = [u8p, u64, u64, u32p]
     lib.oracle_brute_sa.argtypes = [u8p, u64, u32p]
     lib.oracle_check_sa.argtypes = [u8p, u64, u32p, u64p]
+    lib.oracle_lcp.argtypes = [u8p, u64, u32p, u32p]
+    lib.oracle_bwt.argtypes = [u8p, u64, u32p, u8p, u64p]
+    lib.oracle_sa_interval.argtypes = [u8p, u64, u32p, u8p, u64, u64p, u64p]
     for f in ("oracle_sa", "oracle_pd_names", "oracle_prefix_ranks",
-              "oracle_brute_sa", "oracle_check_sa", "oracle_num_threads"):
+              "oracle_brute_sa", "oracle_check_sa", "oracle_num_threads",
+              "oracle_lcp", "oracle_bwt", "oracle_sa_interval"):
         getattr(lib, f).restype = ctypes.c_int
     return lib
 
@@ -145,6 +152,55 @@ def check_sa(text, sa_arr) -> tuple[int, int]:
     rc = _lib().oracle_check_sa(_p(t, ctypes.c_uint8), t.size, _p(s, ctypes.c_uint32),
                                 ctypes.byref(where))
     return int(rc), int(where.value)
+
+
+def _sa32(text, sa_arr) -> np.ndarray:
+    s = np.ascontiguousarray(np.asarray(sa_arr)).view(np.uint32) \
+        if np.asarray(sa_arr).dtype in (np.int32, np.uint32) \
+        else np.ascontiguousarray(sa_arr, dtype=np.uint32)
+    if s.size != _text(text).size:
+        raise ValueError("suffix array and text differ in length")
+    return s
+
+
+def lcp(text, sa_arr) -> np.ndarray:
+    """LCP array of a text and its suffix array, by direct comparison of
+    adjacent suffixes (uint32; lcp[0] = 0)."""
+    t = _text(text)
+    s = _sa32(t, sa_arr)
+    out = np.empty(t.size, dtype=np.uint32)
+    if _lib().oracle_lcp(_p(t, ctypes.c_uint8), t.size, _p(s, ctypes.c_uint32),
+                         _p(out, ctypes.c_uint32)):
+        raise ValueError("suffix array entry out of range")
+    return out
+
+
+def bwt(text, sa_arr) -> tuple[np.ndarray, int]:
+    """Burrows-Wheeler transform of text$ from its suffix array: the n bytes of
+    the transform without its $, and the row of the $."""
+    t = _text(text)
+    s = _sa32(t, sa_arr)
+    out = np.empty(t.size, dtype=np.uint8)
+    d = ctypes.c_uint64(0)
+    if _lib().oracle_bwt(_p(t, ctypes.c_uint8), t.size, _p(s, ctypes.c_uint32),
+                         _p(out, ctypes.c_uint8), ctypes.byref(d)):
+        raise ValueError("suffix array entry out of range")
+    return out, int(d.value)
+
+
+def sa_interval(text, sa_arr, pattern) -> tuple[int, int]:
+    """[lo, hi): the suffix-array positions whose suffixes start with pattern."""
+    t = _text(text)
+    s = _sa32(t, sa_arr)
+    pt = _text(pattern)
+    if pt.size == 0:
+        pt = np.zeros(1, np.uint8)[:0]
+    lo, hi = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    buf = np.ascontiguousarray(pt) if pt.size else np.zeros(1, np.uint8)
+    _lib().oracle_sa_interval(_p(t, ctypes.c_uint8), t.size, _p(s, ctypes.c_uint32),
+                              _p(buf, ctypes.c_uint8), pt.size, ctypes.byref(lo),
+                              ctypes.byref(hi))
+    return int(lo.value), int(hi.value)
 
 
 def num_threads(parallel: bool = True) -> int:

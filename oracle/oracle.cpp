@@ -204,6 +204,89 @@ int oracle_check_sa(const uint8_t* T, uint64_t n, const uint32_t* SA, uint64_t* 
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Index structures derived from a suffix array. The paper's conclusion names
+// the LCP array and further text indexes built from the suffix array as the
+// next step; each function below is the plain definition of its output,
+// computed from the text and a suffix array given by the caller.
+
+// LCP array: lcp[0] = 0 and, for j >= 1, lcp[j] = the number of leading bytes
+// suffixes SA[j - 1] and SA[j] have in common, counted byte by byte.
+int oracle_lcp(const uint8_t* T, uint64_t n, const uint32_t* SA, uint32_t* lcp) {
+  if (n == 0) return 0;
+  lcp[0] = 0;
+  for (uint64_t j = 1; j < n; ++j) {
+    const uint64_t a = SA[j - 1], b = SA[j];
+    if (a >= n || b >= n) return 1;
+    uint64_t l = 0;
+    while (a + l < n && b + l < n && T[a + l] == T[b + l]) ++l;
+    lcp[j] = static_cast<uint32_t>(l);
+  }
+  return 0;
+}
+
+// Burrows-Wheeler transform of T$ ($ below every byte): the suffixes of T$ in
+// sorted order are $ alone, then T[SA[0], n)$, T[SA[1], n)$, ...; the
+// transform lists the character before each of them, read cyclically (T[n - 1]
+// before $ alone, $ before the whole text). out[0, n) receives that column with
+// its one $ left out, and *dollar the row where the $ stands.
+int oracle_bwt(const uint8_t* T, uint64_t n, const uint32_t* SA, uint8_t* out, uint64_t* dollar) {
+  *dollar = 0;
+  if (n == 0) return 0;
+  uint64_t k = 0;
+  out[k++] = T[n - 1];
+  for (uint64_t j = 0; j < n; ++j) {
+    if (SA[j] >= n) return 1;
+    if (SA[j] == 0) {
+      *dollar = j + 1;
+      continue;
+    }
+    out[k++] = T[SA[j] - 1];
+  }
+  return 0;
+}
+
+namespace {
+
+// Compares the first m bytes of suffix s with P: negative if the suffix's
+// prefix is smaller (a suffix that ends first is smaller), 0 if the suffix
+// starts with P, positive if greater.
+int cmp_prefix(const uint8_t* T, uint64_t n, uint64_t s, const uint8_t* P, uint64_t m) {
+  for (uint64_t l = 0; l < m; ++l) {
+    if (s + l >= n) return -1;
+    if (T[s + l] != P[l]) return T[s + l] < P[l] ? -1 : 1;
+  }
+  return 0;
+}
+
+}  // namespace
+
+// The positions [*lo, *hi) of the suffix array whose suffixes start with
+// P[0, m) (contiguous, as the suffixes are sorted): two binary searches with
+// byte comparisons. An empty pattern gives [0, n).
+int oracle_sa_interval(const uint8_t* T, uint64_t n, const uint32_t* SA, const uint8_t* P,
+                       uint64_t m, uint64_t* lo, uint64_t* hi) {
+  uint64_t a = 0, b = n;
+  while (a < b) {  // first j whose suffix is not below P
+    const uint64_t mid = a + (b - a) / 2;
+    if (cmp_prefix(T, n, SA[mid], P, m) < 0)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  *lo = a;
+  b = n;
+  while (a < b) {  // first j whose suffix is above P
+    const uint64_t mid = a + (b - a) / 2;
+    if (cmp_prefix(T, n, SA[mid], P, m) <= 0)
+      a = mid + 1;
+    else
+      b = mid;
+  }
+  *hi = a;
+  return 0;
+}
+
 // Number of threads the parallel sort may use (1 in the sequential build).
 int oracle_num_threads(void) {
 #ifdef _OPENMP

@@ -33,6 +33,36 @@ def py_prefix_ranks(t: bytes, h: int):
     return [first[p] + 1 for p in pads]
 
 
+def py_lcp(t: bytes):
+    sa = py_brute_sa(t)
+    out = [0] * len(t)
+    for j in range(1, len(t)):
+        a, b = t[sa[j - 1]:], t[sa[j]:]
+        l = 0
+        while l < min(len(a), len(b)) and a[l] == b[l]:
+            l += 1
+        out[j] = l
+    return out
+
+
+def py_bwt(t: bytes):
+    """Last column of the sorted rotations of t$ ($ = -1, below every byte)."""
+    seq = list(t) + [-1]
+    m = len(seq)
+    rows = sorted(range(m), key=lambda i: seq[i:] + seq[:i])
+    col = [seq[(i - 1) % m] for i in rows]
+    d = col.index(-1)
+    return bytes(c for c in col if c >= 0), d
+
+
+def py_interval(t: bytes, p: bytes):
+    sa = py_brute_sa(t)
+    m = len(p)
+    lo = sum(1 for s in sa if t[s:s + m] < p)
+    occ = sum(1 for i in range(len(t)) if t[i:i + m] == p)
+    return lo, lo + occ
+
+
 def load(name):
     with open(os.path.join(GOLDEN, name)) as f:
         return json.load(f)
@@ -74,6 +104,24 @@ def pins_pass() -> bool:
         bad[j], bad[j + 1] = bad[j + 1], bad[j]
         if oracle.check_sa(t, bad)[0] != 2:
             return False
+        tb = t.tobytes()
+        sa = np.array(want, dtype=np.uint32)
+        if oracle.lcp(t, sa).tolist() != py_lcp(tb):
+            return False
+        bw, d = oracle.bwt(t, sa)
+        if (bw.tobytes(), d) != py_bwt(tb):
+            return False
+        for _ in range(3):
+            a = int(rng.integers(0, n))
+            pat = tb[a:a + int(rng.integers(0, 4))] if rng.random() < 0.7 else \
+                bytes(rng.integers(0, 3, int(rng.integers(1, 4))).astype(np.uint8))
+            if oracle.sa_interval(t, sa, pat) != py_interval(tb, pat):
+                return False
+    if oracle.lcp(b"banana", [5, 3, 1, 0, 4, 2]).tolist() != [0, 1, 3, 0, 0, 2]:
+        return False
+    bw, d = oracle.bwt(b"banana", [5, 3, 1, 0, 4, 2])
+    if (bw.tobytes(), d) != (b"annbaa", 4):
+        return False
     return True
 
 

@@ -198,6 +198,13 @@ MUTANTS = {
     "no_doubling": ("h *= 2;", "h += 1;"),
     "prefix_longer_first": ("return li < lj ? -1 : 1;", "return li < lj ? 1 : -1;"),
     "checker_loose": ("bool ok = (T[a] < T[b]) ||", "bool ok = (T[a] <= T[b]) ||"),
+    "lcp_overcount": ("lcp[j] = static_cast<uint32_t>(l);",
+                      "lcp[j] = static_cast<uint32_t>(l + (l > 0));"),
+    "bwt_unshifted": ("out[k++] = T[SA[j] - 1];", "out[k++] = T[SA[j]];"),
+    "bwt_dollar_row": ("*dollar = j + 1;", "*dollar = j;"),
+    "interval_open_end": ("if (cmp_prefix(T, n, SA[mid], P, m) <= 0)",
+                          "if (cmp_prefix(T, n, SA[mid], P, m) < 0)"),
+    "interval_short_suffix_larger": ("if (s + l >= n) return -1;", "if (s + l >= n) return 1;"),
     "brute_signed": ("return std::lexicographical_compare(T + a, T + n, T + b, T + n);",
                      "return std::lexicographical_compare((const signed char*)T + a, "
                      "(const signed char*)T + n, (const signed char*)T + b, "
@@ -255,3 +262,61 @@ def test_parallel_build_at_scale():
     ab = np.frombuffer(b"ab" * (m // 2), np.uint8)
     want = np.concatenate([np.arange(m - 2, -1, -2), np.arange(m - 1, 0, -2)]).astype(np.uint32)
     assert np.array_equal(oracle.sa(ab, parallel=True), want)
+
+
+# --------------------------------------------------------------------------
+# Index structures from a suffix array: LCP array, BWT of text$, pattern
+# intervals. Expected values come from Python brute force (rotation sorting for
+# the BWT, direct comparison, occurrence counting) and closed forms.
+
+from oracle_pins import py_bwt, py_interval, py_lcp  # noqa: E402
+
+
+def test_index_textbook_banana():
+    sa = oracle.sa(b"banana")
+    assert oracle.lcp(b"banana", sa).tolist() == [0, 1, 3, 0, 0, 2]
+    bw, d = oracle.bwt(b"banana", sa)
+    assert bw.tobytes() == b"annbaa" and d == 4  # banana$ -> annb$aa
+    assert oracle.sa_interval(b"banana", sa, b"ana") == (1, 3)
+    assert oracle.sa_interval(b"banana", sa, b"") == (0, 6)
+    assert oracle.sa_interval(b"banana", sa, b"nax") == (6, 6)
+    assert oracle.sa_interval(b"banana", sa, b"b") == (3, 4)
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 4, 256])
+def test_index_brute_force(sigma):
+    rng = np.random.default_rng(300 + sigma)
+    for _ in range(40):
+        n = int(rng.integers(1, 90))
+        t = rng.integers(0, sigma, n).astype(np.uint8)
+        tb = t.tobytes()
+        sa = oracle.sa(t)
+        assert oracle.lcp(t, sa).tolist() == py_lcp(tb)
+        bw, d = oracle.bwt(t, sa)
+        assert (bw.tobytes(), d) == py_bwt(tb)
+        for _ in range(5):
+            a = int(rng.integers(0, n))
+            pat = tb[a:a + int(rng.integers(0, 5))]
+            assert oracle.sa_interval(t, sa, pat) == py_interval(tb, pat)
+            pat = rng.integers(0, sigma, int(rng.integers(1, 4))).astype(np.uint8).tobytes()
+            assert oracle.sa_interval(t, sa, pat) == py_interval(tb, pat)
+
+
+def test_index_closed_forms():
+    n = 2000
+    a = np.full(n, 97, np.uint8)
+    sa = oracle.sa(a)
+    assert oracle.lcp(a, sa).tolist() == list(range(n))          # a^j vs a^(j+1)
+    bw, d = oracle.bwt(a, sa)
+    assert bw.tobytes() == b"a" * n and d == n                     # $ ends the column
+    assert oracle.sa_interval(a, sa, b"a" * 10) == (9, n)        # suffixes a^10 .. a^n
+    m = 500
+    ab = np.frombuffer(b"ab" * m, np.uint8)
+    sa = oracle.sa(ab)
+    # (ab)^m: SA lists the a-suffixes (ab)^k, k = 1..m, then the b-suffixes
+    # b(ab)^k, k = 0..m-1; each neighbour shares all of the shorter suffix:
+    # (ab)^k with (ab)^(k+1) 2k bytes, b(ab)^(k-1) with b(ab)^k 2k - 1 bytes.
+    want = [0] + [2 * k for k in range(1, m)] + [0] + [2 * k - 1 for k in range(1, m)]
+    assert oracle.lcp(ab, sa).tolist() == want
+    bw, d = oracle.bwt(ab, sa)
+    assert bw.tobytes() == b"b" + b"b" * (m - 1) + b"a" * m and d == m
