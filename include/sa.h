@@ -150,7 +150,10 @@ typedef struct {
   uint32_t chars0;        /* characters per round-0 key: the first prefix length */
   uint64_t prefix_len;    /* prefix length the ranks resolve after the last round */
   uint32_t lazy_isa;      /* 1 if the ISA was resolved lazily after round 0 */
-  uint32_t reserved;
+  uint32_t graph_rounds;  /* enqueued later rounds replayed from a captured HIP graph
+                             (sa_build / sa_build_rounds) */
+  uint64_t dense_rounds;  /* bit k: round k was dense (most suffixes still active, so it
+                             sorted all n with the names read in position order) */
   uint64_t active[SA_MAX_ROUNDS];       /* suffixes sorted in round k */
   uint32_t passes_run[SA_MAX_ROUNDS];   /* radix passes executed in round k */
   uint32_t key_bits[SA_MAX_ROUNDS];     /* key bits sorted in round k */
@@ -206,7 +209,15 @@ typedef struct {
                             0 (default) = eight ballots, whose cost does not depend on the
                             digits; 1 = an LDS table (fewer instructions, but lanes of
                             equal digits collide in its atomics) */
-  uint32_t reserved[2];  /* must be zero */
+  uint32_t radix_bits;   /* radix-sort digit width in bits: 0 (default) = 8 */
+  uint32_t rounds_ahead; /* doubling rounds after round 0 enqueued before the host reads the
+                            survivor count back: 0 (default) = 1, then 2, 4, ... up to 16
+                            per readback; k in [1, 64] = k each time. A round that finds no
+                            survivor does nothing. */
+  uint32_t round_graphs; /* 0 (default): a later round whose launch arguments repeat is
+                            captured once as a HIP graph and replayed; 1: every kernel is
+                            launched directly. Tracing always launches directly. */
+  uint32_t reserved;     /* must be zero */
 } sa_tuning;
 /* Sets an explicit tuning, used by every later build of the context. t = NULL
  * goes back to automatic choice: the cache entry for each input, else the
@@ -248,6 +259,57 @@ sa_status sa_tune_save(const sa_ctx* ctx, const char* path);
  * defaults when no entry matches. A missing file is an empty cache. */
 sa_status sa_tune_lookup(const char* path, const char* arch, const char* mode, uint64_t n,
                          uint32_t code_bits, sa_tuning* out, int* found);
+
+/* ---------------------------------------------------------------------------
+ * Index structures from a text and its suffix array, on the device. The
+ * paper's conclusion names these as the next step after suffix sorting: the
+ * LCP array and further text indexes built from the suffix array. d_sa must be
+ * the suffix array of d_text (as sa_build writes it); an array that is not a
+ * permutation of [0, n) gives SA_EDEVICE or undefined outputs, never a fault.
+ * Each call returns when its result is complete on `stream`. */
+
+/* LCP array: d_lcp[0] = 0 and, for j >= 1, d_lcp[j] = the number of leading
+ * bytes suffixes d_sa[j - 1] and d_sa[j] have in common. d_lcp: device u32[n].
+ * Uses 4n bytes of the context's workspace (which grows to a build's size).
+ * Method: Kasai et al.'s bound lcp(i + 1) >= lcp(i) - 1 along the text, in
+ * the permuted (Phi) form; every step runs in the library's kernels. */
+sa_status sa_lcp(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, const uint32_t* d_sa,
+                 uint32_t* d_lcp, void* stream);
+
+/* Burrows-Wheeler transform of text$, $ below every byte: the rows are the
+ * suffixes of text$ in sorted order ($ alone first, then d_sa[0], d_sa[1],
+ * ...), and the transform lists the character before each row (cyclically:
+ * text[n - 1] before $ alone, $ before the whole text). d_bwt: device u8[n]
+ * receives it with its single $ left out; *dollar (host) the row of the $,
+ * in [1, n] (0 when n = 0). */
+sa_status sa_bwt(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, const uint32_t* d_sa,
+                 uint8_t* d_bwt, uint64_t* dollar, void* stream);
+
+/* FM index of a text: its transform and occurrence counts sampled every 256
+ * rows for each byte present, in device memory the index owns (about
+ * n + 4 n sigma / 256 bytes). Built from the text and its suffix array; the
+ * caller's buffers are not kept. */
+typedef struct sa_fm sa_fm;
+sa_status sa_fm_create(sa_fm** out, sa_ctx* ctx, const uint8_t* d_text, uint64_t n,
+                       const uint32_t* d_sa, void* stream);
+/* Pattern queries by backward search, one pattern per wavefront.
+ *   d_patterns:  device u8, the patterns concatenated (may be NULL if all are
+ *                empty);
+ *   d_offsets:   device u64[num_patterns + 1]: pattern q is
+ *                d_patterns[d_offsets[q], d_offsets[q + 1]);
+ *   d_ranges:    device u64[2 num_patterns]: for pattern q, [lo, hi) = the
+ *                positions of the suffix array whose suffixes start with it
+ *                (hi - lo occurrences; when there are none, lo = hi = the number
+ *                of suffixes smaller than the pattern). The empty pattern gives
+ *                [0, n).
+ * Enqueued on `stream` without waiting. */
+sa_status sa_fm_count(sa_fm* fm, const uint8_t* d_patterns, const uint64_t* d_offsets,
+                      uint32_t num_patterns, uint64_t* d_ranges, void* stream);
+/* Text length, row of $, bytes present and device bytes of an index (any
+ * output pointer may be NULL). */
+sa_status sa_fm_info(const sa_fm* fm, uint64_t* n, uint64_t* dollar, uint32_t* sigma,
+                     uint64_t* device_bytes);
+sa_status sa_fm_destroy(sa_fm* fm);
 
 /* Device workspace (bytes) a context needs to build `num_texts` texts of
  * `total_n` bytes in all: sa_build when num_texts <= 1 (about 37 bytes per text

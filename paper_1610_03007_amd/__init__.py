@@ -21,7 +21,7 @@ import torch
 from . import _native
 from ._native import SAError, check
 
-__all__ = ["SuffixArrayBuilder", "SuffixArrayServer", "SAError", "workspace_bytes"]
+__all__ = ["SuffixArrayBuilder", "SuffixArrayServer", "FMIndex", "SAError", "workspace_bytes"]
 
 
 # Tuning cache shipped with the package: entries found by the autotuner on
@@ -149,6 +149,45 @@ class SuffixArrayBuilder:
                                                 key_bits, _stream_handle(self.device)),
                   "sa_radix_sort_pairs")
         return keys, vals
+
+    def _sa_of(self, sa: torch.Tensor, n: int) -> torch.Tensor:
+        if sa.dtype not in (torch.int32, torch.uint32) or sa.numel() != n \
+                or not sa.is_contiguous() or sa.device != self.device:
+            raise ValueError(f"sa must be a contiguous 32-bit tensor of {n} elements on "
+                             f"{self.device}")
+        return sa
+
+    def lcp(self, text: torch.Tensor, sa: torch.Tensor,
+            out: torch.Tensor | None = None) -> torch.Tensor:
+        """LCP array (int32 bits of u32) of ``text`` and its suffix array ``sa``:
+        out[0] = 0, out[j] = common prefix length of suffixes sa[j-1] and sa[j]."""
+        t = self._text(text)
+        n = t.numel()
+        s = self._sa_of(sa, n)
+        lcp = self._out(out, n, "out")
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_lcp(self._ctx, ctypes.c_void_p(t.data_ptr()), n,
+                                   ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(lcp.data_ptr()),
+                                   _stream_handle(self.device)), "sa_lcp")
+        return lcp
+
+    def bwt(self, text: torch.Tensor, sa: torch.Tensor):
+        """Burrows-Wheeler transform of text$: (uint8 tensor of n bytes without
+        the $, row of the $)."""
+        t = self._text(text)
+        n = t.numel()
+        s = self._sa_of(sa, n)
+        out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        d = ctypes.c_uint64(0)
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_bwt(self._ctx, ctypes.c_void_p(t.data_ptr()), n,
+                                   ctypes.c_void_p(s.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                   ctypes.byref(d), _stream_handle(self.device)), "sa_bwt")
+        return out, int(d.value)
+
+    def fm_index(self, text: torch.Tensor, sa: torch.Tensor) -> "FMIndex":
+        """FM index of ``text`` (device memory owned by the returned object)."""
+        return FMIndex(self, text, sa)
 
     def last_info(self) -> dict:
         info = _native.BuildInfo()
@@ -304,3 +343,65 @@ class SuffixArrayServer:
         st = _native.ServerStats()
         check(self._lib.sa_server_stats(self._srv, ctypes.byref(st)), "sa_server_stats")
         return {k: getattr(st, k) for k, _ in _native.ServerStats._fields_}
+
+
+class FMIndex:
+    """FM index on the GPU (sa_fm_* ABI): pattern queries by backward search.
+
+    ``count(patterns)`` takes a list of bytes-like patterns (or a uint8 CUDA
+    tensor of the patterns concatenated plus host offsets) and returns an int64
+    tensor of shape (num, 2): for each pattern the suffix-array positions
+    [lo, hi) whose suffixes start with it."""
+
+    def __init__(self, builder: SuffixArrayBuilder, text: torch.Tensor, sa: torch.Tensor):
+        t = builder._text(text)
+        n = t.numel()
+        s = builder._sa_of(sa, n)
+        self.device = builder.device
+        self._lib = builder._lib
+        self._fm = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_fm_create(ctypes.byref(self._fm), builder._ctx,
+                                         ctypes.c_void_p(t.data_ptr()), n,
+                                         ctypes.c_void_p(s.data_ptr()),
+                                         _stream_handle(self.device)), "sa_fm_create")
+
+    def info(self) -> dict:
+        n, d, b = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        sg = ctypes.c_uint32()
+        check(self._lib.sa_fm_info(self._fm, ctypes.byref(n), ctypes.byref(d), ctypes.byref(sg),
+                                   ctypes.byref(b)), "sa_fm_info")
+        return {"n": n.value, "dollar": d.value, "sigma": sg.value, "device_bytes": b.value}
+
+    def count(self, patterns, offsets=None) -> torch.Tensor:
+        import numpy as np
+        if offsets is None:
+            pats = [bytes(p) for p in patterns]
+            off = np.zeros(len(pats) + 1, dtype=np.uint64)
+            np.cumsum([len(p) for p in pats], out=off[1:])
+            cat = b"".join(pats)
+            data = torch.frombuffer(bytearray(cat), dtype=torch.uint8).to(self.device) \
+                if cat else torch.zeros(1, dtype=torch.uint8, device=self.device)
+        else:
+            data = patterns
+            off = np.ascontiguousarray(np.asarray(offsets, dtype=np.uint64))
+        num = off.size - 1
+        d_off = torch.from_numpy(off.view(np.int64)).to(self.device)
+        ranges = torch.empty((num, 2), dtype=torch.int64, device=self.device)
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_fm_count(self._fm, ctypes.c_void_p(data.data_ptr()),
+                                        ctypes.c_void_p(d_off.data_ptr()), num,
+                                        ctypes.c_void_p(ranges.data_ptr()),
+                                        _stream_handle(self.device)), "sa_fm_count")
+        return ranges
+
+    def close(self) -> None:
+        if self._fm:
+            self._lib.sa_fm_destroy(self._fm)
+            self._fm = ctypes.c_void_p()
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass

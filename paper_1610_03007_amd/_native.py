@@ -38,6 +38,7 @@ EXPORTED = [
     "sa_server_create", "sa_server_destroy", "sa_server_submit", "sa_server_poll",
     "sa_server_stats",
     "sa_ctx_get_kernel_stats", "sa_strerror",
+    "sa_lcp", "sa_bwt", "sa_fm_create", "sa_fm_count", "sa_fm_info", "sa_fm_destroy",
 ]
 
 
@@ -50,7 +51,8 @@ class BuildInfo(ctypes.Structure):
         ("chars0", ctypes.c_uint32),
         ("prefix_len", ctypes.c_uint64),
         ("lazy_isa", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("graph_rounds", ctypes.c_uint32),
+        ("dense_rounds", ctypes.c_uint64),
         ("active", ctypes.c_uint64 * SA_MAX_ROUNDS),
         ("passes_run", ctypes.c_uint32 * SA_MAX_ROUNDS),
         ("key_bits", ctypes.c_uint32 * SA_MAX_ROUNDS),
@@ -63,6 +65,8 @@ class BuildInfo(ctypes.Structure):
             "code_bits": int(self.code_bits), "chars0": int(self.chars0),
             "prefix_len": int(self.prefix_len),
             "lazy_isa": bool(self.lazy_isa),
+            "graph_rounds": int(self.graph_rounds),
+            "dense_rounds": [k for k in range(r) if (int(self.dense_rounds) >> k) & 1],
             "active": [int(x) for x in self.active[:r]],
             "passes_run": [int(x) for x in self.passes_run[:r]],
             "key_bits": [int(x) for x in self.key_bits[:r]],
@@ -73,11 +77,12 @@ class Tuning(ctypes.Structure):
     _fields_ = [("sort_items", ctypes.c_uint32), ("lazy_ratio", ctypes.c_uint32),
                 ("round0_full", ctypes.c_uint32), ("sort_wgs_per_cu", ctypes.c_uint32),
                 ("sort_block", ctypes.c_uint32), ("sort_match", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32 * 2)]
+                ("radix_bits", ctypes.c_uint32), ("rounds_ahead", ctypes.c_uint32),
+                ("round_graphs", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
 TUNING_KNOBS = ("sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu", "sort_block",
-                "sort_match")
+                "sort_match", "radix_bits", "rounds_ahead", "round_graphs")
 
 
 def tuning_dict(t: "Tuning") -> dict:
@@ -146,6 +151,13 @@ def _declare(lib: ctypes.CDLL) -> None:
         "sa_server_poll": ([vp, u64, vp, ctypes.POINTER(i32), ctypes.POINTER(ctypes.c_double)],
                            i32),
         "sa_server_stats": ([vp, ctypes.POINTER(ServerStats)], i32),
+        "sa_lcp": ([vp, vp, u64, vp, vp, vp], i32),
+        "sa_bwt": ([vp, vp, u64, vp, vp, ctypes.POINTER(u64), vp], i32),
+        "sa_fm_create": ([ctypes.POINTER(vp), vp, vp, u64, vp, vp], i32),
+        "sa_fm_count": ([vp, vp, vp, u32, vp, vp], i32),
+        "sa_fm_info": ([vp, ctypes.POINTER(u64), ctypes.POINTER(u64), ctypes.POINTER(u32),
+                        ctypes.POINTER(u64)], i32),
+        "sa_fm_destroy": ([vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

@@ -8,7 +8,8 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
-SOURCES = [os.path.join(CSRC, f) for f in ("sa_kernels.hip", "sa_capi.hip", "multi.hip", "tune.hip")]
+SOURCES = [os.path.join(CSRC, f)
+           for f in ("sa_kernels.hip", "sa_capi.hip", "multi.hip", "tune.hip", "index.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("common.h", "kernels.h", "driver.h")] + [
     os.path.join(ROOT, "include", "sa.h")]
 LIB = os.path.join(PKG, "libsa_mi355x.so")

@@ -50,9 +50,17 @@ __device__ inline void store_status(u64* p, u64 v) {
 
 // ---------------------------------------------------------------------------
 // Radix sort plan, computed on the device from the up-front digit histograms.
+// Digits are kRadixBits wide by default; a tuning may choose any width in
+// [kRadixBitsMin, kRadixBitsMax]. Per-digit arrays are sized for the widest
+// digit, per-pass arrays for the narrowest.
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kMaxPasses = 64 / kRadixBits;
+constexpr int kRadixBitsMin = 6;
+constexpr int kRadixBitsMax = 9;
+constexpr int kRadixMax = 1 << kRadixBitsMax;
+constexpr int kMaxPasses = (64 + kRadixBitsMin - 1) / kRadixBitsMin;
+// Passes of rb-bit digits that cover `bits` key bits.
+__host__ __device__ constexpr int passes_for(int bits, int rb) { return (bits + rb - 1) / rb; }
 
 struct SortPlan {
   u32 skip[kMaxPasses];             // pass p is skipped (its digit is constant)
@@ -71,6 +79,57 @@ struct SortPlan {
 // sweep its global digit offsets.
 constexpr int kChunks = 32;
 static_assert(kChunks % 8 == 0, "chunk counts are read eight at a time");
+
+// Sweep geometry of a sort of `count` pairs in tiles of `tile`: the tiles are
+// grouped into chunks of 2^ct_log2 tiles, so that at most kChunks chunks cover
+// the input (nchunks of them non-empty). Host and device derive it alike.
+struct SortGeom {
+  u64 count;
+  u32 tile;
+  u32 ct_log2;
+  u32 nchunks;
+};
+__host__ __device__ inline SortGeom sort_geom(u64 count, u32 tile) {
+  SortGeom g;
+  g.count = count;
+  g.tile = tile;
+  u64 tiles = (count + tile - 1) / tile;
+  if (tiles < 1) tiles = 1;
+  const u64 per = (tiles + kChunks - 1) / kChunks;
+  u32 lg = 0;
+  while ((u64(1) << lg) < per) ++lg;
+  g.ct_log2 = lg;
+  g.nchunks = u32((tiles + (u64(1) << lg) - 1) >> lg);
+  return g;
+}
+
+// Control words of the current sort, in device memory. sort_begin_kernel sets
+// them (from a count the host passes, or from a device counter such as the
+// survivor count of the last re-rank) and every later kernel of the sort and
+// of the re-rank reads them instead of taking the count as an argument, so
+// that a captured round replays with unchanged launch arguments. A count of 0
+// makes every kernel of the round return at once.
+struct SortCtl {
+  u64 count;     // pairs in the sort
+  u32 gen_base;  // look-back generation of pass 0 (pass p uses gen_base + p)
+  u32 gen_next;  // first generation not used yet
+  u32 dense;     // 1: a dense round (every suffix, keys built in position order)
+  u32 reserved;
+};
+
+// Doubling rounds of one text run ahead of the host: the index and offset of
+// the round in progress, and a log the host reads back.
+constexpr int kMaxRounds = 64;
+struct RoundCtl {
+  u32 round;                // later rounds started (round 0 not counted)
+  u32 reserved;
+  u64 h;                    // doubling offset of the round in progress
+  u64 dense;                // bit k: round k was dense
+  u64 active[kMaxRounds];   // suffixes sorted in round k (k >= 1)
+};
+// Plan log: the flags of the sort of round k (kPlanLogWords words per round):
+// skip[kMaxPasses] | src[kMaxPasses] | iota[kMaxPasses] | final buffer.
+constexpr int kPlanLogWords = 3 * kMaxPasses + 1;
 
 // Workgroup and tile shapes.
 constexpr int kSortBlock = 256;          // the smaller sweep workgroup (one thread per digit)
@@ -92,6 +151,7 @@ enum CounterSlot : int {
   kCtrSigma = kMaxPasses + 4,        // distinct bytes in the text
   kCtrCodeBits = kMaxPasses + 5,     // w: bits per character code
   kCtrChars = kMaxPasses + 6,        // c: characters packed in a round-0 key
+  kCtrIndexAux = kMaxPasses + 7,     // index builds: the row of $ in the transform
   kCtrCount = kMaxPasses + 8,
 };
 

@@ -33,6 +33,21 @@ struct TuneTable {
   std::vector<TuneEntry> entries;
 };
 
+// A captured later round (rounds run ahead of the host), keyed by everything
+// its launch arguments depend on. A key is captured the second time it is
+// seen, so that one-off builds never pay for capture.
+struct GraphKey {
+  u64 n, bound;
+  const void* ptr[12];
+  u32 knobs[10];
+};
+struct GraphEntry {
+  GraphKey key;
+  hipGraphExec_t exec = nullptr;
+  u32 seen = 0;
+  u64 last_use = 0;
+};
+
 struct TraceRec {
   hipEvent_t start, stop;
   int kind;
@@ -57,26 +72,42 @@ struct sa_ctx {
   u64 act_ti_cap = 0;
   u64* toff = nullptr;    // batch text offsets on the device
   u64 toff_cap = 0;
-  u64* status = nullptr;  // sort look-back: [tiles][kRadix]
+  u64* status = nullptr;  // sort look-back: [tiles][radix]
   // Small control block: hist_in | hist_run | tickets | counters | plan | present | code.
   void* small = nullptr;
-  u32* hist_in = nullptr;   // [kMaxPasses][kChunks][kRadix] input-order chunk histograms
-  u32* hist_run = nullptr;  // [kMaxPasses][kChunks][kRadix] histograms fed forward by sweeps
+  u32* hist_in = nullptr;   // [passes][kChunks][radix] input-order chunk histograms
+  u32* hist_run = nullptr;  // [passes][kChunks][radix] histograms fed forward by sweeps
   u32* tickets = nullptr;   // [kMaxPasses][kChunks] tile tickets
   u64* counters = nullptr;
+  RoundCtl* rc = nullptr;   // rounds run from the device (follows the counters)
+  u32* plan_log = nullptr;  // [kMaxRounds + 1][kPlanLogWords] (follows rc)
+  SortCtl* ctl = nullptr;
   SortPlan* plan = nullptr;
   u32* present = nullptr;
   u16* code = nullptr;
   u64* sample = nullptr;  // lazy ISA: sampled round-0 sorted keys
-  // Pinned readback area: counters copy + per-sort plan flags.
+  // Pinned mirror of counters | rc | plan_log, refreshed by every readback.
+  void* h_mirror = nullptr;
   u64* h_counters = nullptr;
-  u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][3 * kMaxPasses]
-  u32 gen = 0;
+  RoundCtl* h_rc = nullptr;
+  u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][kPlanLogWords]
+  u32 gen = 1;             // upper bound of ctl->gen_next (look-back generations)
+  // Later rounds run ahead of the host: at most this many per readback
+  // (0 = adaptive, doubling from 1), replayed from captured graphs unless
+  // graphs are off (tuning) or tracing / the no-allocation call is active.
+  u32 rounds_ahead = 0;
+  bool graphs = true;
+  bool graphs_blocked = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<GraphEntry> graph_cache;
+  u64 graph_clock = 0;
+  u64 graph_launches = 0;  // replays of captured rounds (diagnostics)
   int isa_mode = SA_ISA_AUTO;
   int sort_items = kSortItemsDefault;  // radix-sort items per thread (tile size)
   int sort_block = kSortBlockDefault;  // radix-sort workgroup size (256 or 512)
   int sort_wgs_per_cu = 0;             // persistent sweep workgroups per CU (0 = by tile size)
   int sort_match = 0;                  // sweep digit matching: 0 ballots, 1 LDS table
+  int radix_bits = kRadixBits;         // radix-sort digit width
   int num_cus = 256;
   u64 lazy_ratio = kLazyRatioDefault;
   int round0_trim = 1;  // round-0 keys fill whole radix digits
@@ -100,17 +131,37 @@ struct sa_ctx {
 
 namespace drv {
 
-constexpr size_t kChunkHistWords = size_t(kMaxPasses) * kChunks * kRadix;
+// Chunk histograms of one sort: passes x chunks x digits, for the digit width
+// that needs the most words.
+constexpr size_t hist_words_for(int rb) {
+  return size_t(passes_for(64, rb)) * kChunks * (size_t(1) << rb);
+}
+constexpr size_t max_hist_words(int rb) {
+  return rb > kRadixBitsMax ? 0
+                            : (hist_words_for(rb) > max_hist_words(rb + 1) ? hist_words_for(rb)
+                                                                             : max_hist_words(rb + 1));
+}
+constexpr size_t kChunkHistWords = max_hist_words(kRadixBitsMin);
 constexpr size_t kTicketWords = size_t(kMaxPasses) * kChunks;
+static_assert(SA_MAX_ROUNDS == kMaxRounds, "round logs");
 constexpr size_t kSmallHist = (2 * kChunkHistWords + kTicketWords) * sizeof(u32);
+constexpr size_t kClearWords = 2 * kChunkHistWords + kTicketWords;  // cleared by sort_begin
+// The readback span: counters | RoundCtl | plan log, contiguous.
 constexpr size_t kSmallCounters = size_t(kCtrCount) * sizeof(u64);
+constexpr size_t kSmallRoundCtl = sizeof(RoundCtl);
+constexpr int kPlanFlagWords = kPlanLogWords;  // skip, src, iota, final_buf
+constexpr size_t kSmallPlanLog = (size_t(kMaxRounds + 1) * kPlanFlagWords * sizeof(u32) + 255) /
+                                 256 * 256;
+constexpr size_t kMirrorBytes = kSmallCounters + kSmallRoundCtl + kSmallPlanLog;
+constexpr size_t kSmallCtl = 256;
 constexpr size_t kSmallPlan = (sizeof(SortPlan) + 255) / 256 * 256;
 constexpr size_t kSmallPresent = 256 * sizeof(u32);
 constexpr size_t kSmallCode = 256 * sizeof(u16);
 constexpr size_t kSmallSample = size_t(kLazySamples) * sizeof(u64);
-constexpr size_t kSmallBytes =
-    kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent + kSmallCode + kSmallSample;
-constexpr int kPlanFlagWords = 3 * kMaxPasses + 1;  // skip, src, iota, final_buf
+constexpr size_t kSmallBytes = kSmallHist + kMirrorBytes + kSmallCtl + kSmallPlan + kSmallPresent +
+                               kSmallCode + kSmallSample;
+static_assert(kSmallCounters % 8 == 0 && kSmallRoundCtl % 8 == 0, "mirror alignment");
+static_assert(sizeof(SortCtl) <= kSmallCtl, "control block");
 
 
 template <typename T>
@@ -127,7 +178,13 @@ u64 sort_status_words(u64 cap);
 int bits_of(u64 v);
 void free_workspace(sa_ctx* c);
 sa_status ensure_workspace(sa_ctx* c, u64 n);
-u32 next_gen(sa_ctx* c, hipStream_t s);
+// Reserves `count` look-back generations; clears the status words and
+// restarts the device counter first when the 22-bit tags would wrap.
+void reserve_gens(sa_ctx* c, u32 count, hipStream_t s);
+void bind_small(sa_ctx* c, char* p);
+// Initial control words of a freshly allocated control block (synchronous).
+sa_status init_small(char* p);
+void drop_graphs(sa_ctx* c);
 hipEvent_t take_event(sa_ctx* c);
 
 // Brackets one launch with events when tracing.
@@ -171,11 +228,25 @@ struct Bufs {
 };
 
 Bufs full_bufs(sa_ctx* c);
-SortGeom make_geom(u64 count, int items, int block);
-int default_wgs_per_cu(int items, int block, bool table);
+int default_wgs_per_cu(int items, int block, bool table, int rb);
+// Radix passes that cover `bits` key bits at the context's digit width.
+inline int npass_for(const sa_ctx* c, int bits) { return passes_for(bits, c->radix_bits); }
+// A sort in two parts: begin_sort sets the control words (count = *dev_count,
+// else `bound`; with rc it starts a device-driven round); sort_passes runs the
+// histogram, the plan (flags to plan-log row `log_row`, rc->round when < 0)
+// and the sweeps. `bound` >= the count sizes the launch grids. With
+// reserve == false the caller has reserved the generations already.
+void begin_sort(sa_ctx* c, u64 bound, const u64* dev_count, RoundCtl* rc, int npass, bool reserve,
+                hipStream_t s, u64 dense_n = 0);
+void sort_passes(sa_ctx* c, const Bufs& bf, u64 bound, int npass, int vals_present, int log_row,
+                 u64 trace_count, hipStream_t s);
+// A sort of `count` pairs known on the host.
 void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
               hipStream_t s);
-void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s);
+// Re-rank of the current sort (ctl->count elements, at most `bound`).
+void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, u64 bound,
+                u64 trace_count, hipStream_t s);
+u32 stream_grid(const sa_ctx* c, u64 bound, u32 per_block);
 RerankArgs single_args(u64 count, u64 n, int b, int mode);
 sa_status readback(sa_ctx* c, hipStream_t s);
 u32 passes_run(const sa_ctx* c, int slot, int npass);

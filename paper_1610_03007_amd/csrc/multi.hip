@@ -213,7 +213,7 @@ struct Engine {
       {
         Tracer tr(c, s, SA_KERNEL_OTHER, double(A0));
         launch_multi_presence(text_arena, tab, nl, s);
-        launch_multi_codes(tab, nl, idbits, c->round0_trim, s);
+        launch_multi_codes(tab, nl, idbits, c->round0_trim, c->radix_bits, s);
       }
       Tracer tr(c, s, SA_KERNEL_PACK_TEXT, double(A0) * 13.0);
       launch_multi_pack0(text_arena, tab, nl, idshift, c->keysA, c->valsA, s);
@@ -230,7 +230,7 @@ struct Engine {
     }
     const u64 total = A0 + active;
     if (total) {
-      run_sort(c, bufs, total, kMaxPasses, 1, slot_info, s);
+      run_sort(c, bufs, total, npass_for(c, 64), 1, slot_info, s);
       RerankArgs a{};
       a.count = total;
       a.n = 0;
@@ -242,7 +242,7 @@ struct Engine {
       a.tbase = tab.base;
       a.tlen = tab.len;
       a.tround0 = tab.round0;
-      run_rerank(c, bufs, a, sa_arena, s);
+      run_rerank(c, bufs, a, sa_arena, total, total, s);
       last_args = a;
       // Survivors per text; their number is read on the device.
       Tracer tr(c, s, SA_KERNEL_OTHER, 0);
@@ -306,7 +306,7 @@ struct Engine {
       // writing only the ISA.
       RerankArgs a = last_args;
       a.mode = kRerankScatterIsa | kRerankIsaOnly;
-      run_rerank(c, full_bufs(c), a, nullptr, s);
+      run_rerank(c, full_bufs(c), a, nullptr, a.count, a.count, s);
     }
     return SA_OK;
   }
@@ -375,7 +375,7 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
     st = eng.round_step(text, d_sa, r == 0 ? joining : std::vector<u32>(), finished, r, s);
     if (st != SA_OK) return st;
     info.active[r] = in_round;
-    info.passes_run[r] = passes_run(c, r, kMaxPasses);
+    info.passes_run[r] = passes_run(c, r, npass_for(c, 64));
     info.key_bits[r] = 64;
     info.rounds = u32(r + 1);
     in_round = eng.active;

@@ -13,7 +13,11 @@
 
 namespace drv {
 
-u64 sort_status_words(u64 cap) { return ceil_div(cap, kSortTileMin) * kRadix; }
+// Look-back statuses: one per digit of every tile. Tiles of 256-digit sorts
+// have at least kSortTileMin pairs and those of 512-digit sorts at least
+// 2 * kSortTileMin, so 256 words per kSortTileMin pairs (and one tile of
+// slack for the rounding) hold either.
+u64 sort_status_words(u64 cap) { return (ceil_div(cap, kSortTileMin) + 1) * kRadix; }
 
 int bits_of(u64 v) { return v == 0 ? 0 : 64 - __builtin_clzll(v); }
 
@@ -55,19 +59,39 @@ sa_status ensure_workspace(sa_ctx* c, u64 n) {
     free_workspace(c);
     return SA_EDEVICE;
   }
+  // Captured rounds name the old buffers.
+  drop_graphs(c);
   c->cap = cap;
-  c->gen = 0;
   return SA_OK;
 }
 
-// Next look-back generation; clears the status array when the 22-bit counter
-// wraps.
-u32 next_gen(sa_ctx* c, hipStream_t s) {
-  if (c->gen + 1 >= kGenMask) {
+void reserve_gens(sa_ctx* c, u32 count, hipStream_t s) {
+  if (u64(c->gen) + count + 1 >= kGenMask) {
     launch_fill_u64(c->status, sort_status_words(c->cap), 0, s);
-    c->gen = 0;
+    launch_sort_gen_reset(c->ctl, s);
+    c->gen = 1;
   }
-  return ++c->gen;
+  c->gen += count;
+}
+
+sa_status init_small(char* p) {
+  // Everything zero, then the generation counter at 1.
+  SortCtl ctl{};
+  ctl.gen_next = 1;
+  if (hipMemset(p, 0, kSmallBytes) != hipSuccess ||
+      hipMemcpy(p + kSmallHist + kMirrorBytes, &ctl, sizeof(ctl), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    return SA_EDEVICE;
+  }
+  return SA_OK;
+}
+
+void drop_graphs(sa_ctx* c) {
+  for (GraphEntry& e : c->graph_cache)
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  c->graph_cache.clear();
 }
 
 hipEvent_t take_event(sa_ctx* c) {
@@ -105,98 +129,103 @@ void collect_trace(sa_ctx* c) {
 
 Bufs full_bufs(sa_ctx* c) { return Bufs{c->keysA, c->keysB, c->valsA, c->valsB}; }
 
-// Sweep geometry: tiles of block * items pairs, chunks of a power-of-two
-// number of tiles so that at most kChunks chunks cover the input.
-SortGeom make_geom(u64 count, int items, int block) {
-  SortGeom g;
-  g.count = count;
-  g.tile = u32(block * items);
-  const u64 tiles = std::max<u64>(1, ceil_div(count, g.tile));
-  const u64 per = ceil_div(tiles, kChunks);
-  u32 lg = 0;
-  while ((u64(1) << lg) < per) ++lg;
-  g.ct_log2 = lg;
-  g.nchunks = u32(ceil_div(tiles, u64(1) << lg));
-  return g;
+// Workgroups of a grid-stride launch over at most `bound` items, per_block
+// items per workgroup: enough to fill the CUs, never more than the items.
+u32 stream_grid(const sa_ctx* c, u64 bound, u32 per_block) {
+  const u64 want = std::max<u64>(1, ceil_div(bound, per_block));
+  return u32(std::min<u64>(want, u64(c->num_cus) * 16));
 }
 
 // Sweep workgroups one CU holds at once for each tile shape (register and LDS
 // limits of the kernel instances).
-int default_wgs_per_cu(int items, int block, bool table) {
+int default_wgs_per_cu(int items, int block, bool table, int rb) {
   // The runtime's occupancy figure for the shape, cached per shape; if the
   // query fails, what one CU's 160 KB of LDS holds: the key tile, the per-wave
   // digit counts (16 bits), the 16-bit chunk histograms of the next sweep, the
   // match table if any and about 4 KB of small arrays.
-  static std::atomic<int> cache[2][2][32];
-  const int bi = block == 2 * kRadix ? 1 : 0;
+  static std::atomic<int> cache[kRadixBitsMax - kRadixBitsMin + 1][2][2][32];
+  const int ri = std::min(std::max(rb, kRadixBitsMin), kRadixBitsMax) - kRadixBitsMin;
+  const int bi = block == 512 ? 1 : 0;
   const int ii = items & 31;
   const int ti = table ? 1 : 0;
-  int n = cache[ti][bi][ii].load(std::memory_order_relaxed);
+  int n = cache[ri][ti][bi][ii].load(std::memory_order_relaxed);
   if (n > 0) return n;
-  n = onesweep_wgs_per_cu(items, block, table);
+  n = onesweep_wgs_per_cu(items, block, table, rb);
   if (n <= 0) {
-    const int lds = block * items * 8 + (block / kWave / 2) * kRadix * 4 + kChunks * kRadix * 2 +
-                    (table ? (block / kWave) * kRadix * 8 : 0) + 4096;
+    const int radix = 1 << rb;
+    const int lds = block * items * 8 + (block / kWave / 2) * radix * 4 + kChunks * radix * 2 +
+                    (table ? (block / kWave) * radix * 8 : 0) + radix * 12 + 1024;
     n = (160 * 1024) / lds;
     if (n < 1) n = 1;
     return n;
   }
-  cache[ti][bi][ii].store(n, std::memory_order_relaxed);
+  cache[ri][ti][bi][ii].store(n, std::memory_order_relaxed);
   return n;
 }
 
+void begin_sort(sa_ctx* c, u64 bound, const u64* dev_count, RoundCtl* rc, int npass, bool reserve,
+                hipStream_t s, u64 dense_n) {
+  if (reserve) reserve_gens(c, u32(npass), s);
+  Tracer t(c, s, SA_KERNEL_OTHER, 0);
+  static_assert(kCtrSortTiles < kCtrActive && kCtrKeyOr < kCtrActive && kCtrKeyNot < kCtrActive,
+                "sort_begin clears the sort's counters");
+  launch_sort_begin(c->ctl, rc, bound, dev_count, npass, dense_n, c->hist_in, kClearWords,
+                    c->counters, s);
+}
+
 // Sorts (kA, vA or generated values) by the low 8*npass bits. The sorted pairs
-// end in the buffer named by plan->final_buf. The plan flags are copied to
-// h_plans slot `slot` on the stream.
-void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
-              hipStream_t s) {
-  const SortGeom geo = make_geom(count, c->sort_items, c->sort_block);
+// end in the buffer named by plan->final_buf.
+void sort_passes(sa_ctx* c, const Bufs& bf, u64 bound, int npass, int vals_present, int log_row,
+                 u64 trace_count, hipStream_t s) {
+  const u32 tile = u32(c->sort_items * c->sort_block);
   const bool table = c->sort_match == 1;
+  const u32 hgrid = radix_histogram_grid(bound, tile);
   {
-    Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    // Chunk histograms and tickets; tile tickets, the key ORs and the
-    // survivor count the re-rank adds to.
-    static_assert(kCtrSortTiles < kCtrActive && kCtrKeyOr < kCtrActive && kCtrKeyNot < kCtrActive,
-                  "one fill clears the sort's counters");
-    launch_fill_u32(c->hist_in, 2 * kChunkHistWords + kTicketWords, 0, s);
-    launch_fill_u64(c->counters, kCtrActive + 1, 0, s);
-  }
-  {
-    Tracer t(c, s, SA_KERNEL_HISTOGRAM, double(count) * 8.0);
-    launch_radix_histogram(bf.kA, geo, c->hist_in, c->counters, s);
+    Tracer t(c, s, SA_KERNEL_HISTOGRAM, double(trace_count) * 8.0);
+    launch_radix_histogram(bf.kA, c->ctl, tile, hgrid, c->hist_in, c->counters, c->radix_bits, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
-    launch_radix_plan(c->counters, npass, vals_present, c->plan, s);
-    launch_radix_histogram_first(bf.kA, geo, c->plan, c->hist_in, s);
+    launch_radix_plan(c->ctl, c->counters, npass, vals_present, c->plan, c->plan_log, log_row,
+                      c->rc, c->radix_bits, s);
+    launch_radix_histogram_first(bf.kA, c->ctl, tile, hgrid, c->plan, c->hist_in, c->radix_bits,
+                                 s);
   }
-  (void)hipMemcpyAsync(c->h_plans + size_t(slot) * kPlanFlagWords, c->plan->skip,
-                       kPlanFlagWords * sizeof(u32), hipMemcpyDeviceToHost, s);
-  const u64 tiles = ceil_div(count, geo.tile);
+  // Persistent sweep workgroups: what the CUs hold, at most one per tile of
+  // the bound, at least one per chunk.
+  const u64 tiles = ceil_div(std::max<u64>(bound, 1), tile);
   const int per_cu = c->sort_wgs_per_cu > 0
                          ? c->sort_wgs_per_cu
-                         : default_wgs_per_cu(c->sort_items, c->sort_block, table);
-  const u64 want = std::min<u64>(tiles, u64(c->num_cus) * u64(per_cu));
-  const u32 grid = u32(std::max<u64>(1, want / geo.nchunks) * geo.nchunks);
+                         : default_wgs_per_cu(c->sort_items, c->sort_block, table, c->radix_bits);
+  u64 grid = std::min<u64>(tiles, u64(c->num_cus) * u64(per_cu));
+  grid = std::max<u64>(grid, u64(kChunks));
   for (int p = 0; p < npass; ++p) {
-    u32 gen = next_gen(c, s);
-    Tracer t(c, s, SA_KERNEL_SORT_PASS, 0, slot, p, count);
-    launch_onesweep_pass(bf.kA, bf.kB, bf.vA, bf.vB, geo, p, c->plan, c->hist_in, c->hist_run,
-                         c->tickets, c->status, c->counters, gen, c->sort_items,
-                         c->sort_block, table, grid, s);
+    Tracer t(c, s, SA_KERNEL_SORT_PASS, 0, log_row, p, trace_count);
+    launch_onesweep_pass(bf.kA, bf.kB, bf.vA, bf.vB, c->ctl, p, c->plan, c->hist_in, c->hist_run,
+                         c->tickets, c->status, c->counters, c->sort_items, c->sort_block, table,
+                         c->radix_bits, u32(grid), s);
   }
 }
 
-void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, hipStream_t s) {
-  const double count = double(args.count);
+void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present, int slot,
+              hipStream_t s) {
+  begin_sort(c, count, nullptr, nullptr, npass, true, s);
+  sort_passes(c, bf, count, npass, vals_present, slot, count, s);
+}
+
+void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, u64 bound,
+                u64 trace_count, hipStream_t s) {
+  const double count = double(trace_count);
   // 12 bytes read per element; 4 written (ISA, SA or survivor name) plus 4 for a
   // survivor's position, counted as 4 per element either way.
   double bytes = count * 16.0 - ((args.mode & kRerankScatterIsa) ? 0.0 : 4.0 * count);
   if (args.mode & kRerankIsaOnly) bytes = count * 16.0;
   Tracer t(c, s, (args.mode & kRerankIsaOnly) ? SA_KERNEL_ISA_SCATTER : SA_KERNEL_RERANK, bytes);
-  launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->isa, d_sa,
+  const u32 grid = u32(std::min<u64>(std::max<u64>(1, ceil_div(bound, kRerankTile)),
+                                     u64(c->num_cus) * 8));
+  launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->ctl, c->isa, d_sa,
                         args.tbase ? nullptr : c->act_idx, args.tbase ? c->act_ti : nullptr,
-                        c->act_rank, c->counters, s);
+                        c->act_rank, c->counters, grid, s);
 }
 
 // Re-rank arguments of a single text: round 0 (one group, every rank 1) or a
@@ -217,8 +246,9 @@ RerankArgs single_args(u64 count, u64 n, int b, int mode) {
 }
 
 sa_status readback(sa_ctx* c, hipStream_t s) {
-  if (hipMemcpyAsync(c->h_counters, c->counters, kCtrCount * sizeof(u64), hipMemcpyDeviceToHost,
-                     s) != hipSuccess)
+  // counters | rc | plan log in one copy.
+  if (hipMemcpyAsync(c->h_mirror, c->counters, kMirrorBytes, hipMemcpyDeviceToHost, s) !=
+      hipSuccess)
     return SA_EDEVICE;
   if (hipStreamSynchronize(s) != hipSuccess) return SA_EDEVICE;
   if (hipGetLastError() != hipSuccess) return SA_EDEVICE;
@@ -235,6 +265,110 @@ u32 passes_run(const sa_ctx* c, int slot, int npass) {
 
 u32 final_buf_of(const sa_ctx* c, int slot) {
   return c->h_plans[size_t(slot) * kPlanFlagWords + 3 * kMaxPasses];
+}
+
+// Everything one later round of a single text reads: the same for every
+// round of a build, so that a captured round replays unchanged.
+struct LaterRound {
+  u64 n, bound;
+  u64 dense_n;  // n when dense rounds are allowed (the ISA holds every name), else 0
+  int b, npass;
+  bool lazy;
+  Bufs bufs;
+  const u8* text;
+  const u64* keys0;
+  u32* d_sa;
+};
+
+// One later round (Alg. 5 loop body): the round's count is the last re-rank's
+// survivor count, read on the device; with none left every kernel returns at
+// once. log_row: the plan-log row (the round index), or -1 to take it from the
+// device. trace_count: the count, when the host knows it (tracing).
+void enqueue_later_round(sa_ctx* c, const LaterRound& L, bool reserve, int log_row,
+                         u64 trace_count, bool trace_dense, hipStream_t s) {
+  begin_sort(c, L.bound, c->counters + kCtrActive, c->rc, L.npass, reserve, s, L.dense_n);
+  {
+    // A dense round reads two names and writes a key per suffix (16 bytes);
+    // otherwise index, rank and the gathered name in, key and value out.
+    Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(trace_count) * (trace_dense ? 16.0 : 24.0));
+    const u32 grid = stream_grid(c, L.bound, 256);
+    if (L.lazy)
+      launch_pack_pairs_lazy(c->act_idx, c->act_rank, c->ctl, c->rc, L.n, L.b, c->isa, L.text,
+                             c->code, c->counters, L.keys0, c->sample, c->live, L.bufs.kA,
+                             L.bufs.vA, grid, s);
+    else
+      launch_pack_pairs(c->act_idx, c->act_rank, c->ctl, c->rc, L.n, L.b, c->isa, L.bufs.kA,
+                        L.bufs.vA, grid, s);
+  }
+  sort_passes(c, L.bufs, L.bound, L.npass, 1, log_row, trace_count, s);
+  run_rerank(c, L.bufs, single_args(L.bound, L.n, L.b, kRerankScatterIsa), L.d_sa, L.bound,
+             trace_count, s);
+}
+
+GraphKey later_key(const sa_ctx* c, const LaterRound& L) {
+  GraphKey k;
+  std::memset(&k, 0, sizeof(k));
+  k.n = L.n;
+  k.bound = L.bound | (L.dense_n ? u64(1) << 63 : 0);
+  const void* p[12] = {L.bufs.kA, L.bufs.kB, L.bufs.vA, L.bufs.vB, L.text, L.keys0, L.d_sa,
+                       c->isa, c->act_idx, c->small, c->status, c->live};
+  std::memcpy(k.ptr, p, sizeof(p));
+  const u32 knobs[10] = {u32(L.b),           u32(L.npass),           L.lazy ? 1u : 0u,
+                         u32(c->sort_items), u32(c->sort_block),     u32(c->sort_match),
+                         u32(c->sort_wgs_per_cu), u32(c->num_cus),   u32(c->radix_bits), 0u};
+  std::memcpy(k.knobs, knobs, sizeof(knobs));
+  return k;
+}
+
+// The captured form of L's round, if its key has been seen before (captured
+// now on the second sighting); nullptr: launch directly.
+hipGraphExec_t later_graph(sa_ctx* c, const LaterRound& L) {
+  constexpr size_t kMaxGraphs = 8;
+  const GraphKey key = later_key(c, L);
+  c->graph_clock += 1;
+  GraphEntry* e = nullptr;
+  for (GraphEntry& g : c->graph_cache)
+    if (std::memcmp(&g.key, &key, sizeof(key)) == 0) e = &g;
+  if (!e) {
+    if (c->graph_cache.size() >= kMaxGraphs) {
+      auto lru = std::min_element(
+          c->graph_cache.begin(), c->graph_cache.end(),
+          [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+      if (lru->exec) (void)hipGraphExecDestroy(lru->exec);
+      c->graph_cache.erase(lru);
+    }
+    GraphEntry ne;
+    ne.key = key;
+    c->graph_cache.push_back(ne);
+    e = &c->graph_cache.back();
+  }
+  e->last_use = c->graph_clock;
+  e->seen += 1;
+  if (e->exec || e->seen < 2) return e->exec;
+  if (!c->cap_stream &&
+      hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    c->cap_stream = nullptr;
+    return nullptr;
+  }
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  enqueue_later_round(c, L, false, -1, 0, false, c->cap_stream);
+  if (hipStreamEndCapture(c->cap_stream, &g) != hipSuccess || !g) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  hipGraphExec_t exec = nullptr;
+  if (hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    exec = nullptr;
+  }
+  (void)hipGraphDestroy(g);
+  e->exec = exec;
+  return exec;
 }
 
 sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_sa, u32* d_isa,
@@ -256,19 +390,21 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   {
     Tracer t(c, s, SA_KERNEL_OTHER, 0);
     launch_fill_u64(c->counters, kCtrCount, 0, s);
+    launch_fill_u64(reinterpret_cast<u64*>(c->rc), sizeof(RoundCtl) / 8, 0, s);
     launch_fill_u64(reinterpret_cast<u64*>(c->present), 256 / 2, 0, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_OTHER, double(n));
     launch_byte_presence(text, n, c->present, s);
-    launch_alphabet_codes(c->present, c->code, c->counters, c->round0_trim, 0, s);
+    launch_alphabet_codes(c->present, c->code, c->counters, c->round0_trim, 0, c->radix_bits, s);
   }
   {
     Tracer t(c, s, SA_KERNEL_PACK_TEXT, double(n) * 9.0);
     launch_pack_text(text, n, c->code, c->counters, c->keysA, s);
   }
-  run_sort(c, full, n, kMaxPasses, 0, 0, s);
-  run_rerank(c, full, single_args(n, n, 0, 0), d_sa, s);
+  const int npass0 = npass_for(c, 64);
+  run_sort(c, full, n, npass0, 0, 0, s);
+  run_rerank(c, full, single_args(n, n, 0, 0), d_sa, n, n, s);
   st = readback(c, s);
   if (st != SA_OK) return st;
 
@@ -279,9 +415,9 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   info.rounds = 1;
   info.active[0] = n;
   info.key_bits[0] = info.code_bits * info.chars0;
-  info.passes_run[0] = passes_run(c, 0, kMaxPasses);
-  u64 h = info.chars0;
-  info.prefix_len = h;
+  info.passes_run[0] = passes_run(c, 0, npass0);
+  const u64 chars0 = info.chars0;
+  info.prefix_len = chars0;
   u64 active = c->h_counters[kCtrActive];
 
   // ISA after round 0: eager scatter, or lazy (survivors only) when few
@@ -305,46 +441,73 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
       launch_isa_scatter_list(c->act_idx, c->act_rank, active, n, c->isa, c->live, s);
       launch_lazy_sample(keys0, n, c->sample, s);
     } else {
-      run_rerank(c, full, single_args(n, n, 0, kRerankScatterIsa | kRerankIsaOnly), d_sa, s);
+      run_rerank(c, full, single_args(n, n, 0, kRerankScatterIsa | kRerankIsaOnly), d_sa, n, n,
+                 s);
     }
   }
   // Later rounds sort at most `active` pairs; in lazy mode their buffers are
   // carved out of the spare keys so that the round-0 sorted keys stay intact.
-  Bufs later = full;
+  LaterRound L;
+  L.n = n;
+  L.bound = std::max<u64>(active, 1);
+  // Dense rounds read the name of every position, so only the eager ISA has them.
+  L.dense_n = lazy ? 0 : n;
+  L.b = bits_of(n);  // ranks and second ranks are <= n
+  L.npass = npass_for(c, 2 * L.b);
+  L.lazy = lazy;
+  L.bufs = full;
   if (lazy) {
-    later.kA = spare;
-    later.kB = spare + a1;
-    later.vA = reinterpret_cast<u32*>(spare + 2 * a1);
-    later.vB = later.vA + a1;
+    L.bufs.kA = spare;
+    L.bufs.kB = spare + a1;
+    L.bufs.vA = reinterpret_cast<u32*>(spare + 2 * a1);
+    L.bufs.vB = L.bufs.vA + a1;
   }
+  L.text = text;
+  L.keys0 = keys0;
+  L.d_sa = d_sa;
 
-  // Later rounds: only suffixes whose name is still shared.
-  const int b = bits_of(n);  // ranks and second ranks are <= n
-  const int key_bits = 2 * b;
-  const int npass = int(ceil_div(u64(key_bits), kRadixBits));
+  // Later rounds, run ahead of the host: up to `ahead` rounds are enqueued
+  // before the survivor count is read back (1, 2, 4, ... unless fixed by the
+  // tuning); a round that finds no survivor does nothing. Tracing runs one
+  // round per readback so that every launch's count is known.
+  const bool trace = c->trace;
+  const bool use_graphs = c->graphs && !c->graphs_blocked && !trace;
+  u32 ahead = c->rounds_ahead ? c->rounds_ahead : 1;
+  u32 done = 0;  // later rounds run so far
   while (active > 0 && (max_rounds == 0 || info.rounds < max_rounds)) {
-    if (info.rounds >= SA_MAX_ROUNDS) return SA_EDEVICE;  // cannot happen for n < 2^32
-    const int slot = int(info.rounds);
-    {
-      Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
-      if (lazy)
-        launch_pack_pairs_lazy(c->act_idx, c->act_rank, active, n, h, b, c->isa, text, c->code,
-                               c->counters, keys0, c->sample, c->live, later.kA, later.vA, s);
-      else
-        launch_pack_pairs(c->act_idx, c->act_rank, active, n, h, b, c->isa, later.kA, later.vA,
-                          s);
+    u32 todo = trace ? 1 : ahead;
+    if (max_rounds) todo = std::min<u32>(todo, max_rounds - info.rounds);
+    todo = std::min<u32>(todo, u32(SA_MAX_ROUNDS - 1) - done);
+    if (todo == 0) return SA_EDEVICE;  // cannot happen for n < 2^32
+    hipGraphExec_t exec = use_graphs ? later_graph(c, L) : nullptr;
+    if (exec) {
+      reserve_gens(c, u32(L.npass) * todo, s);
+      for (u32 r = 0; r < todo; ++r)
+        if (hipGraphLaunch(exec, s) != hipSuccess) return SA_EDEVICE;
+      c->graph_launches += todo;
+      info.graph_rounds += todo;
+    } else {
+      // With tracing (one round per readback) the host knows the round's count.
+      const bool dense = L.dense_n && 4 * active >= 3 * L.dense_n;
+      for (u32 r = 0; r < todo; ++r)
+        enqueue_later_round(c, L, true, trace ? int(done + 1 + r) : -1,
+                            trace ? (dense ? n : active) : 0, dense, s);
     }
-    run_sort(c, later, active, npass, 1, slot, s);
-    run_rerank(c, later, single_args(active, n, b, kRerankScatterIsa), d_sa, s);
     st = readback(c, s);
     if (st != SA_OK) return st;
-    info.active[slot] = active;
-    info.key_bits[slot] = u32(key_bits);
-    info.passes_run[slot] = passes_run(c, slot, npass);
-    info.rounds += 1;
-    h *= 2;
-    info.prefix_len = h;
+    const u32 now = c->h_rc->round;
+    if (now <= done || now > done + todo) return SA_EDEVICE;
+    info.dense_rounds = c->h_rc->dense;
+    for (u32 k = done + 1; k <= now; ++k) {
+      info.active[k] = c->h_rc->active[k];
+      info.key_bits[k] = u32(2 * L.b);
+      info.passes_run[k] = passes_run(c, int(k), L.npass);
+    }
+    done = now;
+    info.rounds = 1 + done;
+    info.prefix_len = chars0 << done;
     active = c->h_counters[kCtrActive];
+    if (!c->rounds_ahead) ahead = std::min<u32>(2 * ahead, 16);
   }
   if (d_isa) {
     if (lazy)
@@ -381,12 +544,20 @@ void bind_small(sa_ctx* c, char* p) {
   c->hist_in = reinterpret_cast<u32*>(p);
   c->hist_run = c->hist_in + kChunkHistWords;
   c->tickets = c->hist_run + kChunkHistWords;
-  c->counters = reinterpret_cast<u64*>(p + kSmallHist);
-  c->plan = reinterpret_cast<SortPlan*>(p + kSmallHist + kSmallCounters);
-  c->present = reinterpret_cast<u32*>(p + kSmallHist + kSmallCounters + kSmallPlan);
-  c->code = reinterpret_cast<u16*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent);
-  c->sample = reinterpret_cast<u64*>(p + kSmallHist + kSmallCounters + kSmallPlan + kSmallPresent +
-                                     kSmallCode);
+  p += kSmallHist;
+  c->counters = reinterpret_cast<u64*>(p);
+  c->rc = reinterpret_cast<RoundCtl*>(p + kSmallCounters);
+  c->plan_log = reinterpret_cast<u32*>(p + kSmallCounters + kSmallRoundCtl);
+  p += kMirrorBytes;
+  c->ctl = reinterpret_cast<SortCtl*>(p);
+  p += kSmallCtl;
+  c->plan = reinterpret_cast<SortPlan*>(p);
+  p += kSmallPlan;
+  c->present = reinterpret_cast<u32*>(p);
+  p += kSmallPresent;
+  c->code = reinterpret_cast<u16*>(p);
+  p += kSmallCode;
+  c->sample = reinterpret_cast<u64*>(p);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,7 +585,7 @@ constexpr ScratchLayout scratch_layout() {
   L.act_idx = at, at += align256(kNoAllocCap * 4);
   L.act_rank = at, at += align256(kNoAllocCap * 4);
   L.live = at, at += align256((kNoAllocCap + 31) / 32 * 4);
-  L.status = at, at += align256((kNoAllocCap + kSortTileMin - 1) / kSortTileMin * kRadix * 8);
+  L.status = at, at += align256(((kNoAllocCap + kSortTileMin - 1) / kSortTileMin + 1) * kRadix * 8);
   L.small = at, at += align256(kSmallBytes);
   L.bytes = at;
   return L;
@@ -452,8 +623,9 @@ sa_status noalloc_setup(int device) {
     (void)hipGetLastError();
     return SA_EDEVICE;
   }
+  if (init_small(reinterpret_cast<char*>(base + kScratch.small)) != SA_OK) return SA_EDEVICE;
   d.ptr = base;
-  d.gen = 0;
+  d.gen = 1;
   return SA_OK;
 }
 
@@ -466,19 +638,24 @@ struct WorkspaceView {
   u64* status;
   u32 *hist_in, *hist_run, *tickets;
   u64* counters;
+  RoundCtl* rc;
+  u32* plan_log;
+  SortCtl* ctl;
   SortPlan* plan;
   u32* present;
   u16* code;
   u64* sample;
   u32 gen;
   bool trace;
+  bool graphs_blocked;
 };
 
 WorkspaceView save_view(const sa_ctx* c) {
-  return WorkspaceView{c->cap,      c->keysA,   c->keysB,    c->valsA,    c->valsB,
-                       c->isa,      c->live,    c->act_idx,  c->act_rank, c->status,
-                       c->hist_in,  c->hist_run, c->tickets, c->counters, c->plan,
-                       c->present,  c->code,    c->sample,   c->gen,      c->trace};
+  return WorkspaceView{c->cap,      c->keysA,    c->keysB,        c->valsA,    c->valsB,
+                       c->isa,      c->live,     c->act_idx,      c->act_rank, c->status,
+                       c->hist_in,  c->hist_run, c->tickets,      c->counters, c->rc,
+                       c->plan_log, c->ctl,      c->plan,         c->present,  c->code,
+                       c->sample,   c->gen,      c->trace,        c->graphs_blocked};
 }
 
 void restore_view(sa_ctx* c, const WorkspaceView& v) {
@@ -496,12 +673,16 @@ void restore_view(sa_ctx* c, const WorkspaceView& v) {
   c->hist_run = v.hist_run;
   c->tickets = v.tickets;
   c->counters = v.counters;
+  c->rc = v.rc;
+  c->plan_log = v.plan_log;
+  c->ctl = v.ctl;
   c->plan = v.plan;
   c->present = v.present;
   c->code = v.code;
   c->sample = v.sample;
   c->gen = v.gen;
   c->trace = v.trace;
+  c->graphs_blocked = v.graphs_blocked;
 }
 
 }  // namespace drv
@@ -553,17 +734,19 @@ sa_status sa_ctx_create(sa_ctx** out, int device, const char* tune_cache_json) {
     return SA_ENOMEM;
   }
   bind_small(c, static_cast<char*>(c->small));
-  if (noalloc_setup(device) != SA_OK) {
+  if (init_small(static_cast<char*>(c->small)) != SA_OK || noalloc_setup(device) != SA_OK) {
     sa_ctx_destroy(c);
     return SA_EDEVICE;
   }
-  if (hipHostMalloc(reinterpret_cast<void**>(&c->h_counters), kCtrCount * sizeof(u64)) !=
-          hipSuccess ||
-      hipHostMalloc(reinterpret_cast<void**>(&c->h_plans),
-                    size_t(SA_MAX_ROUNDS + 1) * kPlanFlagWords * sizeof(u32)) != hipSuccess) {
+  if (hipHostMalloc(&c->h_mirror, kMirrorBytes) != hipSuccess) {
+    c->h_mirror = nullptr;
     sa_ctx_destroy(c);
     return SA_ENOMEM;
   }
+  c->h_counters = static_cast<u64*>(c->h_mirror);
+  c->h_rc = reinterpret_cast<RoundCtl*>(static_cast<char*>(c->h_mirror) + kSmallCounters);
+  c->h_plans = reinterpret_cast<u32*>(static_cast<char*>(c->h_mirror) + kSmallCounters +
+                                      kSmallRoundCtl);
   *out = c;
   return SA_OK;
 }
@@ -572,9 +755,10 @@ sa_status sa_ctx_destroy(sa_ctx* ctx) {
   if (!ctx) return SA_OK;
   (void)hipSetDevice(ctx->device);
   free_workspace(ctx);
+  drop_graphs(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   (void)hipFree(ctx->small);
-  if (ctx->h_counters) (void)hipHostFree(ctx->h_counters);
-  if (ctx->h_plans) (void)hipHostFree(ctx->h_plans);
+  if (ctx->h_mirror) (void)hipHostFree(ctx->h_mirror);
   (void)hipFree(ctx->toff);
   for (hipEvent_t e : ctx->event_pool) (void)hipEventDestroy(e);
   delete ctx->tune;
@@ -620,6 +804,7 @@ sa_status sa_build_noalloc(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint3
   v.live = reinterpret_cast<u32*>(base + kScratch.live);
   v.status = reinterpret_cast<u64*>(base + kScratch.status);
   v.trace = false;
+  v.graphs_blocked = true;  // capturing a round would allocate
   {
     std::lock_guard<std::mutex> lk(g_noalloc_mu);
     v.gen = g_noalloc[size_t(ctx->device)].gen;
@@ -668,7 +853,7 @@ sa_status sa_radix_sort_pairs(sa_ctx* ctx, uint64_t* d_keys, uint32_t* d_vals, u
       hipMemcpyAsync(ctx->valsA, d_vals, count * sizeof(u32), hipMemcpyDeviceToDevice, s) !=
           hipSuccess)
     return SA_EDEVICE;
-  const int npass = int(ceil_div(key_bits, kRadixBits));
+  const int npass = npass_for(ctx, int(key_bits));
   run_sort(ctx, full_bufs(ctx), count, npass, 1, 0, s);
   st = readback(ctx, s);  // also waits for the plan flags
   if (st != SA_OK) {

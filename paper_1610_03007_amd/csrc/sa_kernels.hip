@@ -19,11 +19,17 @@ namespace {
 
 __device__ inline int lane_id() { return threadIdx.x & (kWave - 1); }
 
-// The 8-bit digit at bit `shift` (a multiple of 8, the same in every lane) of a
-// key, with 32-bit operations: the word that holds it, then a bit-field extract.
-__device__ inline u32 digit_of(u64 k, int shift) {
-  const u32 word = shift >= 32 ? u32(k >> 32) : u32(k);
-  return __builtin_amdgcn_ubfe(word, u32(shift & 31), 8u);
+// The RB-bit digit at bit `shift` (a multiple of RB, the same in every lane)
+// of a key. Byte digits never straddle the two 32-bit words: the word that
+// holds the digit, then a bit-field extract; other widths shift the key.
+template <int RB>
+__device__ inline u32 digit_at(u64 k, int shift) {
+  if constexpr (RB == 8) {
+    const u32 word = shift >= 32 ? u32(k >> 32) : u32(k);
+    return __builtin_amdgcn_ubfe(word, u32(shift & 31), 8u);
+  } else {
+    return u32(k >> shift) & ((1u << RB) - 1u);
+  }
 }
 
 
@@ -158,7 +164,7 @@ void launch_byte_presence(const u8* text, u64 n, u32* present, hipStream_t s) {
 __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restrict__ present,
                                                              u16* __restrict__ code,
                                                              u64* __restrict__ counters,
-                                                             int trim, int idbits) {
+                                                             int trim, int idbits, int rb) {
   __shared__ u32 wsum[4];
   const int t = threadIdx.x;
   u32 p = present[t] ? 1u : 0u;
@@ -177,15 +183,16 @@ __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restri
     u32 w = 32 - __clz(sigma);  // bits of sigma: codes 1..sigma, 0 = sentinel
     if (w == 0) w = 1;
     // As many characters as fit in 64 bits; with `trim`, drop the characters
-    // that would only half-fill a last 8-bit radix digit, saving one sort pass
+    // that would only half-fill a last rb-bit radix digit, saving one sort pass
     // over every suffix for a slightly shorter first prefix.
     // `idbits` high key bits are taken by a text id (batches).
     const u32 avail = 64u - u32(idbits);
     u32 c = avail / w;
     if (c < 1) c = 1;
     const u32 used = u32(idbits) + c * w;
-    if (trim && used % kRadixBits != 0 && used > kRadixBits) {
-      const u32 full = (used / kRadixBits) * kRadixBits;
+    const u32 urb = u32(rb);
+    if (trim && used % urb != 0 && used > urb) {
+      const u32 full = (used / urb) * urb;
       if (full > u32(idbits)) {
         const u32 ct = (full - u32(idbits)) / w;
         if (ct >= 1) c = ct;
@@ -198,9 +205,9 @@ __global__ __launch_bounds__(256) void alphabet_codes_kernel(const u32* __restri
 }
 
 void launch_alphabet_codes(const u32* present, u16* code, u64* counters, int trim, int idbits,
-                           hipStream_t s) {
+                           int rb, hipStream_t s) {
   hipLaunchKernelGGL(alphabet_codes_kernel, dim3(1), dim3(256), 0, s, present, code, counters,
-                     trim, idbits);
+                     trim, idbits, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -300,25 +307,94 @@ void launch_pack_text(const u8* text, u64 n, const u16* code, const u64* counter
 
 __global__ __launch_bounds__(256) void pack_pairs_kernel(const u32* __restrict__ act_idx,
                                                          const u32* __restrict__ act_rank,
-                                                         u64 count, u64 n, u64 h, int b,
-                                                         const u32* __restrict__ isa,
+                                                         const SortCtl* __restrict__ ctl,
+                                                         const RoundCtl* __restrict__ rc, u64 n,
+                                                         int b, const u32* __restrict__ isa,
                                                          u64* __restrict__ keys,
                                                          u32* __restrict__ vals) {
-  u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-  u32 i = act_idx[p];
-  u32 r = act_rank[p];
-  u64 j = u64(i) + h;
-  u32 r1 = (j < n) ? isa[j] : 0u;
-  keys[p] = (u64(r) << b) | u64(r1);
-  vals[p] = i;
+  const u64 count = ctl->count;
+  const u64 h = rc->h;
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  if (ctl->dense) {
+    // Both names are read in position order: two streams, no gather.
+    for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) {
+      const u64 j = i + h;
+      const u32 r1 = (j < n) ? isa[j] : 0u;
+      keys[i] = (u64(isa[i]) << b) | u64(r1);
+    }
+    return;
+  }
+  for (u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += stride) {
+    const u32 i = act_idx[p];
+    const u32 r = act_rank[p];
+    const u64 j = u64(i) + h;
+    const u32 r1 = (j < n) ? isa[j] : 0u;
+    keys[p] = (u64(r) << b) | u64(r1);
+    vals[p] = i;
+  }
 }
 
-void launch_pack_pairs(const u32* act_idx, const u32* act_rank, u64 count, u64 n, u64 h, int b,
-                       const u32* isa, u64* keys, u32* vals, hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(pack_pairs_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s, act_idx,
-                     act_rank, count, n, h, b, isa, keys, vals);
+void launch_pack_pairs(const u32* act_idx, const u32* act_rank, const SortCtl* ctl,
+                       const RoundCtl* rc, u64 n, int b, const u32* isa, u64* keys, u32* vals,
+                       u32 grid, hipStream_t s) {
+  hipLaunchKernelGGL(pack_pairs_kernel, dim3(grid), dim3(256), 0, s, act_idx, act_rank, ctl, rc, n,
+                     b, isa, keys, vals);
+}
+
+// ---------------------------------------------------------------------------
+// Sort control (see SortCtl): the first kernel of every sort.
+
+__global__ __launch_bounds__(256) void sort_begin_kernel(SortCtl* __restrict__ ctl,
+                                                         RoundCtl* __restrict__ rc, u64 host_count,
+                                                         const u64* __restrict__ dev_count,
+                                                         int npass, u64 dense_n,
+                                                         u32* __restrict__ clear,
+                                                         u64 clear_words,
+                                                         u64* __restrict__ counters) {
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  for (u64 i = u64(blockIdx.x) * blockDim.x + threadIdx.x; i < clear_words; i += stride)
+    clear[i] = 0;
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  // The count is read before the counters it may come from are cleared.
+  u64 count = dev_count ? *dev_count : host_count;
+  // Most suffixes still active: sort them all, with keys read in order.
+  const bool dense = count && dense_n && 4 * count >= 3 * dense_n;
+  if (dense) count = dense_n;
+  ctl->dense = dense ? 1u : 0u;
+  if (rc && count) {
+    const u32 k = rc->round + 1;
+    if (k < u32(kMaxRounds)) {
+      rc->round = k;
+      rc->h = counters[kCtrChars] << (k - 1);
+      rc->active[k] = count;
+      if (dense) rc->dense |= u64(1) << k;
+    } else {
+      atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+               (unsigned long long)kErrBounds);
+      count = 0;
+    }
+  }
+  ctl->count = count;
+  ctl->gen_base = ctl->gen_next;
+  ctl->gen_next = ctl->gen_next + u32(npass);
+  for (int i = 0; i <= kCtrActive; ++i) counters[i] = 0;
+}
+
+void launch_sort_begin(SortCtl* ctl, RoundCtl* rc, u64 host_count, const u64* dev_count, int npass,
+                       u64 dense_n, u32* clear, u64 clear_words, u64* counters, hipStream_t s) {
+  u64 blocks = ceil_div(clear_words, 256 * 4);
+  if (blocks < 1) blocks = 1;
+  if (blocks > 256) blocks = 256;
+  hipLaunchKernelGGL(sort_begin_kernel, dim3(u32(blocks)), dim3(256), 0, s, ctl, rc, host_count,
+                     dev_count, npass, dense_n, clear, clear_words, counters);
+}
+
+__global__ void sort_gen_reset_kernel(SortCtl* ctl) {
+  if (threadIdx.x == 0) ctl->gen_next = 1;
+}
+
+void launch_sort_gen_reset(SortCtl* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(sort_gen_reset_kernel, dim3(1), dim3(64), 0, s, ctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,13 +408,36 @@ constexpr int kHistItems = 8;
 // of the keys and of their complements, which tell the plan which digits are
 // constant. Later sweeps get their chunk counts from the sweep before them.
 // Block b counts a contiguous share of chunk b / per_chunk.
+constexpr u64 kHistBlockElems = u64(kHistBlock) * kHistItems * 4;  // a block's share, at least
+constexpr u32 kHistMaxBlocks = 2048;
+
+// Workgroups per chunk of a histogram launch of `grid` workgroups: a few per
+// chunk, at most grid / nchunks. Workgroups past per * nchunks have no share.
+__device__ inline u32 hist_per_chunk(const SortGeom& geo, u32 grid) {
+  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
+  u64 per = (chunk_elems + kHistBlockElems - 1) / kHistBlockElems;
+  const u64 cap = grid / geo.nchunks;
+  if (per > cap) per = cap;
+  if (per < 1) per = 1;
+  return u32(per);
+}
+
+template <int RB>
 __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
-    const u64* __restrict__ keys, u64 count, u64 chunk_elems, u32 nchunks, u32 per_chunk,
+    const u64* __restrict__ keys, const SortCtl* __restrict__ ctl, u32 tile,
     u32* __restrict__ hist_in, u64* __restrict__ counters) {
   constexpr int NP = 2;
-  __shared__ u32 lh[NP * kRadix];
+  constexpr int RADIX = 1 << RB;
+  __shared__ u32 lh[NP * RADIX];
   __shared__ u64 s_or[kHistBlock / kWave], s_not[kHistBlock / kWave];
-  for (int i = threadIdx.x; i < NP * kRadix; i += kHistBlock) lh[i] = 0;
+  const u64 count = ctl->count;
+  if (count == 0) return;
+  const SortGeom geo = sort_geom(count, tile);
+  const u32 per_chunk = hist_per_chunk(geo, gridDim.x);
+  if (blockIdx.x >= per_chunk * geo.nchunks) return;
+  const u32 nchunks = geo.nchunks;
+  const u64 chunk_elems = u64(tile) << geo.ct_log2;
+  for (int i = threadIdx.x; i < NP * RADIX; i += kHistBlock) lh[i] = 0;
   __syncthreads();
   const u32 c = blockIdx.x / per_chunk;
   const u32 g = blockIdx.x % per_chunk;
@@ -367,14 +466,14 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
       if (vmask == 0) continue;  // wave-uniform
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
-        const u32 d = u32(key[j] >> (p * kRadixBits)) & (kRadix - 1);
+        const u32 d = u32(key[j] >> (p * RB)) & (RADIX - 1);
         // Valid lanes form a prefix of the wave, so lane 0 is valid here.
         const u32 d0 = __shfl(d, 0, kWave);
         const u64 same = __ballot(valid[j] && d == d0);
         if (same == vmask) {
-          if (lane == 0) atomicAdd(&lh[p * kRadix + d0], u32(__popcll(vmask)));
+          if (lane == 0) atomicAdd(&lh[p * RADIX + d0], u32(__popcll(vmask)));
         } else if (valid[j]) {
-          atomicAdd(&lh[p * kRadix + d], 1u);
+          atomicAdd(&lh[p * RADIX + d], 1u);
         }
       }
     }
@@ -401,22 +500,31 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
                     (unsigned long long)n);
   }
   if (c >= nchunks) return;
-  for (int i = threadIdx.x; i < NP * kRadix; i += kHistBlock) {
+  for (int i = threadIdx.x; i < NP * RADIX; i += kHistBlock) {
     const u32 v = lh[i];
-    const int p = i / kRadix, d = i % kRadix;
-    if (v) atomicAdd(&hist_in[(size_t(p) * kChunks + c) * kRadix + d], v);
+    const int p = i / RADIX, d = i % RADIX;
+    if (v) atomicAdd(&hist_in[(size_t(p) * kChunks + c) * RADIX + d], v);
   }
 }
 
 // Per-chunk counts of digit plan->first_run when it is 2 or above (keys whose
 // two lowest digits are constant); returns at once otherwise.
+template <int RB>
 __global__ __launch_bounds__(kHistBlock) void radix_histogram_first_kernel(
-    const u64* __restrict__ keys, u64 count, u64 chunk_elems, u32 nchunks, u32 per_chunk,
+    const u64* __restrict__ keys, const SortCtl* __restrict__ ctl, u32 tile,
     const SortPlan* __restrict__ plan, u32* __restrict__ hist_in) {
+  constexpr int RADIX = 1 << RB;
+  const u64 count = ctl->count;
+  if (count == 0) return;
   const u32 p = plan->first_run;
   if (p < 2) return;
-  __shared__ u32 lh[kRadix];
-  for (int i = threadIdx.x; i < kRadix; i += kHistBlock) lh[i] = 0;
+  const SortGeom geo = sort_geom(count, tile);
+  const u32 per_chunk = hist_per_chunk(geo, gridDim.x);
+  if (blockIdx.x >= per_chunk * geo.nchunks) return;
+  const u32 nchunks = geo.nchunks;
+  const u64 chunk_elems = u64(tile) << geo.ct_log2;
+  __shared__ u32 lh[RADIX];
+  for (int i = threadIdx.x; i < RADIX; i += kHistBlock) lh[i] = 0;
   __syncthreads();
   const u32 c = blockIdx.x / per_chunk;
   const u32 g = blockIdx.x % per_chunk;
@@ -428,64 +536,83 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_first_kernel(
 #pragma unroll
     for (int j = 0; j < kHistItems; ++j) {
       const u64 e = base + u64(j) * kHistBlock + threadIdx.x;
-      if (e < ce) atomicAdd(&lh[u32(keys[e] >> (p * kRadixBits)) & (kRadix - 1)], 1u);
+      if (e < ce) atomicAdd(&lh[u32(keys[e] >> (p * RB)) & (RADIX - 1)], 1u);
     }
   }
   __syncthreads();
   if (c >= nchunks) return;
-  for (int d = threadIdx.x; d < kRadix; d += kHistBlock) {
+  for (int d = threadIdx.x; d < RADIX; d += kHistBlock) {
     const u32 v = lh[d];
-    if (v) atomicAdd(&hist_in[(size_t(p) * kChunks + c) * kRadix + d], v);
+    if (v) atomicAdd(&hist_in[(size_t(p) * kChunks + c) * RADIX + d], v);
   }
 }
 
-namespace {
-
-// Blocks of a histogram launch: a few per chunk, at most about 2048 in all.
-u64 hist_blocks_per_chunk(const SortGeom& geo, u64 chunk_elems) {
-  u64 per = ceil_div(chunk_elems, u64(kHistBlock) * kHistItems * 4);
-  const u64 cap = ceil_div(2048, geo.nchunks);
+// Workgroups of a histogram launch for at most `bound` pairs: a few per chunk,
+// at most kHistMaxBlocks in all (and at least kChunks, so that every chunk of
+// a smaller count has one).
+u32 radix_histogram_grid(u64 bound, u32 tile) {
+  const SortGeom geo = sort_geom(bound, tile);
+  const u64 chunk_elems = u64(tile) << geo.ct_log2;
+  u64 per = ceil_div(chunk_elems, kHistBlockElems);
+  const u64 cap = kHistMaxBlocks / geo.nchunks;
   if (per > cap) per = cap;
   if (per < 1) per = 1;
-  return per;
+  u64 grid = per * geo.nchunks;
+  if (grid < u64(kChunks)) grid = kChunks;
+  return u32(grid);
 }
 
-}  // namespace
-
-void launch_radix_histogram(const u64* keys, const SortGeom& geo, u32* hist_in, u64* counters,
-                            hipStream_t s) {
-  if (geo.count == 0) return;
-  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
-  const u64 per = hist_blocks_per_chunk(geo, chunk_elems);
-  hipLaunchKernelGGL(radix_histogram_kernel, dim3(u32(per * geo.nchunks)), dim3(kHistBlock), 0, s,
-                     keys, geo.count, chunk_elems, geo.nchunks, u32(per), hist_in, counters);
+void launch_radix_histogram(const u64* keys, const SortCtl* ctl, u32 tile, u32 grid,
+                            u32* hist_in, u64* counters, int rb, hipStream_t s) {
+#define SA_HIST(RB)                                                                          \
+  hipLaunchKernelGGL(radix_histogram_kernel<RB>, dim3(grid), dim3(kHistBlock), 0, s, keys, ctl, \
+                     tile, hist_in, counters)
+  switch (rb) {
+    case 6: SA_HIST(6); break;
+    case 7: SA_HIST(7); break;
+    case 9: SA_HIST(9); break;
+    default: SA_HIST(8); break;
+  }
+#undef SA_HIST
 }
 
-void launch_radix_histogram_first(const u64* keys, const SortGeom& geo, const SortPlan* plan,
-                                  u32* hist_in, hipStream_t s) {
-  if (geo.count == 0) return;
-  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
-  const u64 per = hist_blocks_per_chunk(geo, chunk_elems);
-  hipLaunchKernelGGL(radix_histogram_first_kernel, dim3(u32(per * geo.nchunks)), dim3(kHistBlock),
-                     0, s, keys, geo.count, chunk_elems, geo.nchunks, u32(per), plan, hist_in);
+void launch_radix_histogram_first(const u64* keys, const SortCtl* ctl, u32 tile, u32 grid,
+                                  const SortPlan* plan, u32* hist_in, int rb, hipStream_t s) {
+#define SA_HIST1(RB)                                                                        \
+  hipLaunchKernelGGL(radix_histogram_first_kernel<RB>, dim3(grid), dim3(kHistBlock), 0, s, keys, \
+                     ctl, tile, plan, hist_in)
+  switch (rb) {
+    case 6: SA_HIST1(6); break;
+    case 7: SA_HIST1(7); break;
+    case 9: SA_HIST1(9); break;
+    default: SA_HIST1(8); break;
+  }
+#undef SA_HIST1
 }
 
 // The sort plan: which digits vary (the others are skipped), which buffer each
 // pass reads, where values are generated and where the output ends.
-__global__ void radix_plan_kernel(const u64* __restrict__ counters, int npass, int vals_present,
-                                  SortPlan* __restrict__ plan) {
+__global__ void radix_plan_kernel(const SortCtl* __restrict__ ctl, const u64* __restrict__ counters,
+                                  int npass, int vals_present, SortPlan* __restrict__ plan,
+                                  u32* __restrict__ plan_log, int log_row,
+                                  const RoundCtl* __restrict__ rc, int rb) {
   if (threadIdx.x != 0) return;
+  const u64 count = ctl->count;
+  if (ctl->dense) vals_present = 0;  // a dense round's values are the positions
   const u64 varying = counters[kCtrKeyOr] & counters[kCtrKeyNot];
   u32 run[kMaxPasses];
   u32 nrun = 0;
   for (int p = 0; p < kMaxPasses; ++p) {
-    run[p] = (p < npass && ((varying >> (p * kRadixBits)) & (kRadix - 1)) != 0) ? 1u : 0u;
+    // (p < npass keeps the shift below 64: the passes cover at most 64 bits.)
+    run[p] = (p < npass && ((varying >> (p * rb)) & ((u64(1) << rb) - 1)) != 0) ? 1u : 0u;
     nrun += run[p];
   }
-  if (nrun == 0) run[npass - 1] = 1;  // all keys equal: one stable copy pass
+  // All keys equal: one stable copy pass; nothing to sort: no pass at all.
+  if (nrun == 0 && count) run[npass - 1] = 1;
   u32 cur = 0;
   bool first = true;
   int prev = -1;
+  plan->first_run = 0;
   for (int p = 0; p < kMaxPasses; ++p) {
     plan->skip[p] = run[p] ? 0u : 1u;
     plan->src[p] = cur;
@@ -501,12 +628,23 @@ __global__ void radix_plan_kernel(const u64* __restrict__ counters, int npass, i
     }
   }
   plan->final_buf = cur;
+  if (!plan_log || count == 0) return;
+  const int row = log_row >= 0 ? log_row : int(rc->round);
+  if (row >= kMaxRounds + 1) return;
+  u32* f = plan_log + size_t(row) * kPlanLogWords;
+  for (int p = 0; p < kMaxPasses; ++p) {
+    f[p] = plan->skip[p];
+    f[kMaxPasses + p] = plan->src[p];
+    f[2 * kMaxPasses + p] = plan->iota[p];
+  }
+  f[3 * kMaxPasses] = cur;
 }
 
-void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPlan* plan,
+void launch_radix_plan(const SortCtl* ctl, const u64* counters, int npass, int vals_present,
+                       SortPlan* plan, u32* plan_log, int log_row, const RoundCtl* rc, int rb,
                        hipStream_t s) {
-  hipLaunchKernelGGL(radix_plan_kernel, dim3(1), dim3(kWave), 0, s, counters, npass,
-                     vals_present, plan);
+  hipLaunchKernelGGL(radix_plan_kernel, dim3(1), dim3(kWave), 0, s, ctl, counters, npass,
+                     vals_present, plan, plan_log, log_row, rc, rb);
 }
 
 // One stable counting sweep over digit `pass`, persistent: workgroup b works on
@@ -527,18 +665,19 @@ void launch_radix_plan(const u64* counters, int npass, int vals_present, SortPla
 // SIMD, two 512-thread workgroups per CU (the 256-thread table variant, which
 // LDS limits to three workgroups per CU anyway, to 168). TABLE selects how a
 // wave finds the lanes that hold the same digit (see the ranking below).
-template <int ITEMS, int BLOCK, bool TABLE>
+template <int ITEMS, int BLOCK, bool TABLE, int RB>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(
     ITEMS <= 8 ? ((TABLE && BLOCK == 256) ? 3 : 4) : 1)))
 void onesweep_pass_kernel(
     u64* __restrict__ keysA, u64* __restrict__ keysB, u32* __restrict__ valsA,
-    u32* __restrict__ valsB, u64 count, int pass, u32 ct_log2, u32 nchunks,
+    u32* __restrict__ valsB, const SortCtl* __restrict__ ctl, int pass,
     const SortPlan* __restrict__ plan, const u32* __restrict__ hist_in,
     u32* __restrict__ hist_run, u32* __restrict__ tickets, u64* __restrict__ status,
-    u64* __restrict__ counters, u32 gen) {
-  static_assert(BLOCK == kRadix || BLOCK == 2 * kRadix, "the first kRadix threads own a digit");
+    u64* __restrict__ counters) {
+  constexpr int RADIX = 1 << RB;
+  static_assert(BLOCK >= RADIX && RADIX >= kWave, "the first RADIX threads own a digit");
   constexpr int NW = BLOCK / kWave;
-  constexpr int DW = kRadix / kWave;  // waves that own digits
+  constexpr int DW = RADIX / kWave;  // waves that own digits
   constexpr int TILE = BLOCK * ITEMS;
   constexpr int kTileTz = __builtin_ctz(TILE);
   constexpr u32 kTileOdd = u32(TILE) >> kTileTz;
@@ -546,31 +685,37 @@ void onesweep_pass_kernel(
   // Per-wave digit counts, two waves per word (16 bits each: a wave ranks at
   // most 64 * ITEMS items and a tile holds at most 6144).
   static_assert(NW % 2 == 0 && TILE < 65536, "16-bit count halves");
-  __shared__ u32 s_cnt[NW / 2][kRadix];
+  __shared__ u32 s_cnt[NW / 2][RADIX];
   // With TABLE, per wave: the lanes of each digit (zero between uses).
-  __shared__ u64 s_match[TABLE ? NW : 1][kRadix];
+  __shared__ u64 s_match[TABLE ? NW : 1][RADIX];
   // Next-sweep counts per (output chunk, digit), two 16-bit halves per word.
-  constexpr int kNextWords = kChunks * kRadix / 2;
+  constexpr int kNextWords = kChunks * RADIX / 2;
   constexpr u32 kNextCheck = 32768;  // elements between overflow checks
   static_assert(TILE <= int(kNextCheck), "a tile fits between two checks");
   __shared__ u32 s_next[kNextWords];
-  __shared__ u32 s_start[kRadix];
-  __shared__ u64 s_base[kRadix];
+  __shared__ u32 s_start[RADIX];
+  __shared__ u64 s_base[RADIX];
   __shared__ u32 s_wsum[DW];
   __shared__ u64 s_tsum[DW];
   __shared__ u32 s_ticket;
   __shared__ u32 s_abort;
 
   if (plan->skip[pass]) return;
+  const u64 count = ctl->count;
+  if (count == 0) return;
+  const u32 gen = ctl->gen_base + u32(pass);
+  const SortGeom geo = sort_geom(count, u32(TILE));
+  const u32 ct_log2 = geo.ct_log2;
+  const u32 nchunks = geo.nchunks;
   const u32 src = plan->src[pass];
   const bool iota = plan->iota[pass] != 0;
   const u64* kin = src ? keysB : keysA;
   u64* kout = src ? keysA : keysB;
   const u32* vin = src ? valsB : valsA;
   u32* vout = src ? valsA : valsB;
-  const int shift = pass * kRadixBits;
+  const int shift = pass * RB;
   const int next = plan->next_run[pass];
-  const int nshift = next >= 0 ? next * kRadixBits : 0;
+  const int nshift = next >= 0 ? next * RB : 0;
 
   const int tid = threadIdx.x;
   const int lane = lane_id();
@@ -586,17 +731,17 @@ void onesweep_pass_kernel(
   // Where this chunk's run of each digit starts: the digit's global start (its
   // count over all chunks, scanned over the digits) plus its count in the
   // earlier chunks.
-  const bool digit_owner = tid < kRadix;  // thread tid owns digit tid
+  const bool digit_owner = tid < RADIX;  // thread tid owns digit tid
   u64 total = 0, below = 0, inc64 = 0, cbase = 0;
   if (digit_owner) {
     const u32* h = (u32(pass) == plan->first_run ? hist_in : hist_run) +
-                   size_t(pass) * kChunks * kRadix;
+                   size_t(pass) * kChunks * RADIX;
     // Eight chunk counts in flight at a time.
     for (int c0 = 0; c0 < kChunks; c0 += 8) {
       u32 part[8];
 #pragma unroll
       for (int c = 0; c < 8; ++c)
-        part[c] = u32(c0 + c) < nchunks ? h[(c0 + c) * kRadix + tid] : 0u;
+        part[c] = u32(c0 + c) < nchunks ? h[(c0 + c) * RADIX + tid] : 0u;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         total += part[c];
@@ -616,8 +761,8 @@ void onesweep_pass_kernel(
   }
   for (int i = tid; i < kNextWords; i += BLOCK) s_next[i] = 0;
   if (TABLE)
-    for (int i = tid; i < NW * kRadix; i += BLOCK) (&s_match[0][0])[i] = 0;
-  u32* next_hist = hist_run + size_t(next >= 0 ? next : 0) * kChunks * kRadix;
+    for (int i = tid; i < NW * RADIX; i += BLOCK) (&s_match[0][0])[i] = 0;
+  u32* next_hist = hist_run + size_t(next >= 0 ? next : 0) * kChunks * RADIX;
   u32 since_check = 0;  // elements counted into s_next since every half was < 32768
 
   for (;;) {
@@ -625,7 +770,7 @@ void onesweep_pass_kernel(
       s_ticket = atomicAdd(tickets + pass * kChunks + chunk, 1u);
       s_abort = 0;
     }
-    for (int i = tid; i < (NW / 2) * kRadix; i += BLOCK) (&s_cnt[0][0])[i] = 0;
+    for (int i = tid; i < (NW / 2) * RADIX; i += BLOCK) (&s_cnt[0][0])[i] = 0;
     if (next >= 0 && since_check + u32(TILE) > kNextCheck - 1) {
       // Every half is at most 32767 + since_check afterwards, and since_check
       // stays below 32768 until the next check: no half carries into the other.
@@ -678,7 +823,7 @@ void onesweep_pass_kernel(
 #pragma unroll
       for (int j = 0; j < ITEMS; ++j) {
         const u32 e = u32(j * kWave + lane);
-        // Missing items take digit 255: after every valid item.
+        // Missing items take the largest digit: after every valid item.
         key[j] = (e < wvalid) ? __builtin_nontemporal_load(kin_w + e) : ~u64(0);
       }
 #pragma unroll
@@ -699,7 +844,7 @@ void onesweep_pass_kernel(
     u32 packed[ITEMS];  // below | leader << 8
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const u32 d = digit_of(key[j], shift);
+      const u32 d = digit_at<RB>(key[j], shift);
       u64 peers;
       if constexpr (TABLE) {
         // Every lane ORs its bit into the wave's table entry of its digit,
@@ -717,7 +862,7 @@ void onesweep_pass_kernel(
         // the digits.
         u32 dlo = 0, dhi = 0;
 #pragma unroll
-        for (int b = 0; b < kRadixBits; ++b) {
+        for (int b = 0; b < RB; ++b) {
           u32 m = u32(int(d << (31 - b)) >> 31);  // bit b of d in every bit
           // Opaque to the optimiser, so that the ballot compares m itself
           // instead of shifting d once more.
@@ -752,7 +897,7 @@ void onesweep_pass_kernel(
         s_cnt[w2][tid] = lo | (hi << 16);
         tot = hi + (c >> 16);
       }
-      u64* my_status = status + tile * kRadix + tid;
+      u64* my_status = status + tile * RADIX + tid;
       store_status(my_status,
                    status_pack(gen, tile == c_first ? kFlagPrefix : kFlagAggregate, tot));
       // Exclusive scan of the tile totals over digits: tile-local run starts.
@@ -771,7 +916,7 @@ void onesweep_pass_kernel(
       // leaves the chunk.
       u64 excl = 0;
       if (tile > c_first)
-        excl = lookback(status + tid, kRadix, tile, tot, gen, false, counters, &s_abort);
+        excl = lookback(status + tid, RADIX, tile, tot, gen, false, counters, &s_abort);
       s_base[tid] = cbase + excl - u64(start);
     }
     __syncthreads();
@@ -780,7 +925,7 @@ void onesweep_pass_kernel(
     // offset in that run, its rank in the wave.
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
-      const u32 d = digit_of(key[j], shift);
+      const u32 d = digit_at<RB>(key[j], shift);
       rank[j] += s_start[d] + ((s_cnt[wave >> 1][d] >> half) & 0xFFFFu);
       s_buf[rank[j]] = key[j];
     }
@@ -790,25 +935,28 @@ void onesweep_pass_kernel(
     const u64 left = count - tile_base;
     const u32 valid = left < u64(TILE) ? u32(left) : u32(TILE);
     since_check += valid;
-    // Reordered position tid + i * BLOCK: its digit, kept for the value pass.
-    u32 qdig[(ITEMS + 3) / 4];
+    // Reordered position tid + i * BLOCK: its digit, kept for the value pass
+    // (QPW digits of QB bits per register).
+    constexpr int QB = RB <= 8 ? 8 : 16;
+    constexpr int QPW = 32 / QB;
+    u32 qdig[(ITEMS + QPW - 1) / QPW];
 #pragma unroll
-    for (int i = 0; i < (ITEMS + 3) / 4; ++i) qdig[i] = 0;
+    for (int i = 0; i < (ITEMS + QPW - 1) / QPW; ++i) qdig[i] = 0;
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) {
       const u32 q = u32(tid + i * BLOCK);
       if (q < valid) {
         const u64 k = s_buf[q];
-        const u32 d = digit_of(k, shift);
-        qdig[i / 4] |= d << (8 * (i % 4));
+        const u32 d = digit_at<RB>(k, shift);
+        qdig[i / QPW] |= d << (QB * (i % QPW));
         const u64 o = s_base[d] + q;
         if (o < count) {
           kout[o] = k;
           if (next >= 0) {
             // Output chunk o / (TILE << ct_log2), with TILE = kTileOdd << kTileTz:
             // a 32-bit division by the odd factor (o < 2^(32 + kTileTz)).
-            const u32 bin = ((u32(o >> kTileTz) / kTileOdd) >> ct_log2) * kRadix +
-                            digit_of(k, nshift);
+            const u32 bin = ((u32(o >> kTileTz) / kTileOdd) >> ct_log2) * RADIX +
+                            digit_at<RB>(k, nshift);
             atomicAdd(&s_next[bin >> 1], 1u << (16 * (bin & 1u)));
           }
         }
@@ -826,7 +974,7 @@ void onesweep_pass_kernel(
     for (int i = 0; i < ITEMS; ++i) {
       const u32 q = u32(tid + i * BLOCK);
       if (q < valid) {
-        const u32 d = (qdig[i / 4] >> (8 * (i % 4))) & 0xFFu;
+        const u32 d = (qdig[i / QPW] >> (QB * (i % QPW))) & ((1u << QB) - 1u);
         const u64 o = s_base[d] + q;
         if (o < count) {
           vout[o] = s_vals[q];
@@ -847,64 +995,71 @@ void onesweep_pass_kernel(
   }
 }
 
-void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortGeom& geo,
-                          int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
-                          u32* tickets, u64* status, u64* counters, u32 gen, int items,
-                          int block, bool table, u32 grid, hipStream_t s) {
-  if (geo.count == 0) return;
-#define SA_ONESWEEP(IT, BL)                                                                   \
-  do {                                                                                        \
-    if (table)                                                                                \
-      hipLaunchKernelGGL((onesweep_pass_kernel<IT, BL, true>), dim3(grid), dim3(BL), 0, s,    \
-                         keysA, keysB, valsA, valsB, geo.count, pass, geo.ct_log2,            \
-                         geo.nchunks, plan, hist_in, hist_run, tickets, status, counters, gen); \
-    else                                                                                      \
-      hipLaunchKernelGGL((onesweep_pass_kernel<IT, BL, false>), dim3(grid), dim3(BL), 0, s,   \
-                         keysA, keysB, valsA, valsB, geo.count, pass, geo.ct_log2,            \
-                         geo.nchunks, plan, hist_in, hist_run, tickets, status, counters, gen); \
-  } while (0)
-  if (block == 2 * kRadix) {
-    switch (items) {
-      case 4: SA_ONESWEEP(4, 512); break;
-      case 12: SA_ONESWEEP(12, 512); break;
-      default: SA_ONESWEEP(8, 512); break;
-    }
-  } else {
-    switch (items) {
-      case 8: SA_ONESWEEP(8, 256); break;
-      case 12: SA_ONESWEEP(12, 256); break;
-      case 20: SA_ONESWEEP(20, 256); break;
-      case 24: SA_ONESWEEP(24, 256); break;
-      default: SA_ONESWEEP(16, 256); break;
-    }
+bool onesweep_supported(int items, int block, bool table, int rb) {
+  if (rb == kRadixBits) {
+    if (block == 512) return items == 4 || items == 8 || items == 12;
+    return block == 256 && (items == 8 || items == 12 || items == 16 || items == 20 ||
+                            items == 24);
   }
-#undef SA_ONESWEEP
+  if (table || block != 512) return false;
+  if (rb == 6 || rb == 7) return items == 4 || items == 8 || items == 12;
+  if (rb == 9) return items == 8;  // 4096-pair tiles: the look-back statuses fit
+  return false;
 }
 
-int onesweep_wgs_per_cu(int items, int block, bool table) {
-  int n = 0;
-  hipError_t e = hipSuccess;
-#define SA_OCC(IT, BL)                                                                         \
-  e = table ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, onesweep_pass_kernel<IT, BL, true>, \
-                                                           BL, 0)                              \
-            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, onesweep_pass_kernel<IT, BL, false>, \
-                                                           BL, 0)
+// Calls F with the kernel instance of a supported shape (the default shape
+// otherwise).
+template <typename F>
+void with_onesweep(int items, int block, bool table, int rb, F&& f) {
+#define SA_K(IT, BL, TB, RB) onesweep_pass_kernel<IT, BL, TB, RB>
+  if (rb == 6 || rb == 7 || rb == 9) {
+    if (rb == 6) {
+      if (items == 4) f(SA_K(4, 512, false, 6), 512);
+      else if (items == 12) f(SA_K(12, 512, false, 6), 512);
+      else f(SA_K(8, 512, false, 6), 512);
+    } else if (rb == 7) {
+      if (items == 4) f(SA_K(4, 512, false, 7), 512);
+      else if (items == 12) f(SA_K(12, 512, false, 7), 512);
+      else f(SA_K(8, 512, false, 7), 512);
+    } else {
+      f(SA_K(8, 512, false, 9), 512);
+    }
+    return;
+  }
   if (block == 2 * kRadix) {
     switch (items) {
-      case 4: SA_OCC(4, 512); break;
-      case 12: SA_OCC(12, 512); break;
-      default: SA_OCC(8, 512); break;
+      case 4: table ? f(SA_K(4, 512, true, 8), 512) : f(SA_K(4, 512, false, 8), 512); break;
+      case 12: table ? f(SA_K(12, 512, true, 8), 512) : f(SA_K(12, 512, false, 8), 512); break;
+      default: table ? f(SA_K(8, 512, true, 8), 512) : f(SA_K(8, 512, false, 8), 512); break;
     }
   } else {
     switch (items) {
-      case 8: SA_OCC(8, 256); break;
-      case 12: SA_OCC(12, 256); break;
-      case 20: SA_OCC(20, 256); break;
-      case 24: SA_OCC(24, 256); break;
-      default: SA_OCC(16, 256); break;
+      case 8: table ? f(SA_K(8, 256, true, 8), 256) : f(SA_K(8, 256, false, 8), 256); break;
+      case 12: table ? f(SA_K(12, 256, true, 8), 256) : f(SA_K(12, 256, false, 8), 256); break;
+      case 20: table ? f(SA_K(20, 256, true, 8), 256) : f(SA_K(20, 256, false, 8), 256); break;
+      case 24: table ? f(SA_K(24, 256, true, 8), 256) : f(SA_K(24, 256, false, 8), 256); break;
+      default: table ? f(SA_K(16, 256, true, 8), 256) : f(SA_K(16, 256, false, 8), 256); break;
     }
   }
-#undef SA_OCC
+#undef SA_K
+}
+
+void launch_onesweep_pass(u64* keysA, u64* keysB, u32* valsA, u32* valsB, const SortCtl* ctl,
+                          int pass, const SortPlan* plan, const u32* hist_in, u32* hist_run,
+                          u32* tickets, u64* status, u64* counters, int items, int block,
+                          bool table, int rb, u32 grid, hipStream_t s) {
+  with_onesweep(items, block, table, rb, [&](auto kernel, int bl) {
+    hipLaunchKernelGGL(kernel, dim3(grid), dim3(bl), 0, s, keysA, keysB, valsA, valsB, ctl, pass,
+                       plan, hist_in, hist_run, tickets, status, counters);
+  });
+}
+
+int onesweep_wgs_per_cu(int items, int block, bool table, int rb) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+  with_onesweep(items, block, table, rb, [&](auto kernel, int bl) {
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, bl, 0);
+  });
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -985,14 +1140,14 @@ __device__ u64 run_start_wave(const u64* __restrict__ keys, u64 p, int sh, u64 x
 __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
-    const SortPlan* __restrict__ plan, const RerankArgs a, u32* __restrict__ isa,
-    u32* __restrict__ sa_out, u32* __restrict__ act_idx, u64* __restrict__ act_ti,
-    u32* __restrict__ act_rank, u64* __restrict__ counters) {
+    const SortPlan* __restrict__ plan, const RerankArgs a, const SortCtl* __restrict__ ctl,
+    u32* __restrict__ isa, u32* __restrict__ sa_out, u32* __restrict__ act_idx,
+    u64* __restrict__ act_ti, u32* __restrict__ act_rank, u64* __restrict__ counters) {
   constexpr int NW = kRerankBlock / kWave;
   constexpr int R = kRerankRows;
   constexpr int T = kRerankTile;
   static_assert(R <= 16, "flag bits of a lane: heads in 0..15, uniques in 16..31");
-  const u64 count = a.count;
+  const u64 count = ctl->count;
   const int mode = a.mode;
   __shared__ u32 s_wh[NW], s_wg[NW], s_ws[NW];
   __shared__ u64 s_prefix[3];
@@ -1005,10 +1160,11 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
-  const u64 tile = blockIdx.x;
+  const u64 lt_mask = (u64(1) << lane) - 1;
+  const u64 tiles = ceil_div(count, u64(T));
+  for (u64 tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
   const u64 base = tile * T;
   const u64 wbase = base + u64(wave) * (R * kWave);  // first element of the wave
-  const u64 lt_mask = (u64(1) << lane) - 1;
 
   // What precedes the tile: wave 0 finds the start of the run of keys equal to
   // keys[base] and wave 1 the start of its group (the last head and the last
@@ -1066,9 +1222,13 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const bool head = valid && (e == 0 || k[r] != kp);
     const bool grp = valid && (e == 0 || (gsh < 64 && (k[r] >> gsh) != (kp >> gsh)));
     const bool uniq = head && (e + 1 == count || kn != k[r]);
+    // Alone in its group: its name was unique before this round, so it was
+    // final already (only a dense round sorts such suffixes again).
+    const bool alone = grp && (e + 1 == count || (gsh < 64 && (kn >> gsh) != (k[r] >> gsh)));
     if (head) flags |= 1u << r;
     if (uniq) flags |= 1u << (16 + r);
     if (grp) gflags |= 1u << r;
+    if (alone) gflags |= 1u << (16 + r);
     const u64 hm = __ballot(head), gm = __ballot(grp), sm = __ballot(valid && !uniq);
     const u32 rowpos = u32((wave * R + r) * kWave);  // tile-local position of lane 0
     if (hm) wh = rowpos + u32(63 - __clzll((long long)hm)) + 1;
@@ -1147,7 +1307,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     if (scatter && (first_round || nr != r0)) isa[gb + v[r]] = u32(nr);
     if (isa_only) continue;
     if (uniq) {
-      sa_out[gb + nr - 1] = v[r];
+      if (first_round || !((gflags >> (16 + r)) & 1u)) sa_out[gb + nr - 1] = v[r];
     } else {
       if (act_ti)
         act_ti[out] = (t << 32) | v[r];
@@ -1159,16 +1319,16 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   if (bad)
     atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
              (unsigned long long)kErrBounds);
+  __syncthreads();  // the next tile reuses the LDS aggregates
+  }
 }
 
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            const u32* valsB, const SortPlan* plan, const RerankArgs& args,
-                           u32* isa, u32* sa_out, u32* act_idx, u64* act_ti, u32* act_rank,
-                           u64* counters, hipStream_t s) {
-  if (args.count == 0) return;
-  const u64 tiles = ceil_div(args.count, kRerankTile);
-  hipLaunchKernelGGL(rerank_compact_kernel, dim3(u32(tiles)), dim3(kRerankBlock), 0, s, keysA,
-                     keysB, valsA, valsB, plan, args, isa, sa_out, act_idx, act_ti, act_rank,
+                           const SortCtl* ctl, u32* isa, u32* sa_out, u32* act_idx, u64* act_ti,
+                           u32* act_rank, u64* counters, u32 grid, hipStream_t s) {
+  hipLaunchKernelGGL(rerank_compact_kernel, dim3(grid), dim3(kRerankBlock), 0, s, keysA, keysB,
+                     valsA, valsB, plan, args, ctl, isa, sa_out, act_idx, act_ti, act_rank,
                      counters);
 }
 
@@ -1255,44 +1415,50 @@ void launch_lazy_sample(const u64* keys0, u64 n, u64* sample, hipStream_t s) {
                      sample);
 }
 
+// A persistent grid: each workgroup stages the code table and the sample in
+// LDS once and strides over the active suffixes.
 __global__ __launch_bounds__(256) void pack_pairs_lazy_kernel(
-    const u32* __restrict__ act_idx, const u32* __restrict__ act_rank, u64 count, u64 n, u64 h,
-    int b, const u32* __restrict__ isa, const u8* __restrict__ text, const u16* __restrict__ code,
+    const u32* __restrict__ act_idx, const u32* __restrict__ act_rank,
+    const SortCtl* __restrict__ ctl, const RoundCtl* __restrict__ rc, u64 n, int b,
+    const u32* __restrict__ isa, const u8* __restrict__ text, const u16* __restrict__ code,
     const u64* __restrict__ counters, const u64* __restrict__ keys0,
     const u64* __restrict__ sample, const u32* __restrict__ live, u64* __restrict__ keys,
     u32* __restrict__ vals) {
   __shared__ u16 s_code[256];
   __shared__ u64 s_sample[kLazySamples];
+  const u64 count = ctl->count;
+  if (u64(blockIdx.x) * blockDim.x >= count) return;
   s_code[threadIdx.x] = code[threadIdx.x];
   for (u32 i = threadIdx.x; i < kLazySamples; i += 256) s_sample[i] = sample[i];
   __syncthreads();
-  u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (p >= count) return;
+  const u64 h = rc->h;
   const u32 w = u32(counters[kCtrCodeBits]);
   const u32 c = u32(counters[kCtrChars]);
-  const u32 i = act_idx[p];
-  const u32 r = act_rank[p];
-  const u64 j = u64(i) + h;
-  u32 r1 = 0;
-  if (j < n) {
-    // ISA[j] holds a name only for suffixes that survived round 0.
-    if ((live[j >> 5] >> (j & 31u)) & 1u)
-      r1 = isa[j];
-    else
-      r1 = round0_rank(j, text, n, s_code, w, c, keys0, s_sample);
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  for (u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += stride) {
+    const u32 i = act_idx[p];
+    const u32 r = act_rank[p];
+    const u64 j = u64(i) + h;
+    u32 r1 = 0;
+    if (j < n) {
+      // ISA[j] holds a name only for suffixes that survived round 0.
+      if ((live[j >> 5] >> (j & 31u)) & 1u)
+        r1 = isa[j];
+      else
+        r1 = round0_rank(j, text, n, s_code, w, c, keys0, s_sample);
+    }
+    keys[p] = (u64(r) << b) | u64(r1);
+    vals[p] = i;
   }
-  keys[p] = (u64(r) << b) | u64(r1);
-  vals[p] = i;
 }
 
-void launch_pack_pairs_lazy(const u32* act_idx, const u32* act_rank, u64 count, u64 n, u64 h,
-                            int b, const u32* isa, const u8* text, const u16* code,
-                            const u64* counters, const u64* keys0, const u64* sample,
-                            const u32* live, u64* keys, u32* vals, hipStream_t s) {
-  if (count == 0) return;
-  hipLaunchKernelGGL(pack_pairs_lazy_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0, s,
-                     act_idx, act_rank, count, n, h, b, isa, text, code, counters, keys0, sample,
-                     live, keys, vals);
+void launch_pack_pairs_lazy(const u32* act_idx, const u32* act_rank, const SortCtl* ctl,
+                            const RoundCtl* rc, u64 n, int b, const u32* isa, const u8* text,
+                            const u16* code, const u64* counters, const u64* keys0,
+                            const u64* sample, const u32* live, u64* keys, u32* vals, u32 grid,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(pack_pairs_lazy_kernel, dim3(grid), dim3(256), 0, s, act_idx, act_rank, ctl,
+                     rc, n, b, isa, text, code, counters, keys0, sample, live, keys, vals);
 }
 
 __global__ __launch_bounds__(256) void isa_complete_kernel(u32* __restrict__ isa, u64 n,
@@ -1408,7 +1574,7 @@ void launch_multi_presence(const u8* arena, TextTab tab, NewList nl, hipStream_t
 }
 
 __global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList nl, int idbits,
-                                                          int trim) {
+                                                          int trim, int rb) {
   __shared__ u32 wsum[4];
   const u32 t = nl.t[blockIdx.x];
   const int d = threadIdx.x;
@@ -1431,26 +1597,29 @@ __global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList n
     u32 c = avail / w;
     if (c < 1) c = 1;
     const u32 used = u32(idbits) + c * w;
-    if (trim && used % kRadixBits != 0 && used > kRadixBits) {
-      const u32 full = (used / kRadixBits) * kRadixBits;
+    const u32 urb = u32(rb);
+    if (trim && used % urb != 0 && used > urb) {
+      const u32 full = (used / urb) * urb;
       if (full > u32(idbits)) {
         const u32 ct = (full - u32(idbits)) / w;
         if (ct >= 1) c = ct;
       }
     }
-    // A full 64-bit key costs an eighth sweep; drop characters to stay within
-    // seven digits while at least 12 remain (an alphabet of at most 7 symbols).
-    if (trim && u32(idbits) + c * w > 56 && 56 > u32(idbits)) {
-      const u32 ct = (56 - u32(idbits)) / w;
+    // A key that reaches the last digit of 64 bits costs one sweep more; drop
+    // characters to one digit fewer while at least 12 remain (an alphabet of
+    // at most 7 symbols).
+    const u32 fewer = u32(passes_for(64, rb) - 1) * urb;
+    if (trim && u32(idbits) + c * w > fewer && fewer > u32(idbits)) {
+      const u32 ct = (fewer - u32(idbits)) / w;
       if (ct >= 12) c = ct;
     }
     tab.wc[t] = w | (c << 16);
   }
 }
 
-void launch_multi_codes(TextTab tab, NewList nl, int idbits, int trim, hipStream_t s) {
+void launch_multi_codes(TextTab tab, NewList nl, int idbits, int trim, int rb, hipStream_t s) {
   if (nl.m == 0) return;
-  hipLaunchKernelGGL(multi_codes_kernel, dim3(nl.m), dim3(256), 0, s, tab, nl, idbits, trim);
+  hipLaunchKernelGGL(multi_codes_kernel, dim3(nl.m), dim3(256), 0, s, tab, nl, idbits, trim, rb);
 }
 
 __global__ __launch_bounds__(kPackBlock) void multi_pack0_kernel(const u8* __restrict__ arena,

@@ -160,18 +160,13 @@ bool num_field(const JVal& o, const char* k, double lo, double hi, double* out) 
 
 // Checks the knobs the way sa_ctx_set_tuning does.
 bool tuning_valid(const sa_tuning& t) {
-  const u32 it = t.sort_items;
-  if (t.sort_block == 512) {
-    if (it != 4 && it != 8 && it != 12) return false;
-  } else if (t.sort_block == 0 || t.sort_block == 256) {
-    if (it != 8 && it != 12 && it != 16 && it != 20 && it != 24) return false;
-  } else {
-    return false;
-  }
-  if (t.lazy_ratio < 3 || t.round0_full > 1 || t.sort_wgs_per_cu > 16 || t.sort_match > 1)
-    return false;
-  for (u32 r : t.reserved)
-    if (r != 0) return false;
+  const u32 rb = t.radix_bits ? t.radix_bits : u32(kRadixBits);
+  if (rb < u32(kRadixBitsMin) || rb > u32(kRadixBitsMax)) return false;
+  if (t.sort_match > 1) return false;
+  const int block = t.sort_block ? int(t.sort_block) : 256;
+  if (!onesweep_supported(int(t.sort_items), block, t.sort_match == 1, int(rb))) return false;
+  if (t.lazy_ratio < 3 || t.round0_full > 1 || t.sort_wgs_per_cu > 16) return false;
+  if (t.rounds_ahead > 64 || t.round_graphs > 1 || t.reserved != 0) return false;
   return true;
 }
 
@@ -183,6 +178,7 @@ sa_tuning default_tuning() {
   t.lazy_ratio = u32(kLazyRatioDefault);
   t.round0_full = 0;
   t.sort_wgs_per_cu = 0;
+  t.radix_bits = u32(kRadixBits);
   return t;
 }
 
@@ -230,6 +226,11 @@ sa_status tune_parse(const std::string& text, TuneTable& out) {
       if (!num_field(e, "sort_match", 0, 1, &v)) return SA_EINVAL;
       te.t.sort_match = u32(v);
     }
+    te.t.radix_bits = u32(kRadixBits);  // entries without the field predate the width choice
+    if (e.get("radix_bits")) {
+      if (!num_field(e, "radix_bits", kRadixBitsMin, kRadixBitsMax, &v)) return SA_EINVAL;
+      te.t.radix_bits = u32(v);
+    }
     if (!tuning_valid(te.t)) return SA_EINVAL;
     te.ms = num_field(e, "ms", 0, 1e12, &v) ? v : 0.0;
     out.entries.push_back(te);
@@ -259,6 +260,7 @@ std::string tune_format(const TuneTable& t) {
       << ", \"sort_items\": " << e.t.sort_items << ", \"sort_wgs_per_cu\": "
       << e.t.sort_wgs_per_cu << ", \"sort_block\": " << e.t.sort_block
       << ", \"sort_match\": " << e.t.sort_match
+      << ", \"radix_bits\": " << (e.t.radix_bits ? e.t.radix_bits : u32(kRadixBits))
       << ", \"lazy_ratio\": " << e.t.lazy_ratio
       << ", \"round0_full\": " << e.t.round0_full << ", \"ms\": " << ms << "}";
   }
@@ -319,6 +321,9 @@ void apply_tuning(sa_ctx* c, const sa_tuning& t) {
   c->round0_trim = t.round0_full ? 0 : 1;
   c->sort_wgs_per_cu = int(t.sort_wgs_per_cu);
   c->sort_match = int(t.sort_match);
+  c->rounds_ahead = t.rounds_ahead;
+  c->graphs = t.round_graphs == 0;
+  c->radix_bits = t.radix_bits ? int(t.radix_bits) : kRadixBits;
 }
 
 sa_tuning current_tuning(const sa_ctx* c) {
@@ -330,6 +335,9 @@ sa_tuning current_tuning(const sa_ctx* c) {
   t.round0_full = c->round0_trim ? 0u : 1u;
   t.sort_wgs_per_cu = u32(c->sort_wgs_per_cu);
   t.sort_match = u32(c->sort_match);
+  t.radix_bits = u32(c->radix_bits);
+  t.rounds_ahead = c->rounds_ahead;
+  t.round_graphs = c->graphs ? 0u : 1u;
   return t;
 }
 
@@ -434,10 +442,10 @@ sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets
     if (e != SA_OK) return e;
     if (log) {
       std::fprintf(stderr,
-                   "sa_tune: items %u block %u wgs/cu %u match %u round0_full %u lazy_ratio %u: "
-                   "%.3f ms\n",
-                   t.sort_items, t.sort_block, t.sort_wgs_per_cu, t.sort_match, t.round0_full,
-                   t.lazy_ratio, ms);
+                   "sa_tune: bits %u items %u block %u wgs/cu %u match %u round0_full %u "
+                   "lazy_ratio %u: %.3f ms\n",
+                   t.radix_bits, t.sort_items, t.sort_block, t.sort_wgs_per_cu, t.sort_match,
+                   t.round0_full, t.lazy_ratio, ms);
       std::fflush(stderr);
     }
     if (best_t == 0 || ms < best_t) {
@@ -461,14 +469,30 @@ sa_status sa_tune(sa_ctx* ctx, const uint8_t* d_texts, const uint64_t* h_offsets
       t.sort_items = sh.items;
       t.sort_block = sh.block;
       t.sort_wgs_per_cu = w;
-      if (w != 0 && int(w) == default_wgs_per_cu(int(sh.items), int(sh.block), false))
+      if (w != 0 && int(w) == default_wgs_per_cu(int(sh.items), int(sh.block), false, kRadixBits))
         continue;  // same as w = 0
       st = trial(t);
     }
   }
-  // Stage 2: digit matching of the sweep; stage 3: round-0 key width;
-  // stage 4: the lazy-ISA threshold.
-  if (st == SA_OK) {
+  // Stage 2: radix digit width (6, 7 and 9 bits run with 512-thread
+  // workgroups and ballot matching) at the default grid.
+  struct Width {
+    u32 rb, items;
+  };
+  const Width widths[] = {{6, 4}, {6, 8}, {6, 12}, {7, 4}, {7, 8}, {7, 12}, {9, 8}};
+  for (const Width& wd : widths) {
+    if (st != SA_OK) break;
+    sa_tuning t = best;
+    t.radix_bits = wd.rb;
+    t.sort_items = wd.items;
+    t.sort_block = 512;
+    t.sort_match = 0;
+    t.sort_wgs_per_cu = 0;
+    st = trial(t);
+  }
+  // Stage 3: digit matching of the sweep (8-bit digits); stage 4: round-0 key
+  // width; stage 5: the lazy-ISA threshold.
+  if (st == SA_OK && best.radix_bits == u32(kRadixBits)) {
     sa_tuning t = best;
     t.sort_match = 1;
     st = trial(t);

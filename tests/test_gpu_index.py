@@ -1,0 +1,158 @@
+"""GPU parity of the index structures built from a suffix array (the paper's
+conclusion: LCP array and text indexes after suffix sorting): LCP array, BWT
+of text$ and FM-index pattern intervals, each against the oracle's definition
+on the same seeded inputs, bit-exact."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def builder():
+    from paper_1610_03007_amd import SuffixArrayBuilder
+    assert torch.cuda.is_available()
+    b = SuffixArrayBuilder(0)
+    yield b
+    b.close()
+
+
+def on_gpu(builder, text):
+    d = torch.from_numpy(np.ascontiguousarray(text)).to("cuda:0")
+    sa = builder.build(d)
+    torch.cuda.synchronize()
+    return d, sa
+
+
+def check_all(builder, text, patterns=None, seed=0):
+    t = np.ascontiguousarray(text, dtype=np.uint8)
+    d, sa = on_gpu(builder, t)
+    sa_h = sa.cpu().numpy().view(np.uint32)
+    want_sa = oracle.sa(t, parallel=t.size > 65536)
+    assert np.array_equal(sa_h, want_sa)
+    lcp = builder.lcp(d, sa)
+    bw, dollar = builder.bwt(d, sa)
+    torch.cuda.synchronize()
+    assert np.array_equal(lcp.cpu().numpy().view(np.uint32), oracle.lcp(t, want_sa)), t.size
+    wb, wd = oracle.bwt(t, want_sa)
+    assert dollar == wd and np.array_equal(bw.cpu().numpy(), wb), t.size
+    if patterns is None:
+        rng = np.random.default_rng(seed)
+        tb = t.tobytes()
+        patterns = [b""]
+        for _ in range(200):
+            a = int(rng.integers(0, max(1, t.size)))
+            patterns.append(tb[a:a + int(rng.integers(1, 24))])
+        patterns += [bytes(rng.integers(0, 256, int(rng.integers(1, 6))).astype(np.uint8))
+                     for _ in range(40)]
+    fm = builder.fm_index(d, sa)
+    try:
+        got = fm.count(patterns).cpu().numpy()
+        info = fm.info()
+        assert info["n"] == t.size and info["dollar"] == wd
+    finally:
+        fm.close()
+    for q, p in enumerate(patterns):
+        assert tuple(int(x) for x in got[q]) == oracle.sa_interval(t, want_sa, p), (t.size, p)
+
+
+def test_banana(builder):
+    t = np.frombuffer(b"banana", np.uint8)
+    check_all(builder, t, [b"a", b"ana", b"b", b"nana", b"banana", b"bananas", b"x", b"", b"n"])
+    d, sa = on_gpu(builder, t)
+    assert builder.lcp(d, sa).cpu().tolist() == [0, 1, 3, 0, 0, 2]
+    bw, dollar = builder.bwt(d, sa)
+    assert bytes(bw.cpu().numpy()) == b"annbaa" and dollar == 4
+
+
+@pytest.mark.parametrize("sigma", [1, 2, 4, 96, 256])
+def test_random_small(builder, sigma):
+    rng = np.random.default_rng(500 + sigma)
+    for k in range(12):
+        n = int(rng.integers(1, 700))
+        check_all(builder, rng.integers(0, sigma, n).astype(np.uint8), seed=k)
+
+
+@pytest.mark.parametrize("kind,n", [("dna", 100003), ("markov", 1 << 20), ("binary", 70001),
+                                    ("bytes", 300007), ("repetitive", 0), ("dna", 1 << 22)])
+def test_tiles_and_stretches(builder, kind, n):
+    """Texts spanning many 512-position LCP stretches, 256-row occurrence
+    blocks and 4096-entry scan chunks, with ragged ends."""
+    rng = np.random.default_rng(n + len(kind))
+    if kind == "dna":
+        t = W.dna(n, seed=n)
+    elif kind == "markov":
+        t = W.markov3(n, chain_seed=7)
+    elif kind == "binary":
+        t = rng.integers(0, 2, n).astype(np.uint8)
+    elif kind == "bytes":
+        t = rng.integers(0, 256, n).astype(np.uint8)
+    else:
+        t = W.repetitive(copies=16, base_len=20011)
+    check_all(builder, t, seed=n)
+
+
+def test_closed_forms(builder):
+    n = 70000
+    a = np.full(n, 97, np.uint8)
+    d, sa = on_gpu(builder, a)
+    assert np.array_equal(builder.lcp(d, sa).cpu().numpy(), np.arange(n, dtype=np.int32))
+    bw, dollar = builder.bwt(d, sa)
+    assert dollar == n and bool((bw == 97).all())
+    fm = builder.fm_index(d, sa)
+    r = fm.count([b"a" * 10, b"a" * n, b"a" * (n + 1), b"b"]).cpu().tolist()
+    fm.close()
+    assert r == [[9, n], [n - 1, n], [n, n], [n, n]]
+    m = 3000
+    ab = np.frombuffer(b"ab" * m, np.uint8).copy()
+    d, sa = on_gpu(builder, ab)
+    want = [0] + [2 * k for k in range(1, m)] + [0] + [2 * k - 1 for k in range(1, m)]
+    assert builder.lcp(d, sa).cpu().tolist() == want
+
+
+def test_full_size_markov(builder):
+    """A 64 MiB Markov text: the whole BWT against its definition, LCP at
+    sampled positions by direct comparison, and 2000 FM queries."""
+    t = W.markov3(1 << 26, chain_seed=11)
+    d, sa = on_gpu(builder, t)
+    sa_h = sa.cpu().numpy().view(np.uint32)
+    assert oracle.check_sa(t, sa_h)[0] == 0
+    bw, dollar = builder.bwt(d, sa)
+    lcp = builder.lcp(d, sa).cpu().numpy().view(np.uint32)
+    wb, wd = oracle.bwt(t, sa_h)
+    assert dollar == wd and np.array_equal(bw.cpu().numpy(), wb)
+    rng = np.random.default_rng(3)
+    tb = t.tobytes()
+    for j in rng.integers(1, t.size, 3000):
+        a, b = int(sa_h[j - 1]), int(sa_h[j])
+        l = 0
+        while a + l < t.size and b + l < t.size and tb[a + l] == tb[b + l]:
+            l += 1
+        assert lcp[j] == l, j
+    pats = []
+    for _ in range(2000):
+        a = int(rng.integers(0, t.size))
+        pats.append(tb[a:a + int(rng.integers(1, 40))])
+    fm = builder.fm_index(d, sa)
+    got = fm.count(pats).cpu().numpy()
+    fm.close()
+    for q, p in enumerate(pats):
+        assert tuple(int(x) for x in got[q]) == oracle.sa_interval(t, sa_h, p), p
+
+
+def test_bad_suffix_array_is_an_error(builder):
+    from paper_1610_03007_amd import SAError
+    t = torch.from_numpy(np.frombuffer(b"abcabc", np.uint8).copy()).to("cuda:0")
+    bad = torch.tensor([5, 4, 3, 2, 1, 1], dtype=torch.int32, device="cuda:0")  # no 0
+    with pytest.raises(SAError):
+        builder.bwt(t, bad)
+    with pytest.raises(SAError):
+        builder.fm_index(t, bad)
+    oob = torch.tensor([5, 4, 3, 2, 1, 9], dtype=torch.int32, device="cuda:0")
+    with pytest.raises(SAError):
+        builder.lcp(t, oob)

@@ -397,3 +397,64 @@ def test_above_2_31(builder):
     status, where = oracle.check_sa(t, sa)
     assert status == 0, (status, where, info)
     sampled_direct_check(t, sa, samples=500)
+
+
+@pytest.mark.parametrize("rb,items", [(6, 4), (6, 8), (6, 12), (7, 4), (7, 8), (7, 12),
+                                      (9, 8)])
+def test_digit_widths(builder, rb, items):
+    """Every radix digit width sorts stably (pairs against numpy's stable sort,
+    keys of 1..64 bits) and builds the same SA as the oracle, single and batched."""
+    builder.set_tuning(radix_bits=rb, sort_items=items, sort_block=512, sort_match=0)
+    try:
+        rng = np.random.default_rng(rb * 100 + items)
+        for bits, count in ((64, 100003), (13, 70001), (62, 4096 * 9 + 5), (1, 777)):
+            keys = rng.integers(0, 2**63, count, dtype=np.uint64) * np.uint64(2) + \
+                rng.integers(0, 2, count, dtype=np.uint64)
+            if bits < 64:
+                keys %= np.uint64(1) << np.uint64(bits)
+            keys[::7] = keys[3]
+            vals = rng.integers(0, 2**31, count, dtype=np.uint32)
+            order = np.argsort(keys, kind="stable")
+            k_t, v_t = dev(keys.view(np.int64)), dev(vals.view(np.int32))
+            builder.radix_sort_pairs(k_t, v_t, bits)
+            torch.cuda.synchronize()
+            assert np.array_equal(k_t.cpu().numpy().view(np.uint64), keys[order]), bits
+            assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals[order]), bits
+        for t in (W.dna(200003, seed=rb), W.markov3(150001, chain_seed=rb),
+                  W.repetitive(copies=20, base_len=3001), np.full(9000, 65, np.uint8)):
+            assert_same(builder, t)
+            assert builder.last_info()["passes_run"][0] <= -(-64 // rb)
+        info = builder.last_info()
+        assert builder.tuning()["radix_bits"] == rb
+        texts = [W.dna(int(n), seed=int(n)) for n in rng.integers(1, 30000, 40)]
+        off = np.zeros(len(texts) + 1, dtype=np.uint64)
+        np.cumsum([t.size for t in texts], out=off[1:])
+        sa = builder.build_batch(dev(np.concatenate(texts)), off)
+        torch.cuda.synchronize()
+        sa = sa.cpu().numpy().view(np.uint32)
+        for k, t in enumerate(texts):
+            assert np.array_equal(sa[int(off[k]):int(off[k + 1])], oracle.sa(t)), k
+        del info
+    finally:
+        builder.auto_tuning()
+
+
+@pytest.mark.parametrize("rb,items", [(6, 8), (7, 12), (9, 8)])
+def test_digit_width_skewed_next_digit(builder, rb, items):
+    """2^25 keys whose next digit is almost always 0 at every width: the 16-bit
+    next-pass counts must move to the global histogram before they overflow."""
+    builder.set_tuning(radix_bits=rb, sort_items=items, sort_block=512, sort_match=0)
+    try:
+        rng = np.random.default_rng(rb)
+        count = 1 << 25
+        keys = rng.integers(0, 2, count, dtype=np.uint64)
+        rare = rng.random(count) < 1e-3
+        keys[rare] |= rng.integers(1, 1 << rb, int(rare.sum()), dtype=np.uint64) << np.uint64(rb)
+        vals = np.arange(count, dtype=np.uint32)
+        order = np.argsort(keys, kind="stable")
+        k_t, v_t = dev(keys.view(np.int64)), dev(vals.view(np.int32))
+        builder.radix_sort_pairs(k_t, v_t, 2 * rb)
+        torch.cuda.synchronize()
+        assert np.array_equal(v_t.cpu().numpy().view(np.uint32), vals[order])
+    finally:
+        builder.auto_tuning()

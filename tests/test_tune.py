@@ -28,13 +28,13 @@ def write(tmp_path, entries, fmt=FORMAT):
 
 
 def test_tuning_struct_layout():
-    """The binding's sa_tuning mirror has the header's eight 32-bit fields, in
+    """The binding's sa_tuning mirror has the header's ten 32-bit fields, in
     order (the library writes the whole struct)."""
     import ctypes
     names = [f[0] for f in _native.Tuning._fields_]
     assert names == ["sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu", "sort_block",
-                     "sort_match", "reserved"]
-    assert ctypes.sizeof(_native.Tuning) == 32
+                     "sort_match", "radix_bits", "rounds_ahead", "round_graphs", "reserved"]
+    assert ctypes.sizeof(_native.Tuning) == 40
     header = open(os.path.join(os.path.dirname(__file__), "..", "include", "sa.h")).read()
     body = header[header.index("typedef struct {\n  uint32_t sort_items;"):]
     body = body[:body.index("} sa_tuning;")]
@@ -82,7 +82,8 @@ def test_knobs_round_trip(tmp_path):
     found, t = _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)
     assert found
     assert t == {"sort_items": 12, "sort_wgs_per_cu": 6, "lazy_ratio": 64, "round0_full": 1,
-                 "sort_block": 256, "sort_match": 0}
+                 "sort_block": 256, "sort_match": 0, "radix_bits": 8, "rounds_ahead": 0,
+                 "round_graphs": 0}
     p = write(tmp_path, [entry(sort_items=8, sort_block=512, sort_match=1)])
     t = _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)[1]
     assert t["sort_block"] == 512 and t["sort_match"] == 1
@@ -103,7 +104,13 @@ def test_malformed_files_are_rejected(tmp_path, bad):
 @pytest.mark.parametrize("knob", [{"sort_items": 10}, {"lazy_ratio": 2}, {"round0_full": 2},
                                   {"sort_wgs_per_cu": 17}, {"log2n": 64}, {"mode": "serve"},
                                   {"sort_block": 384}, {"sort_block": 512, "sort_items": 16},
-                                  {"sort_items": 4}, {"sort_match": 2}])
+                                  {"sort_items": 4}, {"sort_match": 2},
+                                  {"radix_bits": 5}, {"radix_bits": 10},
+                                  {"radix_bits": 7, "sort_block": 256, "sort_items": 8},
+                                  {"radix_bits": 6, "sort_block": 512, "sort_items": 8,
+                                   "sort_match": 1},
+                                  {"radix_bits": 9, "sort_block": 512, "sort_items": 12},
+                                  {"radix_bits": 9, "sort_block": 512, "sort_items": 4}])
 def test_invalid_knobs_are_rejected(tmp_path, knob):
     p = write(tmp_path, [entry(**knob)])
     with pytest.raises(SAError):
@@ -132,7 +139,9 @@ def test_autotune_save_and_reuse(tmp_path):
         assert doc["format"] == FORMAT and len(doc["entries"]) == 1
         e = doc["entries"][0]
         assert e["mode"] == "single" and e["log2n"] == 18 and e["code_bits"] == 3
-        assert {k: e[k] for k in best} == best
+        # The cache holds the searched knobs; the launch policies are not tuned.
+        searched = {k: v for k, v in best.items() if k not in ("rounds_ahead", "round_graphs")}
+        assert {k: e[k] for k in searched} == searched
         # The tuner leaves automatic choice in force: the next build uses the entry.
         sa = b.build(d, sigma=4)
         torch.cuda.synchronize()
@@ -187,3 +196,12 @@ def test_autotune_batch_mode(tmp_path):
             assert np.array_equal(sa[int(off[t]):int(off[t + 1])], oracle.sa(text))
     finally:
         b.close()
+
+
+@pytest.mark.parametrize("rb,items", [(6, 4), (6, 12), (7, 8), (9, 8), (8, 12)])
+def test_digit_width_entries(tmp_path, rb, items):
+    """Entries carry the radix digit width; widths other than 8 bits take
+    512-thread sweeps of 4, 8 or 12 items (8 at 9 bits)."""
+    p = write(tmp_path, [entry(radix_bits=rb, sort_block=512, sort_items=items)])
+    found, t = _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)
+    assert found and t["radix_bits"] == rb and t["sort_items"] == items
