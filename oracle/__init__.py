@@ -10,6 +10,8 @@ compiles it with g++ on demand and wraps it with ctypes over numpy arrays:
 * :func:`sa` -- plain prefix doubling (paper Alg. 1 with the inverse-suffix-array
   pairing of Alg. 4), no discarding; 1-based names with 0 as the sentinel.
 * :func:`pd_names` -- the names after a given number of doubling sorts.
+* :func:`pa_names`, :func:`pa_sa` -- prefix a-tupling (a = 4: the paper's prefix
+  quadrupling): names of single characters, then sorts of a-tuples of names.
 * :func:`prefix_ranks` -- the closed form of the names for prefix length ``h``:
   1 + the number of suffixes whose padded length-``h`` prefix is smaller.
 * :func:`brute_sa` -- the definition: sort all suffixes lexicographically.
@@ -64,7 +66,10 @@ def configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_lcp.argtypes = [u8p, u64, u32p, u32p]
     lib.oracle_bwt.argtypes = [u8p, u64, u32p, u8p, u64p]
     lib.oracle_sa_interval.argtypes = [u8p, u64, u32p, u8p, u64, u64p, u64p]
-    for f in ("oracle_sa", "oracle_pd_names", "oracle_prefix_ranks",
+    lib.oracle_pa_names.argtypes = [u8p, u64, ctypes.c_uint32, u64, u32p, u64p]
+    lib.oracle_pa_sa.argtypes = [u8p, u64, ctypes.c_uint32, u32p]
+    for f in ("oracle_sa", "oracle_pd_names", "oracle_prefix_ranks", "oracle_pa_names",
+              "oracle_pa_sa",
               "oracle_brute_sa", "oracle_check_sa", "oracle_num_threads",
               "oracle_lcp", "oracle_bwt", "oracle_sa_interval"):
         getattr(lib, f).restype = ctypes.c_int
@@ -115,6 +120,30 @@ def pd_names(text, steps: int) -> tuple[np.ndarray, int]:
     if rc:
         raise ValueError("bad arguments")
     return out, int(h.value)
+
+
+def pa_names(text, a: int, steps: int) -> tuple[np.ndarray, int]:
+    """Names after at most ``steps`` sorts of a-tuples (prefix a-tupling; 0:
+    the names of single characters), and the prefix length they resolve
+    (a^steps, or the length at which every name became distinct)."""
+    t = _text(text)
+    out = np.empty(t.size, dtype=np.uint32)
+    h = ctypes.c_uint64(0)
+    rc = _lib().oracle_pa_names(_p(t, ctypes.c_uint8), t.size, a, steps,
+                                _p(out, ctypes.c_uint32), ctypes.byref(h))
+    if rc:
+        raise ValueError("bad arguments")
+    return out, int(h.value)
+
+
+def pa_sa(text, a: int) -> np.ndarray:
+    """Suffix array by prefix a-tupling (a = 4: prefix quadrupling)."""
+    t = _text(text)
+    out = np.empty(t.size, dtype=np.uint32)
+    rc = _lib().oracle_pa_sa(_p(t, ctypes.c_uint8), t.size, a, _p(out, ctypes.c_uint32))
+    if rc:
+        raise ValueError("bad arguments")
+    return out
 
 
 def prefix_ranks(text, h: int) -> np.ndarray:

@@ -143,6 +143,72 @@ int oracle_pd_names(const uint8_t* T, uint64_t n, uint64_t steps, uint32_t* name
   return 0;
 }
 
+// Prefix a-tupling (Section 2.1, "Prefix Quadrupling": a = 4; a = 2 is plain
+// doubling): the names start from single characters (prefix length 1), and each
+// sort orders the a-tuples (name[i], name[i+h], ..., name[i+(a-1)h]) with the
+// sentinel 0 past the end, renames them as in Alg. 2 and the max-PrefixSum,
+// and multiplies the resolved prefix length h by a. Runs at most `steps` tuple
+// sorts (no sort at all for 0: the names of single characters), stopping early
+// once every name is distinct, and leaves the names in `name`; *h_out = the
+// prefix length they resolve. Returns 0, or 1 for n >= 2^32 or a < 2.
+int oracle_pa_names(const uint8_t* T, uint64_t n, uint32_t a, uint64_t steps, uint32_t* name,
+                    uint64_t* h_out) {
+  if (n >= (uint64_t(1) << 32) || a < 2) return 1;
+  *h_out = 1;
+  if (n == 0) return 0;
+  // Names of single characters: 1 + the number of positions holding a smaller byte.
+  uint64_t below[257] = {0};
+  for (uint64_t i = 0; i < n; ++i) below[uint64_t(T[i]) + 1] += 1;
+  for (int c = 1; c <= 256; ++c) below[c] += below[c - 1];
+  uint64_t distinct = 0;
+  for (int c = 0; c < 256; ++c) distinct += below[c + 1] != below[c];
+  for (uint64_t i = 0; i < n; ++i) name[i] = static_cast<uint32_t>(below[T[i]] + 1);
+  uint64_t h = 1, done = 0;
+  std::vector<uint32_t> tup(n * uint64_t(a));
+  std::vector<uint32_t> idx(n);
+  while (distinct < n && done < steps) {
+    for (uint64_t i = 0; i < n; ++i)
+      for (uint32_t j = 0; j < a; ++j) {
+        const uint64_t q = i + uint64_t(j) * h;
+        tup[i * a + j] = q < n ? name[q] : 0;
+      }
+    std::iota(idx.begin(), idx.end(), 0u);
+    auto less = [&](uint32_t x, uint32_t y) {
+      return std::lexicographical_compare(&tup[uint64_t(x) * a], &tup[uint64_t(x) * a] + a,
+                                          &tup[uint64_t(y) * a], &tup[uint64_t(y) * a] + a);
+    };
+    auto same = [&](uint32_t x, uint32_t y) {
+      return std::equal(&tup[uint64_t(x) * a], &tup[uint64_t(x) * a] + a,
+                        &tup[uint64_t(y) * a]);
+    };
+    std::sort(idx.begin(), idx.end(), less);
+    uint64_t head = 0;
+    distinct = 0;
+    for (uint64_t p = 0; p < n; ++p) {
+      if (p == 0 || !same(idx[p - 1], idx[p])) {
+        head = p;
+        ++distinct;
+      }
+      name[idx[p]] = static_cast<uint32_t>(head + 1);
+    }
+    h *= a;
+    ++done;
+  }
+  *h_out = h;
+  return 0;
+}
+
+// Suffix array by prefix a-tupling: names until all are distinct, then
+// SA[name[i] - 1] = i.
+int oracle_pa_sa(const uint8_t* T, uint64_t n, uint32_t a, uint32_t* SA) {
+  if (n >= (uint64_t(1) << 32) || a < 2) return 1;
+  std::vector<uint32_t> name(n);
+  uint64_t h = 0;
+  oracle_pa_names(T, n, a, ~uint64_t(0), name.data(), &h);
+  for (uint64_t i = 0; i < n; ++i) SA[name[i] - 1] = static_cast<uint32_t>(i);
+  return 0;
+}
+
 // Closed form of the names for prefix length h: ranks[i] = 1 + #{ j :
 // pad_h(j) < pad_h(i) }, where pad_h(i) is T[i, i+h) cut at n (the sentinel
 // ending it). Computed by sorting positions with the padded-prefix comparison.

@@ -117,6 +117,22 @@ def pins_pass() -> bool:
                 bytes(rng.integers(0, 3, int(rng.integers(1, 4))).astype(np.uint8))
             if oracle.sa_interval(t, sa, pat) != py_interval(tb, pat):
                 return False
+    # Prefix a-tupling: after k sorts the names resolve prefix length a^k.
+    for a in (2, 3, 4):
+        for _ in range(12):
+            n = int(rng.integers(2, 90))
+            t = rng.integers(0, int(rng.choice([2, 3, 256])), n).astype(np.uint8)
+            tb = t.tobytes()
+            if oracle.pa_sa(t, a).tolist() != py_brute_sa(tb):
+                return False
+            for k in range(0, 4):
+                names, h = oracle.pa_names(t, a, k)
+                if h > a ** k or names.tolist() != py_prefix_ranks(tb, h):
+                    return False
+                if h == a ** k and k > 0 and len(set(py_prefix_ranks(tb, a ** (k - 1)))) == n:
+                    return False  # names were distinct already: no further sort runs
+    if oracle.pa_sa(b"aaaaaaaaaaaaaaaaaaaaaaaa", 4).tolist() != list(range(23, -1, -1)):
+        return False
     if oracle.lcp(b"banana", [5, 3, 1, 0, 4, 2]).tolist() != [0, 1, 3, 0, 0, 2]:
         return False
     bw, d = oracle.bwt(b"banana", [5, 3, 1, 0, 4, 2])

@@ -112,7 +112,7 @@ def test_batch_digit_match(builder, match):
     """Both sweep digit matches on multi-text keys (slot bits on top)."""
     rng = np.random.default_rng(40 + match)
     texts = mixed_texts(rng, 200, 5000)
-    builder.set_tuning(sort_match=match)
+    builder.set_tuning(sort_match=match, radix_bits=8, sort_items=8, sort_block=512)
     try:
         sa, off = run_batch(builder, texts)
         assert builder.tuning()["sort_match"] == match

@@ -181,7 +181,7 @@ def test_dna1m(builder):
     """n = 2^20 ACGT text (seed 0): bit-exact against the oracle."""
     t = W.dna(1 << 20, seed=0)
     assert_same(builder, t)  # whatever tuning the cache picks
-    builder.set_tuning(round0_full=0)
+    builder.set_tuning(round0_full=0, radix_bits=8, sort_items=8, sort_block=512)
     try:
         assert_same(builder, t)
         info = builder.last_info()
@@ -189,6 +189,9 @@ def test_dna1m(builder):
         builder.set_tuning(round0_full=1)
         assert_same(builder, t)
         assert builder.last_info()["chars0"] == 21  # 63 key bits
+        builder.set_tuning(round0_full=0, radix_bits=7)
+        assert_same(builder, t)
+        assert builder.last_info()["chars0"] == 21  # 63 bits are nine whole 7-bit digits
     finally:
         builder.auto_tuning()
 
@@ -327,7 +330,7 @@ def test_full_size(builder, kind):
 def test_sort_tile_variants(builder, items, block, match):
     """Every radix-sort tile shape, with either digit match, sorts stably and
     builds the same SA."""
-    builder.set_tuning(sort_items=items, sort_block=block, sort_match=match)
+    builder.set_tuning(sort_items=items, sort_block=block, sort_match=match, radix_bits=8)
     try:
         rng = np.random.default_rng(items)
         count = 100003
@@ -352,7 +355,7 @@ def test_radix_sort_skewed_next_digit(builder, items, block, match):
     always 0: each sweep workgroup counts far more than 65535 elements into
     one (output chunk, next digit) bin, so its 16-bit LDS counts must move to
     the global histogram before they overflow."""
-    builder.set_tuning(sort_items=items, sort_block=block, sort_match=match)
+    builder.set_tuning(sort_items=items, sort_block=block, sort_match=match, radix_bits=8)
     try:
         rng = np.random.default_rng(items * block)
         count = 1 << 26

@@ -205,6 +205,13 @@ MUTANTS = {
     "interval_open_end": ("if (cmp_prefix(T, n, SA[mid], P, m) <= 0)",
                           "if (cmp_prefix(T, n, SA[mid], P, m) < 0)"),
     "interval_short_suffix_larger": ("if (s + l >= n) return -1;", "if (s + l >= n) return 1;"),
+    "tuple_last_rank_dropped": ("for (uint32_t j = 0; j < a; ++j) {",
+                                "for (uint32_t j = 0; j + 1 < a; ++j) {"),
+    "tuple_offset_stride": ("const uint64_t q = i + uint64_t(j) * h;",
+                            "const uint64_t q = i + uint64_t(j) * (h > 1 ? h / 2 : 1);"),
+    "tuple_h_doubled": ("    h *= a;\n    ++done;", "    h *= 2;\n    ++done;"),
+    "tuple_char_names_zero": ("name[i] = static_cast<uint32_t>(below[T[i]] + 1);",
+                              "name[i] = static_cast<uint32_t>(below[T[i]]);"),
     "brute_signed": ("return std::lexicographical_compare(T + a, T + n, T + b, T + n);",
                      "return std::lexicographical_compare((const signed char*)T + a, "
                      "(const signed char*)T + n, (const signed char*)T + b, "

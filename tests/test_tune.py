@@ -153,7 +153,7 @@ def test_autotune_save_and_reuse(tmp_path):
     b2 = SuffixArrayBuilder(0, tune_cache=path)
     try:
         other = 8 if best["sort_items"] != 8 else 12
-        b2.set_tuning(sort_items=other)
+        b2.set_tuning(sort_items=other, sort_block=512, radix_bits=8)
         sa = b2.build(d)
         torch.cuda.synchronize()
         assert b2.tuning_source() == "explicit" and b2.tuning()["sort_items"] == other
