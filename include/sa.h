@@ -217,7 +217,11 @@ typedef struct {
   uint32_t round_graphs; /* 0 (default): a later round whose launch arguments repeat is
                             captured once as a HIP graph and replayed; 1: every kernel is
                             launched directly. Tracing always launches directly. */
-  uint32_t reserved;     /* must be zero */
+  uint32_t prefix_mult;  /* names resolve prefix lengths multiplied per later round by: 0 or 2
+                            (default) = prefix doubling, rank pairs; 4 = prefix quadrupling
+                            (Section 2.1): rank quadruples sorted as two 2b-bit words, half
+                            the rounds, always with the eager ISA. sa_build and
+                            sa_build_rounds only; batches and the server double. */
 } sa_tuning;
 /* Sets an explicit tuning, used by every later build of the context. t = NULL
  * goes back to automatic choice: the cache entry for each input, else the

@@ -128,8 +128,15 @@ struct RoundCtl {
   u64 active[kMaxRounds];   // suffixes sorted in round k (k >= 1)
 };
 // Plan log: the flags of the sort of round k (kPlanLogWords words per round):
-// skip[kMaxPasses] | src[kMaxPasses] | iota[kMaxPasses] | final buffer.
+// skip[kMaxPasses] | src[kMaxPasses] | iota[kMaxPasses] | final buffer. Row
+// k + kPlanRowSecond holds the second sort of a quadrupling round k (the high
+// word of its two-word keys).
 constexpr int kPlanLogWords = 3 * kMaxPasses + 1;
+constexpr int kPlanRowSecond = kMaxRounds + 1;
+constexpr int kPlanLogRows = 2 * kPlanRowSecond;
+// log_row values that name a row through the round index on the device.
+constexpr int kLogRowRound = -1;         // row rc->round
+constexpr int kLogRowRoundSecond = -2;   // row rc->round + kPlanRowSecond
 
 // Workgroup and tile shapes.
 constexpr int kSortBlock = 256;          // the smaller sweep workgroup (one thread per digit)

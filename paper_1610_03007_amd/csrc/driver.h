@@ -80,7 +80,7 @@ struct sa_ctx {
   u32* tickets = nullptr;   // [kMaxPasses][kChunks] tile tickets
   u64* counters = nullptr;
   RoundCtl* rc = nullptr;   // rounds run from the device (follows the counters)
-  u32* plan_log = nullptr;  // [kMaxRounds + 1][kPlanLogWords] (follows rc)
+  u32* plan_log = nullptr;  // [kPlanLogRows][kPlanLogWords] (follows rc)
   SortCtl* ctl = nullptr;
   SortPlan* plan = nullptr;
   u32* present = nullptr;
@@ -90,7 +90,7 @@ struct sa_ctx {
   void* h_mirror = nullptr;
   u64* h_counters = nullptr;
   RoundCtl* h_rc = nullptr;
-  u32* h_plans = nullptr;  // [SA_MAX_ROUNDS + 1][kPlanLogWords]
+  u32* h_plans = nullptr;  // [kPlanLogRows][kPlanLogWords]
   u32 gen = 1;             // upper bound of ctl->gen_next (look-back generations)
   // Later rounds run ahead of the host: at most this many per readback
   // (0 = adaptive, doubling from 1), replayed from captured graphs unless
@@ -108,6 +108,7 @@ struct sa_ctx {
   int sort_wgs_per_cu = 0;             // persistent sweep workgroups per CU (0 = by tile size)
   int sort_match = 0;                  // sweep digit matching: 0 ballots, 1 LDS table
   int radix_bits = kRadixBits;         // radix-sort digit width
+  int prefix_mult = 2;                 // 2: prefix doubling; 4: prefix quadrupling (sa_build)
   int num_cus = 256;
   u64 lazy_ratio = kLazyRatioDefault;
   int round0_trim = 1;  // round-0 keys fill whole radix digits
@@ -150,7 +151,7 @@ constexpr size_t kClearWords = 2 * kChunkHistWords + kTicketWords;  // cleared b
 constexpr size_t kSmallCounters = size_t(kCtrCount) * sizeof(u64);
 constexpr size_t kSmallRoundCtl = sizeof(RoundCtl);
 constexpr int kPlanFlagWords = kPlanLogWords;  // skip, src, iota, final_buf
-constexpr size_t kSmallPlanLog = (size_t(kMaxRounds + 1) * kPlanFlagWords * sizeof(u32) + 255) /
+constexpr size_t kSmallPlanLog = (size_t(kPlanLogRows) * kPlanFlagWords * sizeof(u32) + 255) /
                                  256 * 256;
 constexpr size_t kMirrorBytes = kSmallCounters + kSmallRoundCtl + kSmallPlanLog;
 constexpr size_t kSmallCtl = 256;
@@ -237,7 +238,7 @@ inline int npass_for(const sa_ctx* c, int bits) { return passes_for(bits, c->rad
 // and the sweeps. `bound` >= the count sizes the launch grids. With
 // reserve == false the caller has reserved the generations already.
 void begin_sort(sa_ctx* c, u64 bound, const u64* dev_count, RoundCtl* rc, int npass, bool reserve,
-                hipStream_t s, u64 dense_n = 0);
+                hipStream_t s, u64 dense_n = 0, int log2a = 1);
 void sort_passes(sa_ctx* c, const Bufs& bf, u64 bound, int npass, int vals_present, int log_row,
                  u64 trace_count, hipStream_t s);
 // A sort of `count` pairs known on the host.

@@ -29,7 +29,6 @@ void free_workspace(sa_ctx* c) {
   (void)hipFree(c->isa);
   (void)hipFree(c->live);
   (void)hipFree(c->act_idx);
-  (void)hipFree(c->act_rank);
   (void)hipFree(c->status);
   (void)hipFree(c->act_ti);
   c->act_ti = nullptr;
@@ -45,13 +44,16 @@ sa_status ensure_workspace(sa_ctx* c, u64 n) {
   free_workspace(c);
   u64 cap = std::max<u64>(n, 1 << 16);
   bool ok = dev_alloc(&c->keysA, cap) && dev_alloc(&c->keysB, cap) && dev_alloc(&c->valsA, cap) &&
-            dev_alloc(&c->valsB, cap) && dev_alloc(&c->isa, cap) && dev_alloc(&c->act_idx, cap) &&
+            dev_alloc(&c->valsB, cap) && dev_alloc(&c->isa, cap) && dev_alloc(&c->act_idx, 2 * cap) &&
             dev_alloc(&c->live, ceil_div(cap, 32)) &&
-            dev_alloc(&c->act_rank, cap) && dev_alloc(&c->status, sort_status_words(cap));
+            dev_alloc(&c->status, sort_status_words(cap));
   if (!ok) {
     free_workspace(c);
     return SA_ENOMEM;
   }
+  // The active list's ranks follow its positions in the same allocation, so
+  // that a quadrupling round can use both as one u64 array.
+  c->act_rank = c->act_idx + cap;
   // The status array starts cleared; generations then keep it valid without
   // further clearing.
   if (hipMemset(c->status, 0, sort_status_words(cap) * sizeof(u64)) != hipSuccess ||
@@ -164,12 +166,12 @@ int default_wgs_per_cu(int items, int block, bool table, int rb) {
 }
 
 void begin_sort(sa_ctx* c, u64 bound, const u64* dev_count, RoundCtl* rc, int npass, bool reserve,
-                hipStream_t s, u64 dense_n) {
+                hipStream_t s, u64 dense_n, int log2a) {
   if (reserve) reserve_gens(c, u32(npass), s);
   Tracer t(c, s, SA_KERNEL_OTHER, 0);
   static_assert(kCtrSortTiles < kCtrActive && kCtrKeyOr < kCtrActive && kCtrKeyNot < kCtrActive,
                 "sort_begin clears the sort's counters");
-  launch_sort_begin(c->ctl, rc, bound, dev_count, npass, dense_n, c->hist_in, kClearWords,
+  launch_sort_begin(c->ctl, rc, bound, dev_count, npass, dense_n, log2a, c->hist_in, kClearWords,
                     c->counters, s);
 }
 
@@ -274,6 +276,7 @@ struct LaterRound {
   u64 dense_n;  // n when dense rounds are allowed (the ISA holds every name), else 0
   int b, npass;
   bool lazy;
+  bool quad;    // prefix quadrupling: rank quadruples, two sorts per round (needs the eager ISA)
   Bufs bufs;
   const u8* text;
   const u64* keys0;
@@ -284,9 +287,54 @@ struct LaterRound {
 // survivor count, read on the device; with none left every kernel returns at
 // once. log_row: the plan-log row (the round index), or -1 to take it from the
 // device. trace_count: the count, when the host knows it (tracing).
+// A quadrupling round (Section 2.1, prefix quadrupling): the rank quadruple
+// (r0, r1, r2, r3) is sorted as two words, the low one first (see
+// launch_pack_quad_lo), and renamed with the low word's run names as ties.
+// pk (u64 per element) spans the active-list arrays, which the round reads
+// only before it is written and writes only after it is consumed.
+void enqueue_quad_round(sa_ctx* c, const LaterRound& L, bool reserve, int log_row,
+                        u64 trace_count, bool trace_dense, hipStream_t s) {
+  u64* pk = reinterpret_cast<u64*>(c->act_idx);
+  const u32 grid = stream_grid(c, L.bound, 256);
+  begin_sort(c, L.bound, c->counters + kCtrActive, c->rc, L.npass, reserve, s, L.dense_n, 2);
+  {
+    // Two names in (gathered unless dense), the low key and the position out.
+    Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(trace_count) * (trace_dense ? 16.0 : 20.0));
+    launch_pack_quad_lo(c->act_idx, c->ctl, c->rc, L.n, L.b, c->isa, L.bufs.kA, L.bufs.vA, grid,
+                        s);
+  }
+  sort_passes(c, L.bufs, L.bound, L.npass, 1, log_row, trace_count, s);
+  {
+    RerankArgs a = single_args(L.bound, L.n, 0, kRerankPairOut);
+    a.pair_out = pk;
+    run_rerank(c, L.bufs, a, L.d_sa, L.bound, trace_count, s);
+  }
+  {
+    // Position in; two gathered names in, the high key out.
+    Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(trace_count) * 24.0);
+    launch_pack_quad_hi(pk, c->ctl, c->rc, L.n, L.b, c->isa, L.bufs.kA, c->counters, grid, s);
+  }
+  // The high-word sort: the same count, values generated (the low-sorted index).
+  begin_sort(c, L.bound, &c->ctl->count, nullptr, L.npass, reserve, s, 0, 1);
+  sort_passes(c, L.bufs, L.bound, L.npass, 0,
+              log_row >= 0 ? log_row + kPlanRowSecond : kLogRowRoundSecond, trace_count, s);
+  {
+    // Index in and in place out; a gathered 8-byte pair; the tie word out.
+    Tracer t(c, s, SA_KERNEL_OTHER, double(trace_count) * 20.0);
+    launch_quad_permute(c->ctl, c->plan, pk, L.bufs.vA, L.bufs.vB, c->counters, grid, s);
+  }
+  RerankArgs a = single_args(L.bound, L.n, L.b, kRerankScatterIsa);
+  a.tie = 1;
+  run_rerank(c, L.bufs, a, L.d_sa, L.bound, trace_count, s);
+}
+
 void enqueue_later_round(sa_ctx* c, const LaterRound& L, bool reserve, int log_row,
                          u64 trace_count, bool trace_dense, hipStream_t s) {
-  begin_sort(c, L.bound, c->counters + kCtrActive, c->rc, L.npass, reserve, s, L.dense_n);
+  if (L.quad) {
+    enqueue_quad_round(c, L, reserve, log_row, trace_count, trace_dense, s);
+    return;
+  }
+  begin_sort(c, L.bound, c->counters + kCtrActive, c->rc, L.npass, reserve, s, L.dense_n, 1);
   {
     // A dense round reads two names and writes a key per suffix (16 bytes);
     // otherwise index, rank and the gathered name in, key and value out.
@@ -315,7 +363,8 @@ GraphKey later_key(const sa_ctx* c, const LaterRound& L) {
   std::memcpy(k.ptr, p, sizeof(p));
   const u32 knobs[10] = {u32(L.b),           u32(L.npass),           L.lazy ? 1u : 0u,
                          u32(c->sort_items), u32(c->sort_block),     u32(c->sort_match),
-                         u32(c->sort_wgs_per_cu), u32(c->num_cus),   u32(c->radix_bits), 0u};
+                         u32(c->sort_wgs_per_cu), u32(c->num_cus),   u32(c->radix_bits),
+                         L.quad ? 1u : 0u};
   std::memcpy(k.knobs, knobs, sizeof(knobs));
   return k;
 }
@@ -428,8 +477,13 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   // Later-round buffers are carved at 256-byte boundaries (vector accesses).
   const u64 a1 = (std::max<u64>(active, 1) + 63) / 64 * 64;
   const bool fits = a1 * 24 <= n * 8;
+  // Quadrupling reads the names of positions i .. i + 3h from the ISA
+  // directly, so it takes the eager form.
+  const bool quad = c->prefix_mult == 4;
   bool lazy = false;
-  if (c->isa_mode == SA_ISA_LAZY)
+  if (quad)
+    lazy = false;
+  else if (c->isa_mode == SA_ISA_LAZY)
     lazy = fits;
   else if (c->isa_mode == SA_ISA_AUTO)
     lazy = fits && active * c->lazy_ratio <= n;
@@ -455,6 +509,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
   L.b = bits_of(n);  // ranks and second ranks are <= n
   L.npass = npass_for(c, 2 * L.b);
   L.lazy = lazy;
+  L.quad = quad;
   L.bufs = full;
   if (lazy) {
     L.bufs.kA = spare;
@@ -481,7 +536,7 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
     if (todo == 0) return SA_EDEVICE;  // cannot happen for n < 2^32
     hipGraphExec_t exec = use_graphs ? later_graph(c, L) : nullptr;
     if (exec) {
-      reserve_gens(c, u32(L.npass) * todo, s);
+      reserve_gens(c, u32(L.npass) * todo * (quad ? 2u : 1u), s);
       for (u32 r = 0; r < todo; ++r)
         if (hipGraphLaunch(exec, s) != hipSuccess) return SA_EDEVICE;
       c->graph_launches += todo;
@@ -500,12 +555,13 @@ sa_status build_rounds(sa_ctx* c, const u8* text, u64 n, u32 max_rounds, u32* d_
     info.dense_rounds = c->h_rc->dense;
     for (u32 k = done + 1; k <= now; ++k) {
       info.active[k] = c->h_rc->active[k];
-      info.key_bits[k] = u32(2 * L.b);
-      info.passes_run[k] = passes_run(c, int(k), L.npass);
+      info.key_bits[k] = u32((quad ? 4 : 2) * L.b);
+      info.passes_run[k] = passes_run(c, int(k), L.npass) +
+                           (quad ? passes_run(c, int(k) + kPlanRowSecond, L.npass) : 0u);
     }
     done = now;
     info.rounds = 1 + done;
-    info.prefix_len = chars0 << done;
+    info.prefix_len = chars0 << ((quad ? 2 : 1) * done);
     active = c->h_counters[kCtrActive];
     if (!c->rounds_ahead) ahead = std::min<u32>(2 * ahead, 16);
   }
@@ -591,6 +647,8 @@ constexpr ScratchLayout scratch_layout() {
   return L;
 }
 constexpr ScratchLayout kScratch = scratch_layout();
+static_assert(kScratch.act_rank == kScratch.act_idx + kNoAllocCap * 4,
+              "the active list's ranks follow its positions (one u64 array in quadrupling rounds)");
 
 static __device__ __align__(256) unsigned char scratch[kScratch.bytes];
 

@@ -342,12 +342,124 @@ void launch_pack_pairs(const u32* act_idx, const u32* act_rank, const SortCtl* c
 }
 
 // ---------------------------------------------------------------------------
+// Prefix quadrupling (Section 2.1): a round sorts the rank quadruples
+// (r0, r1, r2, r3) = (ISA[i], ISA[i+h], ISA[i+2h], ISA[i+3h]) (0 past the end)
+// and resolves prefix length 4h. The 4b-bit key is sorted as two 2b-bit words,
+// least significant first (LSD order across the words):
+//   1. lo = r2 << b | r3 for every sorted suffix, values = position;
+//   2. sort; name the runs of equal lo (1 + the run's first sorted position),
+//      written with the position as pk[q] = lname << 32 | i in sorted order;
+//   3. hi = r0 << b | r1 in that order;
+//   4. stable sort of hi with generated values q (the lo-sorted index);
+//   5. permute: position and lname of each hi-sorted element, read through q;
+//   6. re-rank with (hi, lname) as the key, hi's upper half as the group.
+// lname increases with lo, so (hi, lname) orders like (r0, r1, r2, r3).
+
+__device__ inline u32 isa_or_zero(const u32* __restrict__ isa, u64 j, u64 n) {
+  return j < n ? isa[j] : 0u;
+}
+
+__global__ __launch_bounds__(256) void pack_quad_lo_kernel(const u32* __restrict__ act_idx,
+                                                           const SortCtl* __restrict__ ctl,
+                                                           const RoundCtl* __restrict__ rc, u64 n,
+                                                           int b, const u32* __restrict__ isa,
+                                                           u64* __restrict__ keys,
+                                                           u32* __restrict__ vals) {
+  const u64 count = ctl->count;
+  const u64 h = rc->h;
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  const bool dense = ctl->dense != 0;
+  for (u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += stride) {
+    // A dense round takes every position in order (the sort generates the
+    // values); otherwise the survivors' positions.
+    const u64 i = dense ? p : u64(act_idx[p]);
+    const u32 r2 = isa_or_zero(isa, i + 2 * h, n);
+    const u32 r3 = isa_or_zero(isa, i + 3 * h, n);
+    keys[p] = (u64(r2) << b) | u64(r3);
+    if (!dense) vals[p] = u32(i);
+  }
+}
+
+void launch_pack_quad_lo(const u32* act_idx, const SortCtl* ctl, const RoundCtl* rc, u64 n, int b,
+                         const u32* isa, u64* keys, u32* vals, u32 grid, hipStream_t s) {
+  hipLaunchKernelGGL(pack_quad_lo_kernel, dim3(grid), dim3(256), 0, s, act_idx, ctl, rc, n, b, isa,
+                     keys, vals);
+}
+
+__global__ __launch_bounds__(256) void pack_quad_hi_kernel(const u64* __restrict__ pk,
+                                                           const SortCtl* __restrict__ ctl,
+                                                           const RoundCtl* __restrict__ rc, u64 n,
+                                                           int b, const u32* __restrict__ isa,
+                                                           u64* __restrict__ keys,
+                                                           u64* __restrict__ counters) {
+  const u64 count = ctl->count;
+  const u64 h = rc->h;
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  bool bad = false;
+  for (u64 q = u64(blockIdx.x) * blockDim.x + threadIdx.x; q < count; q += stride) {
+    const u64 i = u64(u32(pk[q]));
+    if (i >= n) {
+      bad = true;
+      keys[q] = 0;
+      continue;
+    }
+    keys[q] = (u64(isa[i]) << b) | u64(isa_or_zero(isa, i + h, n));
+  }
+  if (bad)
+    atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+             (unsigned long long)kErrBounds);
+}
+
+void launch_pack_quad_hi(const u64* pk, const SortCtl* ctl, const RoundCtl* rc, u64 n, int b,
+                         const u32* isa, u64* keys, u64* counters, u32 grid, hipStream_t s) {
+  hipLaunchKernelGGL(pack_quad_hi_kernel, dim3(grid), dim3(256), 0, s, pk, ctl, rc, n, b, isa, keys,
+                     counters);
+}
+
+// After the hi sort: its values are lo-sorted indices q; each becomes the
+// element's position (in place) and its run name of lo goes to the other
+// value buffer, which the re-rank reads as the key's tie word.
+__global__ __launch_bounds__(256) void quad_permute_kernel(const SortCtl* __restrict__ ctl,
+                                                           const SortPlan* __restrict__ plan,
+                                                           const u64* __restrict__ pk,
+                                                           u32* __restrict__ valsA,
+                                                           u32* __restrict__ valsB,
+                                                           u64* __restrict__ counters) {
+  const u64 count = ctl->count;
+  const u32 fb = plan->final_buf;
+  u32* vals = fb ? valsB : valsA;
+  u32* tie = fb ? valsA : valsB;
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  bool bad = false;
+  for (u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x; p < count; p += stride) {
+    const u64 q = vals[p];
+    if (q >= count) {
+      bad = true;
+      continue;
+    }
+    const u64 x = pk[q];
+    vals[p] = u32(x);
+    tie[p] = u32(x >> 32);
+  }
+  if (bad)
+    atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+             (unsigned long long)kErrBounds);
+}
+
+void launch_quad_permute(const SortCtl* ctl, const SortPlan* plan, const u64* pk, u32* valsA,
+                         u32* valsB, u64* counters, u32 grid, hipStream_t s) {
+  hipLaunchKernelGGL(quad_permute_kernel, dim3(grid), dim3(256), 0, s, ctl, plan, pk, valsA, valsB,
+                     counters);
+}
+
+// ---------------------------------------------------------------------------
 // Sort control (see SortCtl): the first kernel of every sort.
 
 __global__ __launch_bounds__(256) void sort_begin_kernel(SortCtl* __restrict__ ctl,
                                                          RoundCtl* __restrict__ rc, u64 host_count,
                                                          const u64* __restrict__ dev_count,
                                                          int npass, u64 dense_n,
+                                                         int log2a,
                                                          u32* __restrict__ clear,
                                                          u64 clear_words,
                                                          u64* __restrict__ counters) {
@@ -365,7 +477,7 @@ __global__ __launch_bounds__(256) void sort_begin_kernel(SortCtl* __restrict__ c
     const u32 k = rc->round + 1;
     if (k < u32(kMaxRounds)) {
       rc->round = k;
-      rc->h = counters[kCtrChars] << (k - 1);
+      rc->h = counters[kCtrChars] << (u32(log2a) * (k - 1));
       rc->active[k] = count;
       if (dense) rc->dense |= u64(1) << k;
     } else {
@@ -381,12 +493,13 @@ __global__ __launch_bounds__(256) void sort_begin_kernel(SortCtl* __restrict__ c
 }
 
 void launch_sort_begin(SortCtl* ctl, RoundCtl* rc, u64 host_count, const u64* dev_count, int npass,
-                       u64 dense_n, u32* clear, u64 clear_words, u64* counters, hipStream_t s) {
+                       u64 dense_n, int log2a, u32* clear, u64 clear_words, u64* counters,
+                       hipStream_t s) {
   u64 blocks = ceil_div(clear_words, 256 * 4);
   if (blocks < 1) blocks = 1;
   if (blocks > 256) blocks = 256;
   hipLaunchKernelGGL(sort_begin_kernel, dim3(u32(blocks)), dim3(256), 0, s, ctl, rc, host_count,
-                     dev_count, npass, dense_n, clear, clear_words, counters);
+                     dev_count, npass, dense_n, log2a, clear, clear_words, counters);
 }
 
 __global__ void sort_gen_reset_kernel(SortCtl* ctl) {
@@ -629,8 +742,10 @@ __global__ void radix_plan_kernel(const SortCtl* __restrict__ ctl, const u64* __
   }
   plan->final_buf = cur;
   if (!plan_log || count == 0) return;
-  const int row = log_row >= 0 ? log_row : int(rc->round);
-  if (row >= kMaxRounds + 1) return;
+  const int row = log_row >= 0                ? log_row
+                  : log_row == kLogRowRound ? int(rc->round)
+                                            : int(rc->round) + kPlanRowSecond;
+  if (row >= kPlanLogRows) return;
   u32* f = plan_log + size_t(row) * kPlanLogWords;
   for (int p = 0; p < kMaxPasses; ++p) {
     f[p] = plan->skip[p];
@@ -1074,15 +1189,24 @@ int onesweep_wgs_per_cu(int items, int block, bool table, int rb) {
 // galloping down from p in strides 1, 64, 64^2, ... until a probe falls below
 // x, then narrowing the bracketed interval 64-fold per step. A run of length L
 // costs about 2 log64(L) dependent wave loads; every probe is inside [0, p].
-__device__ u64 run_start_wave(const u64* __restrict__ keys, u64 p, int sh, u64 x) {
+// With TIE, elements are ordered by (key, tie[]) and the run is that of equal
+// (key, tie) pairs (sh must be 0).
+template <bool TIE>
+__device__ u64 run_start_wave(const u64* __restrict__ keys, const u32* __restrict__ tie, u64 p,
+                              int sh, u64 x, u32 tx) {
   using i64 = long long;
   const int lane = lane_id();
+  auto is_below = [&](i64 pos) {
+    const u64 kp = keys[pos] >> sh;
+    if (!TIE) return kp < x;
+    return kp < x || (kp == x && tie[pos] < tx);
+  };
   i64 hi = i64(p);  // (keys[hi] >> sh) == x
   i64 lo = -1;      // (keys[lo] >> sh) < x, or -1
   i64 stride = 1;
   for (;;) {
     const i64 pos = hi - stride * (lane + 1);
-    const bool below = pos < 0 || (keys[pos] >> sh) < x;
+    const bool below = pos < 0 || is_below(pos);
     const u64 m = __ballot(below);
     if (m) {
       const int l = __ffsll((long long)m) - 1;
@@ -1097,7 +1221,7 @@ __device__ u64 run_start_wave(const u64* __restrict__ keys, u64 p, int sh, u64 x
   while (hi - lo > 1) {
     const i64 st = (hi - lo + kWave - 1) / kWave;
     const i64 pos = hi - st * (lane + 1);
-    const bool below = pos <= lo || (keys[pos] >> sh) < x;
+    const bool below = pos <= lo || is_below(pos);
     const u64 m = __ballot(below);  // lane 63 probes at or below lo: m != 0
     const int l = __ffsll((long long)m) - 1;
     const i64 nlo = hi - st * (l + 1);
@@ -1137,6 +1261,10 @@ __device__ u64 run_start_wave(const u64* __restrict__ keys, u64 p, int sh, u64 x
 // output range with one atomic add per tile, so survivors keep their sorted
 // order inside a tile but tiles land in any order (the next round sorts them
 // anyway).
+// TIE (quadrupling rounds): the key is (keys[p], tie word), the tie words
+// being the value buffer the sort did not end in; groups still come from the
+// key's upper part.
+template <bool TIE>
 __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
@@ -1155,8 +1283,11 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const u32 fb = plan->final_buf;
   const u64* keys = fb ? keysB : keysA;
   const u32* vals = fb ? valsB : valsA;
+  const u32* tie = fb ? valsA : valsB;  // TIE only
   const bool scatter = (mode & kRerankScatterIsa) != 0;
   const bool isa_only = (mode & kRerankIsaOnly) != 0;
+  const bool pair_out = (mode & kRerankPairOut) != 0;
+  const bool no_survivors = isa_only || pair_out;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
@@ -1181,7 +1312,13 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
       start = 0;  // one group holds every element
     } else if (base > 0) {
       const u64 x = kb >> sh;
-      if ((keys[base - 1] >> sh) == x) start = run_start_wave(keys, base, sh, x);
+      if (TIE && wave == 0) {
+        const u32 tb = tie[base];
+        if (keys[base - 1] == x && tie[base - 1] == tb)
+          start = run_start_wave<true>(keys, tie, base, 0, x, tb);
+      } else if ((keys[base - 1] >> sh) == x) {
+        start = run_start_wave<false>(keys, nullptr, base, sh, x, 0);
+      }
     }
     if (lane == 0) s_prefix[wave] = start;
   }
@@ -1198,6 +1335,14 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64 e = wbase + u64(r) * kWave + lane;
     v[r] = e < count ? vals[e] : 0;
   }
+  u32 tw[TIE ? R : 1];
+  if (TIE) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const u64 e = wbase + u64(r) * kWave + lane;
+      tw[r] = e < count ? tie[e] : 0;
+    }
+  }
 
   // Flags per element (bit r: head, bit 16 + r: unique; gflags bit r: group
   // start) and the wave's aggregates: last head, last group start (tile-local
@@ -1207,6 +1352,11 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const u64 edge_next = wbase + u64(R) * kWave;
   const u64 k_before = (lane == 0 && wbase > 0 && wbase - 1 < count) ? keys[wbase - 1] : 0;
   const u64 k_after = (lane == kWave - 1 && edge_next < count) ? keys[edge_next] : 0;
+  u32 t_before = 0, t_after = 0;
+  if (TIE) {
+    t_before = (lane == 0 && wbase > 0 && wbase - 1 < count) ? tie[wbase - 1] : 0;
+    t_after = (lane == kWave - 1 && edge_next < count) ? tie[edge_next] : 0;
+  }
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const u64 e = wbase + u64(r) * kWave + lane;
@@ -1216,12 +1366,23 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64 first_next = r + 1 < R ? __shfl(k[r + 1], 0, kWave) : k_after;
     if (lane == 0) kp = last_prev;
     if (lane == kWave - 1) kn = first_next;
+    bool diff_prev = k[r] != kp, diff_next = kn != k[r];
+    if (TIE) {
+      u32 tp = __shfl_up(tw[r], 1, kWave);
+      u32 tn = __shfl_down(tw[r], 1, kWave);
+      const u32 tl = r > 0 ? __shfl(tw[r - 1], kWave - 1, kWave) : t_before;
+      const u32 tf = r + 1 < R ? __shfl(tw[r + 1], 0, kWave) : t_after;
+      if (lane == 0) tp = tl;
+      if (lane == kWave - 1) tn = tf;
+      diff_prev = diff_prev || tw[r] != tp;
+      diff_next = diff_next || tn != tw[r];
+    }
     const bool valid = e < count;
     int gsh = a.gshift;
     if (valid && a.tbase && a.tround0[k[r] >> a.idshift]) gsh = a.idshift;  // group = text
-    const bool head = valid && (e == 0 || k[r] != kp);
+    const bool head = valid && (e == 0 || diff_prev);
     const bool grp = valid && (e == 0 || (gsh < 64 && (k[r] >> gsh) != (kp >> gsh)));
-    const bool uniq = head && (e + 1 == count || kn != k[r]);
+    const bool uniq = head && (e + 1 == count || diff_next);
     // Alone in its group: its name was unique before this round, so it was
     // final already (only a dense round sorts such suffixes again).
     const bool alone = grp && (e + 1 == count || (gsh < 64 && (kn >> gsh) != (k[r] >> gsh)));
@@ -1245,7 +1406,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     u32 tts = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) tts += s_ws[w];
-    s_prefix[2] = (tts && !isa_only)
+    s_prefix[2] = (tts && !no_survivors)
                       ? atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
                                   (unsigned long long)tts)
                       : 0;
@@ -1301,6 +1462,10 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
       bad = true;
       continue;
     }
+    if (pair_out) {
+      a.pair_out[e] = (nr << 32) | u64(v[r]);
+      continue;
+    }
     // The ISA already holds every active suffix's previous name, so a name
     // that did not change (a group that did not split, or the first sub-group
     // of one that did) is not written again.
@@ -1327,9 +1492,14 @@ void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
                            const u32* valsB, const SortPlan* plan, const RerankArgs& args,
                            const SortCtl* ctl, u32* isa, u32* sa_out, u32* act_idx, u64* act_ti,
                            u32* act_rank, u64* counters, u32 grid, hipStream_t s) {
-  hipLaunchKernelGGL(rerank_compact_kernel, dim3(grid), dim3(kRerankBlock), 0, s, keysA, keysB,
-                     valsA, valsB, plan, args, ctl, isa, sa_out, act_idx, act_ti, act_rank,
-                     counters);
+  if (args.tie)
+    hipLaunchKernelGGL(rerank_compact_kernel<true>, dim3(grid), dim3(kRerankBlock), 0, s, keysA,
+                       keysB, valsA, valsB, plan, args, ctl, isa, sa_out, act_idx, act_ti, act_rank,
+                       counters);
+  else
+    hipLaunchKernelGGL(rerank_compact_kernel<false>, dim3(grid), dim3(kRerankBlock), 0, s, keysA,
+                       keysB, valsA, valsB, plan, args, ctl, isa, sa_out, act_idx, act_ti, act_rank,
+                       counters);
 }
 
 // ---------------------------------------------------------------------------

@@ -166,7 +166,8 @@ bool tuning_valid(const sa_tuning& t) {
   const int block = t.sort_block ? int(t.sort_block) : 256;
   if (!onesweep_supported(int(t.sort_items), block, t.sort_match == 1, int(rb))) return false;
   if (t.lazy_ratio < 3 || t.round0_full > 1 || t.sort_wgs_per_cu > 16) return false;
-  if (t.rounds_ahead > 64 || t.round_graphs > 1 || t.reserved != 0) return false;
+  if (t.rounds_ahead > 64 || t.round_graphs > 1) return false;
+  if (t.prefix_mult != 0 && t.prefix_mult != 2 && t.prefix_mult != 4) return false;
   return true;
 }
 
@@ -179,6 +180,7 @@ sa_tuning default_tuning() {
   t.round0_full = 0;
   t.sort_wgs_per_cu = 0;
   t.radix_bits = u32(kRadixBits);
+  t.prefix_mult = 2;
   return t;
 }
 
@@ -231,6 +233,11 @@ sa_status tune_parse(const std::string& text, TuneTable& out) {
       if (!num_field(e, "radix_bits", kRadixBitsMin, kRadixBitsMax, &v)) return SA_EINVAL;
       te.t.radix_bits = u32(v);
     }
+    te.t.prefix_mult = 2;  // entries without the field predate quadrupling
+    if (e.get("prefix_mult")) {
+      if (!num_field(e, "prefix_mult", 2, 4, &v)) return SA_EINVAL;
+      te.t.prefix_mult = u32(v);
+    }
     if (!tuning_valid(te.t)) return SA_EINVAL;
     te.ms = num_field(e, "ms", 0, 1e12, &v) ? v : 0.0;
     out.entries.push_back(te);
@@ -261,6 +268,7 @@ std::string tune_format(const TuneTable& t) {
       << e.t.sort_wgs_per_cu << ", \"sort_block\": " << e.t.sort_block
       << ", \"sort_match\": " << e.t.sort_match
       << ", \"radix_bits\": " << (e.t.radix_bits ? e.t.radix_bits : u32(kRadixBits))
+      << ", \"prefix_mult\": " << (e.t.prefix_mult == 4 ? 4u : 2u)
       << ", \"lazy_ratio\": " << e.t.lazy_ratio
       << ", \"round0_full\": " << e.t.round0_full << ", \"ms\": " << ms << "}";
   }
@@ -324,6 +332,7 @@ void apply_tuning(sa_ctx* c, const sa_tuning& t) {
   c->rounds_ahead = t.rounds_ahead;
   c->graphs = t.round_graphs == 0;
   c->radix_bits = t.radix_bits ? int(t.radix_bits) : kRadixBits;
+  c->prefix_mult = t.prefix_mult == 4 ? 4 : 2;
 }
 
 sa_tuning current_tuning(const sa_ctx* c) {
@@ -338,6 +347,7 @@ sa_tuning current_tuning(const sa_ctx* c) {
   t.radix_bits = u32(c->radix_bits);
   t.rounds_ahead = c->rounds_ahead;
   t.round_graphs = c->graphs ? 0u : 1u;
+  t.prefix_mult = u32(c->prefix_mult);
   return t;
 }
 
