@@ -12,6 +12,10 @@ compiles it with g++ on demand and wraps it with ctypes over numpy arrays:
 * :func:`pd_names` -- the names after a given number of doubling sorts.
 * :func:`pa_names`, :func:`pa_sa` -- prefix a-tupling (a = 4: the paper's prefix
   quadrupling): names of single characters, then sorts of a-tuples of names.
+* :func:`opk_order`, :func:`pdd_sa`, :func:`pdd_round` -- prefix doubling with
+  discarding by sorting (Alg. 5 with the comparator of Eq. 1 and Alg. 6): the
+  comparator's position order, the suffix array with per-round item counts, and
+  the working items of one round.
 * :func:`prefix_ranks` -- the closed form of the names for prefix length ``h``:
   1 + the number of suffixes whose padded length-``h`` prefix is smaller.
 * :func:`brute_sa` -- the definition: sort all suffixes lexicographically.
@@ -68,7 +72,10 @@ def configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_sa_interval.argtypes = [u8p, u64, u32p, u8p, u64, u64p, u64p]
     lib.oracle_pa_names.argtypes = [u8p, u64, ctypes.c_uint32, u64, u32p, u64p]
     lib.oracle_pa_sa.argtypes = [u8p, u64, ctypes.c_uint32, u32p]
-    for f in ("oracle_sa", "oracle_pd_names", "oracle_prefix_ranks", "oracle_pa_names",
+    lib.oracle_opk_order.argtypes = [u64, u64, u32p]
+    lib.oracle_pdd_sa.argtypes = [u8p, u64, u64, u32p, u64p, u64, u64p]
+    lib.oracle_pdd_round.argtypes = [u8p, u64, u64, u64, u32p, u32p, u8p, u64p]
+    for f in ("oracle_opk_order", "oracle_pdd_sa", "oracle_pdd_round","oracle_sa", "oracle_pd_names", "oracle_prefix_ranks", "oracle_pa_names",
               "oracle_pa_sa",
               "oracle_brute_sa", "oracle_check_sa", "oracle_num_threads",
               "oracle_lcp", "oracle_bwt", "oracle_sa_interval"):
@@ -144,6 +151,49 @@ def pa_sa(text, a: int) -> np.ndarray:
     if rc:
         raise ValueError("bad arguments")
     return out
+
+
+def opk_order(n: int, h: int) -> np.ndarray:
+    """Positions 0..n-1 ordered by (i mod h, i div h): the comparator of Eq. 1."""
+    out = np.empty(n, dtype=np.uint32)
+    if _lib().oracle_opk_order(n, h, _p(out, ctypes.c_uint32)):
+        raise ValueError("bad arguments")
+    return out
+
+
+def pdd_sa(text, c: int = 2) -> tuple[np.ndarray, np.ndarray]:
+    """Suffix array by sort-based prefix doubling with discarding (Alg. 5) from
+    names of c-character prefixes, and the per-round counts as rows
+    (|P|, |I|, |D'|, |U'|): working items, non-unique items, items discarded
+    (finalised), unique items kept for the next round."""
+    t = _text(text)
+    out = np.empty(t.size, dtype=np.uint32)
+    counts = np.zeros(4 * 64, dtype=np.uint64)
+    rounds = ctypes.c_uint64(0)
+    if _lib().oracle_pdd_sa(_p(t, ctypes.c_uint8), t.size, c, _p(out, ctypes.c_uint32),
+                            _p(counts, ctypes.c_uint64), 64, ctypes.byref(rounds)):
+        raise ValueError("bad arguments")
+    r = int(rounds.value)
+    return out, counts[:4 * r].reshape(r, 4)
+
+
+def pdd_round(text, c: int, k: int):
+    """The working items of round k (>= 1) of :func:`pdd_sa` after the
+    comparator sort: (positions, names, unique flags), or None if the build
+    ended before round k."""
+    t = _text(text)
+    n = t.size
+    pos = np.empty(max(n, 1), dtype=np.uint32)
+    names = np.empty(max(n, 1), dtype=np.uint32)
+    uniq = np.empty(max(n, 1), dtype=np.uint8)
+    m = ctypes.c_uint64(0)
+    rc = _lib().oracle_pdd_round(_p(t, ctypes.c_uint8), n, c, k, _p(pos, ctypes.c_uint32),
+                                 _p(names, ctypes.c_uint32), _p(uniq, ctypes.c_uint8),
+                                 ctypes.byref(m))
+    if rc:
+        return None
+    mm = int(m.value)
+    return pos[:mm], names[:mm], uniq[:mm].astype(bool)
 
 
 def prefix_ranks(text, h: int) -> np.ndarray:

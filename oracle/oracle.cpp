@@ -209,6 +209,165 @@ int oracle_pa_sa(const uint8_t* T, uint64_t n, uint32_t a, uint32_t* SA) {
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Prefix doubling with discarding by sorting (Alg. 5 with the comparator of
+// Eq. 1 and the helper functions of Alg. 6): no inverse suffix array; each
+// round sorts the working items by text position in the comparator's order so
+// that suffix i and suffix i + h are neighbours, pairs them in one scan, and
+// keeps a unique item only while a non-unique item may still need its name.
+// Readings: names are 1-based (0 is the sentinel); the window arrays' length
+// l is the number of items; the last window is the one ending at the last
+// item; the non-unique items are sorted by name pair before renaming; a new
+// name is the old one plus the offset of the item's run of equal pairs inside
+// its group of equal old names; the loop ends when no item is non-unique.
+
+// Positions 0..n-1 in the order of Eq. 1 for offset h: by i mod h, then by
+// i div h (h = 2^k in the paper; any h >= 1 here).
+int oracle_opk_order(uint64_t n, uint64_t h, uint32_t* out) {
+  if (n >= (uint64_t(1) << 32) || h == 0) return 1;
+  std::vector<uint32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0u);
+  std::sort(idx.begin(), idx.end(), [h](uint32_t a, uint32_t b) {
+    if (a % h != b % h) return a % h < b % h;
+    return a / h < b / h;
+  });
+  std::copy(idx.begin(), idx.end(), out);
+  return 0;
+}
+
+namespace {
+
+struct Item {
+  uint32_t i, r;
+  char s;  // 'u' unique, 'n' not unique
+};
+
+// Alg. 5 from names of c-character prefixes. Runs until no item is
+// non-unique, or stops before round max_rounds + 1 (0: no limit). Per round k
+// (1-based) appends |P|, |I|, |D'|, |U'| to `counts` and, when k == snap_round,
+// copies P (sorted by the comparator, with the states) to snap.
+uint64_t sort_discarding(const uint8_t* T, uint64_t n, uint64_t c, uint32_t* SA,
+                         std::vector<uint64_t>* counts, uint64_t max_rounds,
+                         uint64_t snap_round, std::vector<Item>* snap) {
+  // Initial names: 1 + the number of suffixes whose c-prefix is smaller, with
+  // the items in name order (the sorted triples of the initial step, which
+  // uses c = 2).
+  std::vector<uint32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0u);
+  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+    return cmp_prefix(T, n, c, a, b) < 0;
+  });
+  std::vector<Item> N(n);
+  uint64_t head = 0;
+  for (uint64_t p = 0; p < n; ++p) {
+    if (p > 0 && cmp_prefix(T, n, c, idx[p - 1], idx[p]) != 0) head = p;
+    N[p] = Item{idx[p], static_cast<uint32_t>(head + 1), 'n'};
+  }
+  std::vector<Item> U;
+  uint64_t h = c, round = 0;
+  for (;;) {
+    ++round;
+    // Unique: in name order, an item is unique if its name differs from both
+    // neighbours' (the first and last compare with their one neighbour).
+    const uint64_t l = N.size();
+    for (uint64_t j = 0; j < l; ++j) {
+      const bool differs_prev = j == 0 || N[j - 1].r != N[j].r;
+      const bool differs_next = j + 1 == l || N[j + 1].r != N[j].r;
+      N[j].s = (differs_prev && differs_next) ? 'u' : 'n';
+    }
+    // Union with the kept unique items, sorted by the comparator of Eq. 1.
+    std::vector<Item> P = N;
+    P.insert(P.end(), U.begin(), U.end());
+    std::sort(P.begin(), P.end(), [h](const Item& a, const Item& b) {
+      if (a.i % h != b.i % h) return a.i % h < b.i % h;
+      return a.i / h < b.i / h;
+    });
+    if (round == snap_round && snap) *snap = P;
+    // NPairs over windows of three: a non-unique item takes the name of its
+    // successor if that is suffix i + h (else the sentinel 0); a unique item is
+    // kept only if the two items before it are both non-unique (one of them may
+    // need its name in the next round), otherwise discarded: its name is final.
+    std::vector<std::pair<uint64_t, uint32_t>> I;  // (r0 << 32 | r1, i)
+    std::vector<Item> Unext;
+    uint64_t discarded = 0;
+    const uint64_t m = P.size();
+    for (uint64_t p = 0; p < m; ++p) {
+      const Item& x = P[p];
+      if (x.s == 'n') {
+        const bool next = p + 1 < m && uint64_t(P[p + 1].i) == uint64_t(x.i) + h;
+        const uint64_t r1 = next ? P[p + 1].r : 0;
+        I.push_back({(uint64_t(x.r) << 32) | r1, x.i});
+      } else if (p >= 2 && P[p - 1].s == 'n' && P[p - 2].s == 'n') {
+        Unext.push_back(x);
+      } else {
+        SA[x.r - 1] = x.i;
+        ++discarded;
+      }
+    }
+    if (counts) {
+      counts->push_back(m);
+      counts->push_back(I.size());
+      counts->push_back(discarded);
+      counts->push_back(Unext.size());
+    }
+    U = Unext;
+    if (I.empty()) break;
+    if (max_rounds != 0 && round >= max_rounds) break;
+    // Sort the non-unique items by name pair and rename: old name + (start of
+    // the run of equal pairs - start of the group of equal old names).
+    std::sort(I.begin(), I.end());
+    N.assign(I.size(), Item{0, 0, 'n'});
+    uint64_t run = 0, grp = 0;
+    for (uint64_t p = 0; p < I.size(); ++p) {
+      if (p > 0 && I[p].first != I[p - 1].first) run = p;
+      if (p > 0 && (I[p].first >> 32) != (I[p - 1].first >> 32)) grp = p;
+      const uint64_t r0 = I[p].first >> 32;
+      N[p] = Item{I[p].second, static_cast<uint32_t>(r0 + run - grp), 'n'};
+    }
+    h *= 2;
+  }
+  return round;
+}
+
+}  // namespace
+
+// Suffix array by sort-based prefix doubling with discarding, from names of
+// c-character prefixes (c = 2 is the paper's initial step). counts (may be
+// NULL) receives |P|, |I|, |D'|, |U'| of every round, at most max_counts
+// rounds; *rounds_out the number of rounds. Returns 0, or 1 on bad input.
+int oracle_pdd_sa(const uint8_t* T, uint64_t n, uint64_t c, uint32_t* SA, uint64_t* counts,
+                  uint64_t max_counts, uint64_t* rounds_out) {
+  if (n >= (uint64_t(1) << 32) || c == 0) return 1;
+  *rounds_out = 0;
+  if (n == 0) return 0;
+  std::vector<uint64_t> cnt;
+  *rounds_out = sort_discarding(T, n, c, SA, &cnt, 0, 0, nullptr);
+  if (counts)
+    for (uint64_t k = 0; k < cnt.size() && k < 4 * max_counts; ++k) counts[k] = cnt[k];
+  return 0;
+}
+
+// The working items P of round k (>= 1) after the comparator sort: positions,
+// names and states ('u' = 1, 'n' = 0); *m receives |P| (the arrays hold n).
+// Returns 1 if the build ended before round k.
+int oracle_pdd_round(const uint8_t* T, uint64_t n, uint64_t c, uint64_t k, uint32_t* pos,
+                     uint32_t* names, uint8_t* unique, uint64_t* m) {
+  if (n >= (uint64_t(1) << 32) || c == 0 || k == 0) return 1;
+  *m = 0;
+  if (n == 0) return 1;
+  std::vector<uint32_t> sa(n);
+  std::vector<Item> P;
+  const uint64_t rounds = sort_discarding(T, n, c, sa.data(), nullptr, k, k, &P);
+  if (rounds < k) return 1;
+  *m = P.size();
+  for (uint64_t p = 0; p < P.size(); ++p) {
+    pos[p] = P[p].i;
+    names[p] = P[p].r;
+    unique[p] = P[p].s == 'u' ? 1 : 0;
+  }
+  return 0;
+}
+
 // Closed form of the names for prefix length h: ranks[i] = 1 + #{ j :
 // pad_h(j) < pad_h(i) }, where pad_h(i) is T[i, i+h) cut at n (the sentinel
 // ending it). Computed by sorting positions with the padded-prefix comparison.

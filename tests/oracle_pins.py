@@ -68,6 +68,70 @@ def load(name):
         return json.load(f)
 
 
+def pdd_pins(rng) -> bool:
+    """Sort-based prefix doubling with discarding (Alg. 5)."""
+    g = load("paper_example1_comparator.json")
+    t = g["text"].encode()
+    for h, printed in g["comparator_sorted_printed"].items():
+        if oracle.opk_order(len(t), int(h)).tolist() != [p[0] for p in printed]:
+            return False
+    # With c = 2 (the paper's initial pairs) the working items of rounds 1 and
+    # 2 are the printed lists: every non-unique item is in them, and the one
+    # unique item (position 8) is kept while two non-unique items precede it.
+    for k, h in ((1, "2"), (2, "4")):
+        pos, names, uniq = oracle.pdd_round(t, 2, k)
+        printed = g["comparator_sorted_printed"][h]
+        if pos.tolist() != [p[0] for p in printed] or \
+                names.tolist() != [p[1] + 1 for p in printed]:
+            return False
+    pos, names, _ = oracle.pdd_round(t, 2, 1)
+    pairs = [(int(pos[p]), int(names[p]),
+              int(names[p + 1]) if p + 1 < len(pos) and pos[p + 1] == pos[p] + 2 else 0)
+             for p in range(len(pos))]
+    # Printed names are 0-based; the partner's name is the sentinel when
+    # suffix i + 2 does not exist.
+    want = [(i, a + 1, b + 1 if i + 2 < len(t) else 0) for i, a, b in g["pairs_printed"]["2"]]
+    if pairs != want:
+        return False
+    g = load("pdd_worked_aba.json")
+    sa, counts = oracle.pdd_sa(g["text"].encode(), g["c"])
+    if sa.tolist() != g["sa"] or counts.astype(int).tolist() != g["counts"]:
+        return False
+    for _ in range(40):
+        n = int(rng.integers(1, 100))
+        tt = rng.integers(0, int(rng.choice([1, 2, 3, 256])), n).astype(np.uint8)
+        tb = tt.tobytes()
+        c = int(rng.choice([1, 2, 3, 8]))
+        sa, counts = oracle.pdd_sa(tt, c)
+        if sa.tolist() != py_brute_sa(tb):
+            return False
+        P, I, D, U = (counts[:, j].astype(int).tolist() for j in range(4))
+        if P[0] != n or sum(D) != n or I[-1] != 0 or U[-1] != 0:
+            return False
+        for k in range(len(P)):
+            if P[k] != I[k] + D[k] + U[k]:
+                return False
+            if k + 1 < len(P) and P[k + 1] != I[k] + U[k]:
+                return False
+            h = c << k
+            got = oracle.pdd_round(tt, c, k + 1)
+            if got is None:
+                return False
+            pos, names, uniq = got
+            # Names are the closed form at prefix length h, unique flags agree
+            # with them, and every non-unique item finds suffix i + h present.
+            want = py_prefix_ranks(tb, h)
+            if names.tolist() != [want[i] for i in pos.tolist()]:
+                return False
+            present = set(pos.tolist())
+            for i, u in zip(pos.tolist(), uniq.tolist()):
+                if u != (want.count(want[i]) == 1):
+                    return False
+                if not u and i + h < n and i + h not in present:
+                    return False
+    return True
+
+
 def pins_pass() -> bool:
     for fixture in ("paper_example1_bdacbdacb.json", "banana.json"):
         g = load(fixture)
@@ -132,6 +196,8 @@ def pins_pass() -> bool:
                 if h == a ** k and k > 0 and len(set(py_prefix_ranks(tb, a ** (k - 1)))) == n:
                     return False  # names were distinct already: no further sort runs
     if oracle.pa_sa(b"aaaaaaaaaaaaaaaaaaaaaaaa", 4).tolist() != list(range(23, -1, -1)):
+        return False
+    if not pdd_pins(rng):
         return False
     if oracle.lcp(b"banana", [5, 3, 1, 0, 4, 2]).tolist() != [0, 1, 3, 0, 0, 2]:
         return False

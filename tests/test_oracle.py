@@ -195,7 +195,8 @@ MUTANTS = {
     "dropped_second_rank": ("S[i] = Triple{(r0 << 32) | r1, static_cast<uint32_t>(i)};",
                             "S[i] = Triple{(r0 << 32), static_cast<uint32_t>(i)};"),
     "early_stop": ("if (distinct == n) break;", "if (distinct + 1 >= n) break;"),
-    "no_doubling": ("h *= 2;", "h += 1;"),
+    "no_doubling": ("    h *= 2;\n  }\n  if (h_out) *h_out = h;", "    h += 1;\n  }\n  if (h_out) *h_out = h;"),
+    "pdd_no_doubling": ("    h *= 2;\n  }\n  return round;", "    h += 1;\n  }\n  return round;"),
     "prefix_longer_first": ("return li < lj ? -1 : 1;", "return li < lj ? 1 : -1;"),
     "checker_loose": ("bool ok = (T[a] < T[b]) ||", "bool ok = (T[a] <= T[b]) ||"),
     "lcp_overcount": ("lcp[j] = static_cast<uint32_t>(l);",
@@ -212,6 +213,20 @@ MUTANTS = {
     "tuple_h_doubled": ("    h *= a;\n    ++done;", "    h *= 2;\n    ++done;"),
     "tuple_char_names_zero": ("name[i] = static_cast<uint32_t>(below[T[i]] + 1);",
                               "name[i] = static_cast<uint32_t>(below[T[i]]);"),
+    "pdd_keep_after_one": ("} else if (p >= 2 && P[p - 1].s == 'n' && P[p - 2].s == 'n') {",
+                           "} else if (p >= 1 && P[p - 1].s == 'n') {"),
+    "pdd_discard_all": ("} else if (p >= 2 && P[p - 1].s == 'n' && P[p - 2].s == 'n') {",
+                        "} else if (false) {"),
+    "pdd_partner_any_next": ("const bool next = p + 1 < m && uint64_t(P[p + 1].i) == uint64_t(x.i) + h;",
+                             "const bool next = p + 1 < m;"),
+    "pdd_comparator_div_first": ("      if (a.i % h != b.i % h) return a.i % h < b.i % h;\n      return a.i / h < b.i / h;\n    });\n    if (round",
+                                 "      if (a.i / h != b.i / h) return a.i / h < b.i / h;\n      return a.i % h < b.i % h;\n    });\n    if (round"),
+    "pdd_rename_no_group": ("N[p] = Item{I[p].second, static_cast<uint32_t>(r0 + run - grp), 'n'};",
+                            "N[p] = Item{I[p].second, static_cast<uint32_t>(1 + run), 'n'};"),
+    "pdd_unique_one_side": ("N[j].s = (differs_prev && differs_next) ? 'u' : 'n';",
+                            "N[j].s = differs_next ? 'u' : 'n';"),
+    "opk_order_swapped": ("    if (a % h != b % h) return a % h < b % h;\n    return a / h < b / h;",
+                          "    if (a / h != b / h) return a / h < b / h;\n    return a % h < b % h;"),
     "brute_signed": ("return std::lexicographical_compare(T + a, T + n, T + b, T + n);",
                      "return std::lexicographical_compare((const signed char*)T + a, "
                      "(const signed char*)T + n, (const signed char*)T + b, "
