@@ -16,6 +16,8 @@ compiles it with g++ on demand and wraps it with ctypes over numpy arrays:
   discarding by sorting (Alg. 5 with the comparator of Eq. 1 and Alg. 6): the
   comparator's position order, the suffix array with per-round item counts, and
   the working items of one round.
+* :func:`dc3_sample_ranks` -- the ranks among themselves of the suffixes that
+  start at positions not divisible by 3 (the sample of DC3), by definition.
 * :func:`prefix_ranks` -- the closed form of the names for prefix length ``h``:
   1 + the number of suffixes whose padded length-``h`` prefix is smaller.
 * :func:`brute_sa` -- the definition: sort all suffixes lexicographically.
@@ -75,7 +77,8 @@ def configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_opk_order.argtypes = [u64, u64, u32p]
     lib.oracle_pdd_sa.argtypes = [u8p, u64, u64, u32p, u64p, u64, u64p]
     lib.oracle_pdd_round.argtypes = [u8p, u64, u64, u64, u32p, u32p, u8p, u64p]
-    for f in ("oracle_opk_order", "oracle_pdd_sa", "oracle_pdd_round","oracle_sa", "oracle_pd_names", "oracle_prefix_ranks", "oracle_pa_names",
+    lib.oracle_dc3_sample_ranks.argtypes = [u8p, u64, u32p, u32p]
+    for f in ("oracle_dc3_sample_ranks", "oracle_opk_order", "oracle_pdd_sa", "oracle_pdd_round","oracle_sa", "oracle_pd_names", "oracle_prefix_ranks", "oracle_pa_names",
               "oracle_pa_sa",
               "oracle_brute_sa", "oracle_check_sa", "oracle_num_threads",
               "oracle_lcp", "oracle_bwt", "oracle_sa_interval"):
@@ -194,6 +197,19 @@ def pdd_round(text, c: int, k: int):
         return None
     mm = int(m.value)
     return pos[:mm], names[:mm], uniq[:mm].astype(bool)
+
+
+def dc3_sample_ranks(text) -> tuple[np.ndarray, np.ndarray]:
+    """(R1, R2): 1-based ranks among all sample suffixes (positions i with
+    i mod 3 != 0) of the suffixes 3t + 1 and 3t + 2."""
+    t = _text(text)
+    n = t.size
+    r1 = np.zeros((n + 1) // 3, dtype=np.uint32)
+    r2 = np.zeros(n // 3, dtype=np.uint32)
+    if _lib().oracle_dc3_sample_ranks(_p(t, ctypes.c_uint8), n, _p(r1, ctypes.c_uint32),
+                                      _p(r2, ctypes.c_uint32)):
+        raise ValueError("bad arguments")
+    return r1, r2
 
 
 def prefix_ranks(text, h: int) -> np.ndarray:

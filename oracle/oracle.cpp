@@ -368,6 +368,30 @@ int oracle_pdd_round(const uint8_t* T, uint64_t n, uint64_t c, uint64_t k, uint3
   return 0;
 }
 
+// ---------------------------------------------------------------------------
+// Difference cover DC3 (Section 2.2): the ranks of the sample suffixes, those
+// starting at positions i with i mod 3 != 0, among themselves. r1[t] is the
+// 1-based rank of suffix 3t + 1 (t < #{i < n : i mod 3 == 1}), r2[t] that of
+// suffix 3t + 2. By definition: the sample positions in suffix-array order
+// (the suffix array from the prefix-doubling function above).
+int oracle_dc3_sample_ranks(const uint8_t* T, uint64_t n, uint32_t* r1, uint32_t* r2) {
+  if (n >= (uint64_t(1) << 32)) return 1;
+  if (n == 0) return 0;
+  std::vector<uint32_t> sa(n);
+  oracle_sa(T, n, sa.data());
+  uint32_t rank = 0;
+  for (uint64_t j = 0; j < n; ++j) {
+    const uint64_t i = sa[j];
+    if (i % 3 == 0) continue;
+    ++rank;
+    if (i % 3 == 1)
+      r1[i / 3] = rank;
+    else
+      r2[i / 3] = rank;
+  }
+  return 0;
+}
+
 // Closed form of the names for prefix length h: ranks[i] = 1 + #{ j :
 // pad_h(j) < pad_h(i) }, where pad_h(i) is T[i, i+h) cut at n (the sentinel
 // ending it). Computed by sorting positions with the padded-prefix comparison.

@@ -199,6 +199,19 @@ def pins_pass() -> bool:
         return False
     if not pdd_pins(rng):
         return False
+    g = load("paper_example3_dbacbacbd.json")
+    r1, r2 = oracle.dc3_sample_ranks(g["text"].encode())
+    if r1.tolist() != g["dc3_r1"] or r2.tolist() != g["dc3_r2"]:
+        return False
+    for _ in range(30):
+        n = int(rng.integers(1, 80))
+        tt = rng.integers(0, int(rng.choice([1, 2, 3, 256])), n).astype(np.uint8)
+        sample = [i for i in py_brute_sa(tt.tobytes()) if i % 3]
+        rank = {i: k + 1 for k, i in enumerate(sample)}
+        r1, r2 = oracle.dc3_sample_ranks(tt)
+        if r1.tolist() != [rank[i] for i in range(1, n, 3)] or \
+                r2.tolist() != [rank[i] for i in range(2, n, 3)]:
+            return False
     if oracle.lcp(b"banana", [5, 3, 1, 0, 4, 2]).tolist() != [0, 1, 3, 0, 0, 2]:
         return False
     bw, d = oracle.bwt(b"banana", [5, 3, 1, 0, 4, 2])

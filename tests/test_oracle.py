@@ -227,6 +227,9 @@ MUTANTS = {
                             "N[j].s = differs_next ? 'u' : 'n';"),
     "opk_order_swapped": ("    if (a % h != b % h) return a % h < b % h;\n    return a / h < b / h;",
                           "    if (a / h != b / h) return a / h < b / h;\n    return a % h < b % h;"),
+    "dc3_rank_zero_based": ("    ++rank;\n    if (i % 3 == 1)", "    if (i % 3 == 1)"),
+    "dc3_ranks_swapped": ("      r1[i / 3] = rank;\n    else\n      r2[i / 3] = rank;",
+                          "      r2[i / 3] = rank;\n    else\n      r1[i / 3] = rank;"),
     "brute_signed": ("return std::lexicographical_compare(T + a, T + n, T + b, T + n);",
                      "return std::lexicographical_compare((const signed char*)T + a, "
                      "(const signed char*)T + n, (const signed char*)T + b, "
