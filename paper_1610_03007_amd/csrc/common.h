@@ -89,6 +89,13 @@ struct SortGeom {
   u32 ct_log2;
   u32 nchunks;
 };
+// Sort-based pairing (Eq. 1): position i is keyed (i mod h) * q + (i div h)
+// with q = ceil(n / h), so that positions ordered by key are ordered by
+// residue modulo h, then by quotient: suffix i + h directly follows suffix i
+// when both are present. Keys stay below h * q <= n + h - 1.
+__host__ __device__ inline u64 opk_key(u64 i, u64 h, u64 q) { return (i % h) * q + i / h; }
+__host__ __device__ inline u64 opk_pos(u64 key, u64 h, u64 q) { return (key % q) * h + key / q; }
+
 __host__ __device__ inline SortGeom sort_geom(u64 count, u32 tile) {
   SortGeom g;
   g.count = count;
@@ -159,7 +166,9 @@ enum CounterSlot : int {
   kCtrCodeBits = kMaxPasses + 5,     // w: bits per character code
   kCtrChars = kMaxPasses + 6,        // c: characters packed in a round-0 key
   kCtrIndexAux = kMaxPasses + 7,     // index builds: the row of $ in the transform
-  kCtrCount = kMaxPasses + 8,
+  kCtrPairI = kMaxPasses + 8,        // sort-based pairing: non-unique items paired this round
+  kCtrPairU = kMaxPasses + 9,        // sort-based pairing: unique items kept for the next round
+  kCtrCount = kMaxPasses + 10,
 };
 
 }  // namespace sa

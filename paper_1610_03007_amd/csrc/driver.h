@@ -73,6 +73,10 @@ struct sa_ctx {
   u64* toff = nullptr;    // batch text offsets on the device
   u64 toff_cap = 0;
   u64* status = nullptr;  // sort look-back: [tiles][radix]
+  // Sort-based pairing (sa_build_sorted_pairs): three item buffers.
+  u64* pair_k[3] = {nullptr, nullptr, nullptr};
+  u32* pair_v[3] = {nullptr, nullptr, nullptr};
+  u64 pair_cap = 0;
   // Small control block: hist_in | hist_run | tickets | counters | plan | present | code.
   void* small = nullptr;
   u32* hist_in = nullptr;   // [passes][kChunks][radix] input-order chunk histograms
@@ -186,6 +190,7 @@ void bind_small(sa_ctx* c, char* p);
 // Initial control words of a freshly allocated control block (synchronous).
 sa_status init_small(char* p);
 void drop_graphs(sa_ctx* c);
+void free_pair_workspace(sa_ctx* c);
 hipEvent_t take_event(sa_ctx* c);
 
 // Brackets one launch with events when tracing.

@@ -813,6 +813,7 @@ sa_status sa_ctx_destroy(sa_ctx* ctx) {
   if (!ctx) return SA_OK;
   (void)hipSetDevice(ctx->device);
   free_workspace(ctx);
+  free_pair_workspace(ctx);
   drop_graphs(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   (void)hipFree(ctx->small);

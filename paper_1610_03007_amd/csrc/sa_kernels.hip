@@ -1287,7 +1287,9 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const bool scatter = (mode & kRerankScatterIsa) != 0;
   const bool isa_only = (mode & kRerankIsaOnly) != 0;
   const bool pair_out = (mode & kRerankPairOut) != 0;
-  const bool no_survivors = isa_only || pair_out;
+  const bool emit = (mode & kRerankEmit) != 0;
+  const bool no_survivors = isa_only || pair_out || emit;
+  const u64 emit_at = emit ? *a.emit_base : 0;
   const int tid = threadIdx.x;
   const int lane = lane_id();
   const int wave = tid / kWave;
@@ -1464,6 +1466,11 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     }
     if (pair_out) {
       a.pair_out[e] = (nr << 32) | u64(v[r]);
+      continue;
+    }
+    if (emit) {
+      a.emit_keys[emit_at + e] = opk_key(v[r], a.emit_h, a.emit_q) | (uniq ? kUniqueBit : 0);
+      a.emit_vals[emit_at + e] = u32(nr);
       continue;
     }
     // The ISA already holds every active suffix's previous name, so a name
