@@ -172,6 +172,41 @@ sa_status sa_last_build_info(const sa_ctx* ctx, sa_build_info* out);
 sa_status sa_build_rounds(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t max_rounds,
                           uint32_t* d_sa, uint32_t* d_isa, void* stream);
 
+/* Prefix doubling with discarding by sorting (Section 2.1, Alg. 5 with the
+ * comparator of Eq. 1 and the Unique / NPairs / renaming functions of Alg. 6):
+ * the same suffix array as sa_build, built without an inverse suffix array.
+ * Each round sorts the working items by (i mod h, i div h) so that suffix
+ * i + h follows suffix i, pairs neighbours in one scan, keeps a unique item
+ * only while the two items before it are non-unique (its name may still be
+ * needed), sorts the non-unique items by name pair and renames them. This is
+ * the form for a text sharded across devices, where ISA[i + h] is remote; on
+ * one device it moves more bytes than sa_build.
+ *   h_counts: host u64[4 * max_rounds] or NULL: for round k = 1, 2, ... the
+ *             items sorted |P|, the non-unique items paired |I|, the items
+ *             discarded (final) and the unique items kept.
+ * Other arguments, errors and limits as sa_build; rounds and passes in
+ * sa_last_build_info (active[k] = |P| of round k). */
+sa_status sa_build_sorted_pairs(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t sigma,
+                                uint32_t* d_sa, uint64_t* h_counts, uint32_t max_rounds,
+                                void* stream);
+
+/* Suffix array by the difference cover algorithm DC3 (Section 2.2, Alg. 7): a
+ * second suffix sorter, recursive on the suffixes at positions i mod 3 != 0.
+ * Each level sorts their character triples and names them; equal names send
+ * the names (positions 1, 4, 7, ... then 2, 5, 8, ...) to the next level,
+ * whose suffix array orders them; the suffixes at i mod 3 == 0 are sorted by
+ * (T[i], rank of i + 1), and the two lists are merged with the method's
+ * comparison. Same result as sa_build.
+ *   d_text, n, d_sa, stream: as sa_build (n < 2^32).
+ *   d_rank12: device u32[n] or NULL: the top level's sample ranks, for each
+ *             position i with i mod 3 != 0 the 1-based rank of suffix i among
+ *             those suffixes, 0 where i mod 3 == 0.
+ * Levels in sa_last_build_info: rounds = recursion levels, active[k] = the
+ * length of the string at level k. Each level allocates its arrays (about
+ * 4 bytes per symbol each) on top of the context's workspace. */
+sa_status sa_build_dc3(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t* d_sa,
+                       uint32_t* d_rank12, void* stream);
+
 /* The sorting step on its own (the Sort of Alg. 1 and 5): stable LSD radix
  * sort of `count` (key, value) pairs in place, ordered by the low `key_bits`
  * bits of the key (1..64; higher bits must be zero). d_keys: device u64[count],

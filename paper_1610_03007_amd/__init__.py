@@ -98,6 +98,41 @@ class SuffixArrayBuilder:
                   "sa_build")
         return sa
 
+    def build_sorted_pairs(self, text: torch.Tensor, out: torch.Tensor | None = None,
+                           sigma: int = 256):
+        """Suffix array by prefix doubling with discarding by sorting (no inverse
+        suffix array; ``sa_build_sorted_pairs``). Returns (sa, counts): counts
+        is a (rounds, 4) uint64 array of |P|, |I|, discarded, kept per round."""
+        import numpy as np
+        t = self._text(text)
+        n = t.numel()
+        sa = self._out(out, n, "out")
+        counts = np.zeros((64, 4), dtype=np.uint64)
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_build_sorted_pairs(
+                self._ctx, ctypes.c_void_p(t.data_ptr()), n, sigma,
+                ctypes.c_void_p(sa.data_ptr()), counts.ctypes.data_as(ctypes.c_void_p), 64,
+                _stream_handle(self.device)), "sa_build_sorted_pairs")
+        rounds = self.last_info()["rounds"] if n else 1
+        return sa, counts[:max(0, rounds - 1)]
+
+    def build_dc3(self, text: torch.Tensor, out: torch.Tensor | None = None,
+                  with_ranks: bool = False):
+        """Suffix array by DC3 (``sa_build_dc3``). With ``with_ranks`` returns
+        (sa, rank12): the top level's sample ranks by position (0 at positions
+        divisible by 3)."""
+        t = self._text(text)
+        n = t.numel()
+        sa = self._out(out, n, "out")
+        r12 = torch.empty(n, dtype=torch.int32, device=self.device) if with_ranks else None
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_build_dc3(self._ctx, ctypes.c_void_p(t.data_ptr()), n,
+                                         ctypes.c_void_p(sa.data_ptr()),
+                                         ctypes.c_void_p(r12.data_ptr() if r12 is not None
+                                                         else None),
+                                         _stream_handle(self.device)), "sa_build_dc3")
+        return (sa, r12) if with_ranks else sa
+
     def build_batch(self, texts: torch.Tensor, offsets, out: torch.Tensor | None = None):
         """Suffix arrays of many texts in one batched build.
 
