@@ -184,7 +184,8 @@ def kernel_table(stats: dict, steps: int) -> dict:
     return out
 
 
-def run_build(name: str, steps: int, warmup: int, cpu: bool, sort_items: int = 0) -> dict:
+def run_build(name: str, steps: int, warmup: int, cpu: bool, sort_items: int = 0,
+              per_text: bool = True) -> dict:
     """Times `steps` builds of one workload (HIP events on the build stream)."""
     import torch
 
@@ -276,7 +277,7 @@ def run_build(name: str, steps: int, warmup: int, cpu: bool, sort_items: int = 0
     log(f"{name}: {ms:.3f} ms/build, {value:.1f} Msuffixes/s, whole-build "
         f"{rec['whole_build_roofline']['frac']:.3f} of peak, sweep "
         f"{rec['sweep_roofline']['frac']:.3f}")
-    if offsets is not None:
+    if offsets is not None and per_text:
         # Per-text baseline on the same GPU: one sa_build per text, in order.
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
@@ -289,17 +290,182 @@ def run_build(name: str, steps: int, warmup: int, cpu: bool, sort_items: int = 0
         e1.record(stream)
         torch.cuda.synchronize()
         per_text_ms = e0.elapsed_time(e1)
-        per_text = n / (per_text_ms / 1e3) / 1e6
+        pt_rate = n / (per_text_ms / 1e3) / 1e6
         rec["texts"] = int(offsets.size - 1)
-        rec["per_text"] = {"msuffixes_s": round(per_text, 2), "ms": round(per_text_ms, 2)}
-        rec["batched_vs_per_text"] = round(value / per_text, 3)
-        log(f"{name}: per-text {per_text:.1f} Msuffixes/s -> batched x{value / per_text:.2f}")
+        rec["per_text"] = {"msuffixes_s": round(pt_rate, 2), "ms": round(per_text_ms, 2)}
+        rec["batched_vs_per_text"] = round(value / pt_rate, 3)
+        log(f"{name}: per-text {pt_rate:.1f} Msuffixes/s -> batched x{value / pt_rate:.2f}")
     b.close()
     del d_text, d_sa
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     rec["cpu_baseline"] = cpu_rows(name, text, offsets) if cpu else None
     return rec
+
+
+# ---------------------------------------------------------------------------
+# Rows beyond the headline path: prefix quadrupling, DC3, sort-based
+# discarding and the index structures built from a suffix array. Each is
+# checked against the headline path's suffix array of the same text and timed
+# with HIP events; its kernel table comes from as many traced runs.
+
+def _timed(fn, steps: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def _traced(b, fn, steps: int) -> dict:
+    import torch
+    b.reset_stats()
+    b.set_trace(True)
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    b.set_trace(False)
+    return kernel_table(b.kernel_stats(), steps)
+
+
+def _summary(name: str, n: int, ms: float, table: dict, extra: dict) -> dict:
+    alg = sum(v["gb_s"] * v["ms_per_step"] / 1e3 for v in table.values())  # GB per step
+    rec = {"workload": name, "n": n, "ms_per_build": round(ms, 4),
+           "msuffixes_s": round(n / (ms / 1e3) / 1e6, 2),
+           "whole_build_roofline": {
+               "bound": "hbm", "algorithmic_gb": round(alg, 3),
+               "achieved": round(alg / (ms / 1e3), 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(alg / (ms / 1e3) / HBM_PEAK_GBS, 4)},
+           "kernels": table}
+    rec.update(extra)
+    log(f"{name}: {ms:.3f} ms, {rec['msuffixes_s']} Msuffixes/s, whole "
+        f"{rec['whole_build_roofline']['frac']:.3f} of peak")
+    return rec
+
+
+def run_extras(steps: int = 2, warmup: int = 1) -> dict:
+    import numpy as np
+    import torch
+
+    from paper_1610_03007_amd import SuffixArrayBuilder
+    dev = torch.device("cuda", 0)
+    out = {}
+    b = SuffixArrayBuilder(0)
+
+    # Prefix quadrupling on the repetitive 2^30 text (the most rounds).
+    text, _ = make_text("repetitive_1g")
+    n = int(text.size)
+    d_text = torch.from_numpy(text).to(dev)
+    ref = b.build(d_text)
+    dbl = b.last_info()
+    b.set_tuning(prefix_mult=4)
+    sa = torch.empty_like(ref)
+    ms = _timed(lambda: b.build(d_text, out=sa), steps, warmup)
+    info = b.last_info()
+    same = bool(torch.equal(sa, ref))
+    table = _traced(b, lambda: b.build(d_text, out=sa), steps)
+    b.auto_tuning()
+    out["repetitive_1g_quadrupling"] = _summary(
+        "repetitive_1g_quadrupling", n, ms, table,
+        {"rounds": info["rounds"], "rounds_doubling": dbl["rounds"],
+         "active_per_round": info["active"], "passes_per_round": info["passes_run"],
+         "equals_doubling_sa": same})
+    del d_text, ref, sa
+    torch.cuda.empty_cache()
+
+    # DC3, sort-based discarding and the index structures on the Markov 2^28 text.
+    text, _ = make_text("markov_256m")
+    n = int(text.size)
+    d_text = torch.from_numpy(text).to(dev)
+    ref = b.build(d_text)
+    torch.cuda.synchronize()
+    sa = torch.empty_like(ref)
+    ms = _timed(lambda: b.build_dc3(d_text, out=sa), steps, warmup)
+    info = b.last_info()
+    same = bool(torch.equal(sa, ref))
+    table = _traced(b, lambda: b.build_dc3(d_text, out=sa), 1)
+    out["markov_256m_dc3"] = _summary(
+        "markov_256m_dc3", n, ms, table,
+        {"levels": info["rounds"], "level_sizes": info["active"], "equals_doubling_sa": same})
+    counts = [None]
+
+    def sp():
+        _, counts[0] = b.build_sorted_pairs(d_text, out=sa)
+    ms = _timed(sp, steps, warmup)
+    info = b.last_info()
+    same = bool(torch.equal(sa, ref))
+    table = _traced(b, sp, steps)
+    out["markov_256m_sorted_pairs"] = _summary(
+        "markov_256m_sorted_pairs", n, ms, table,
+        {"rounds": info["rounds"], "counts_p_i_discarded_kept": counts[0].astype(int).tolist(),
+         "equals_doubling_sa": same})
+
+    # Index structures from the suffix array: bytes per suffix as counted by
+    # the kernels (LCP 28, BWT 10, FM occurrence samples 1 + 8 sigma / 256).
+    lcp = torch.empty_like(ref)
+    ms_lcp = _timed(lambda: b.lcp(d_text, ref, out=lcp), steps, warmup)
+    ms_bwt = _timed(lambda: b.bwt(d_text, ref), steps, warmup)
+    fm = [None]
+
+    def fm_build():
+        if fm[0] is not None:
+            fm[0].close()
+        fm[0] = b.fm_index(d_text, ref)
+    ms_fm = _timed(fm_build, steps, warmup)
+    rng = np.random.default_rng(8)
+    starts = rng.integers(0, n - 64, 1 << 16)
+    pats = [text[s:s + int(rng.integers(4, 33))].tobytes() for s in starts]
+    ranges = fm[0].count(pats)
+    torch.cuda.synchronize()
+    ms_q = _timed(lambda: fm[0].count(pats), steps, warmup)
+    sigma = fm[0].info()["sigma"]
+    fm[0].close()
+    # Parity at full size on sampled rows: LCP by direct comparison, pattern
+    # ranges contain the pattern's own start position.
+    lc = lcp.cpu().numpy().view(np.uint32)
+    sh = ref.cpu().numpy().view(np.uint32)
+    rows = rng.integers(1, n, 2000)
+
+    def lcp_direct(a: int, c: int, cap: int = 1 << 14) -> int:
+        x, y = text[a:a + cap], text[c:c + cap]
+        m = min(x.size, y.size)
+        neq = np.nonzero(x[:m] != y[:m])[0]
+        return int(neq[0]) if neq.size else (m if m < cap else -1)  # -1: at least cap
+
+    lcp_ok = True
+    for j in rows:
+        d = lcp_direct(int(sh[j - 1]), int(sh[j]))
+        lcp_ok &= (int(lc[j]) >= (1 << 14)) if d < 0 else int(lc[j]) == d
+    rg = ranges.cpu().numpy()
+    isa_pos = np.empty(n, dtype=np.int64)
+    isa_pos[sh] = np.arange(n)
+    q_ok = bool(all(rg[k, 0] <= isa_pos[starts[k]] < rg[k, 1] for k in range(0, len(pats), 64)))
+    idx = {
+        "lcp": {"ms": round(ms_lcp, 4), "gb_s": round(28.0 * n / ms_lcp / 1e6, 1)},
+        "bwt": {"ms": round(ms_bwt, 4), "gb_s": round(10.0 * n / ms_bwt / 1e6, 1)},
+        "fm_build": {"ms": round(ms_fm, 4),
+                     "gb_s": round((1.0 + 8.0 * sigma / 256) * n / ms_fm / 1e6, 1)},
+        "fm_count": {"patterns": len(pats), "ms": round(ms_q, 4),
+                     "mpatterns_s": round(len(pats) / ms_q / 1e3, 2)},
+        "lcp_sampled_rows_match": lcp_ok,
+        "pattern_ranges_hold_their_start": q_ok,
+    }
+    for k in ("lcp", "bwt", "fm_build"):
+        idx[k]["frac"] = round(idx[k]["gb_s"] / HBM_PEAK_GBS, 4)
+    log(f"index: {idx}")
+    out["markov_256m_index"] = idx
+    b.close()
+    del d_text, ref, sa, lcp
+    torch.cuda.empty_cache()
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -438,7 +604,7 @@ def run_server_load(pools, stream, warm: float, mode: str, digests: dict | None 
     return ls, done_sufs[0], window, stats, mismatches[0]
 
 
-def run_serve(seconds: float) -> dict:
+def run_serve(seconds: float, legs=("server", "per_text")) -> dict:
     import numpy as np
     t0 = time.perf_counter()
     pools = serve_pools()
@@ -448,7 +614,7 @@ def run_serve(seconds: float) -> dict:
     warm = min(2.0, seconds / 4)
     res = {}
     digests: dict = {}
-    for mode in ("server", "per_text"):
+    for mode in legs:
         ls, sufs, window, stats, bad = run_server_load(pools, stream, warm, mode, digests)
         res[mode] = {
             "requests": int(ls.size),
@@ -466,12 +632,15 @@ def run_serve(seconds: float) -> dict:
     # Capacity: the first requests of the stream all submitted at once.
     cap_n = int(np.searchsorted(stream[0], min(3.0, seconds)))
     sat = (np.zeros(cap_n), stream[1][:cap_n], stream[2][:cap_n], stream[3][:cap_n])
-    for mode in ("server", "per_text"):
+    for mode in legs:
         ls, sufs, window, _, _ = run_server_load(pools, sat, 0.0, mode)
         res[mode]["capacity_msuffixes_s"] = round(sufs / window / 1e6, 2)
         res[mode]["capacity_requests"] = cap_n
         log(f"serve {mode} capacity: {res[mode]['capacity_msuffixes_s']} Msuffixes/s")
     offered = float(stream[1][stream[0] >= warm].sum()) / (seconds - warm) / 1e6
+    if tuple(legs) != ("server", "per_text"):
+        return {"workload": "serve", "seconds": seconds, "warmup_s": warm,
+                "offered_msuffixes_s": round(offered, 2), "legs": list(legs), **res}
     return {
         "workload": "serve",
         "description": WORKLOADS["serve"],
@@ -557,6 +726,14 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="all", choices=["all"] + sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle rows")
+    ap.add_argument("--no-per-text", action="store_true",
+                    help="batch workload: skip the one-sa_build-per-text baseline (profiling)")
+    ap.add_argument("--serve-legs", default="server,per_text",
+                    help="serve workload: which legs to run (server, per_text or both)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip quadrupling, DC3, sort-based discarding and the index rows")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="run only those rows (one JSON object)")
     ap.add_argument("--sort-items", type=int, default=0,
                     help="radix-sort items per thread (0 = library default)")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -580,8 +757,13 @@ def main() -> int:
         return tune_main(args)
     cpu = not args.no_cpu
 
+    if args.extras_only:
+        print(json.dumps(run_extras()), flush=True)
+        return 0
     if args.workload == "serve":
-        rec = run_serve(args.serve_seconds)
+        rec = run_serve(args.serve_seconds, tuple(x for x in args.serve_legs.split(",") if x))
+        if "msuffixes_s" not in rec:
+            rec["msuffixes_s"] = rec[rec["legs"][0]]["msuffixes_s"]
         out = {"metric": METRIC, "value": rec["msuffixes_s"], "unit": "Msuffixes/s",
                "n_gpus": 1, "steps": 1, "warmup": 0,
                "ms_per_step": round(args.serve_seconds * 1e3, 1), "higher_is_better": True,
@@ -602,11 +784,14 @@ def main() -> int:
                 steps, warmup = min(steps, 3), min(warmup, 1)
             elif name == "dna_1m":
                 steps = max(steps, 20)
-        records[name] = run_build(name, steps, warmup, cpu, args.sort_items)
+        records[name] = run_build(name, steps, warmup, cpu, args.sort_items,
+                                  per_text=not args.no_per_text)
     head = names[0]
     out = headline(records[head], args.steps, args.warmup, head)
     if args.workload == "all":
         records["serve"] = run_serve(args.serve_seconds)
+        if not args.no_extras:
+            records.update(run_extras())
     out["configs"] = {k: v for k, v in records.items() if k != head}
     out["batch"] = ({"texts": records[head]["texts"],
                      "batched_msuffixes_s": records[head]["msuffixes_s"],
