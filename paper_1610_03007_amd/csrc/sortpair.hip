@@ -206,9 +206,16 @@ sa_status build_sortpair(sa_ctx* c, const u8* text, u64 n, u32* d_sa, u64* h_cou
                          c->plan, c->ctl, n, h, q, b, h2, q2, c->keysA, c->valsA, c->pair_k[W],
                          c->pair_v[W], d_sa, c->counters);
     }
+    // Tracing attributes bytes per launch, so it reads the pair count back.
+    u64 traced = pcount;
+    if (c->trace) {
+      st = readback(c, s);
+      if (st != SA_OK) return st;
+      traced = c->h_counters[kCtrPairI];
+    }
     // The non-unique items, by name pair; renamed into the next round's items.
     begin_sort(c, pcount, c->counters + kCtrPairI, nullptr, npass_i, true, s);
-    sort_passes(c, full, pcount, npass_i, 1, int(k) + kPlanRowSecond, pcount, s);
+    sort_passes(c, full, pcount, npass_i, 1, int(k) + kPlanRowSecond, traced, s);
     {
       RerankArgs a = single_args(pcount, n, b, kRerankEmit);
       a.emit_keys = c->pair_k[W];
@@ -216,7 +223,7 @@ sa_status build_sortpair(sa_ctx* c, const u8* text, u64 n, u32* d_sa, u64* h_cou
       a.emit_base = c->counters + kCtrPairU;
       a.emit_h = h2;
       a.emit_q = q2;
-      run_rerank(c, full, a, d_sa, pcount, pcount, s);
+      run_rerank(c, full, a, d_sa, pcount, traced, s);
     }
     st = readback(c, s);
     if (st != SA_OK) return st;
