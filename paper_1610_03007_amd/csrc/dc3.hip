@@ -15,8 +15,8 @@
 //   4. Merge the two sorted lists with the comparison of the method: against a
 //      suffix j = 1 mod 3, compare (x[i], rank(i+1)); against j = 2 mod 3,
 //      (x[i], x[i+1], rank(i+2)) -- each side reaches a sample rank, so no
-//      comparison ties. Every element finds its place in the other list by
-//      binary search and goes to SA[own index + elements below it].
+//      comparison ties. The merge splits the output into tiles along the merge
+//      path (a binary search per tile boundary) and merges each tile in LDS.
 //
 // The sorts are the library's LSD radix sort. A triple of b-bit symbols fits a
 // 64-bit key while 3b <= 64 (the bytes of the text: 27 bits); wider levels
@@ -116,69 +116,127 @@ __device__ inline u64 dc3_rank(const Dc3Str<T>& str, const u32* __restrict__ ran
   return p < str.m ? rankp[p] : 0;
 }
 
-// Suffix i (i mod 3 == 0) below sample suffix j.
+// Step 4, merge. Every suffix of both sorted lists gets a comparison record
+// (x[p], x[p+1], rank(p+1), rank(p+2)) and its position; a mod-0 record A
+// and a sample record B compare as the method says: against B at j = 1 mod 3,
+// (x, rank(p+1)); against j = 2 mod 3, (x, x[p+1], rank(p+2)). Records are
+// gathered once (random reads), then the merge reads them in order.
+struct Dc3Rec {
+  u32 c0, c1, r1, r2;
+};
+
 template <typename T>
-__device__ inline bool dc3_less0(const Dc3Str<T>& str, const u32* __restrict__ rankp, u64 i,
-                                 u64 j) {
-  const u64 ci = str.sym(i), cj = str.sym(j);
-  if (ci != cj) return ci < cj;
-  if (j % 3 == 1) return dc3_rank(str, rankp, i + 1) < dc3_rank(str, rankp, j + 1);
-  const u64 di = str.sym(i + 1), dj = str.sym(j + 1);
-  if (di != dj) return di < dj;
-  return dc3_rank(str, rankp, i + 2) < dc3_rank(str, rankp, j + 2);
+__device__ inline Dc3Rec dc3_rec(const Dc3Str<T>& str, const u32* __restrict__ rankp, u64 p) {
+  return Dc3Rec{u32(str.sym(p)), u32(str.sym(p + 1)), u32(dc3_rank(str, rankp, p + 1)),
+                u32(dc3_rank(str, rankp, p + 2))};
 }
 
-// Step 4: element t < n0 is the t-th suffix of the sorted mod-0 list (values
-// of the final sort buffer), element n0 + r the sample suffix of rank r + 1.
+// A (mod 0) below B (sample suffix at position pb).
+__device__ inline bool dc3_rec_less(const Dc3Rec& a, const Dc3Rec& b, u64 pb) {
+  if (a.c0 != b.c0) return a.c0 < b.c0;
+  if (pb % 3 == 1) return a.r1 < b.r1;
+  if (a.c1 != b.c1) return a.c1 < b.c1;
+  return a.r2 < b.r2;
+}
+
 template <typename T>
-__global__ __launch_bounds__(256) void dc3_merge_kernel(Dc3Str<T> str, u64 n0, u64 n12,
-                                                        const u32* __restrict__ vA,
-                                                        const u32* __restrict__ vB,
-                                                        const SortPlan* __restrict__ plan,
-                                                        const u32* __restrict__ rankp,
-                                                        const u32* __restrict__ byrank,
-                                                        u32* __restrict__ sa,
-                                                        u64* __restrict__ counters) {
+__global__ __launch_bounds__(256) void dc3_records_kernel(
+    Dc3Str<T> str, u64 n0, u64 n12, const u32* __restrict__ vA, const u32* __restrict__ vB,
+    const SortPlan* __restrict__ plan, const u32* __restrict__ rankp,
+    const u32* __restrict__ byrank, Dc3Rec* __restrict__ rec0, u32* __restrict__ pos0,
+    Dc3Rec* __restrict__ rec12) {
   const u32* s0 = plan->final_buf ? vB : vA;
-  const u64 total = n0 + n12;
   const u64 stride = u64(gridDim.x) * blockDim.x;
-  bool bad = false;
-  for (u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x; t < total; t += stride) {
-    u64 lo = 0, hi, own, p;
+  for (u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x; t < n0 + n12; t += stride) {
     if (t < n0) {
-      // Sample suffixes below suffix i: the first rank whose suffix is not.
-      p = s0[t];
-      own = t;
-      hi = n12;
-      while (lo < hi) {
-        const u64 mid = (lo + hi) >> 1;
-        if (!dc3_less0(str, rankp, p, byrank[mid]))
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
+      const u32 i = s0[t];
+      pos0[t] = i;
+      rec0[t] = dc3_rec(str, rankp, i);
     } else {
-      // Mod-0 suffixes below sample suffix p.
-      own = t - n0;
-      p = byrank[own];
-      hi = n0;
-      while (lo < hi) {
-        const u64 mid = (lo + hi) >> 1;
-        if (dc3_less0(str, rankp, s0[mid], p))
-          lo = mid + 1;
-        else
-          hi = mid;
-      }
+      rec12[t - n0] = dc3_rec(str, rankp, byrank[t - n0]);
     }
-    const u64 at = own + lo;
-    if (at < str.m && p < str.m)
-      sa[at] = u32(p);
-    else
-      bad = true;
   }
-  if (bad)
-    atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
-             (unsigned long long)kErrBounds);
+}
+
+// Merge path: split[t] = how many mod-0 suffixes are among the first
+// min(t * tile, m) suffixes of the merged order.
+__global__ __launch_bounds__(256) void dc3_partition_kernel(
+    const Dc3Rec* __restrict__ rec0, const Dc3Rec* __restrict__ rec12,
+    const u32* __restrict__ byrank, u64 n0, u64 n12, u64 tile, u64 ntiles,
+    u64* __restrict__ split) {
+  const u64 m = n0 + n12;
+  for (u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x; t <= ntiles;
+       t += u64(gridDim.x) * blockDim.x) {
+    const u64 d = t * tile < m ? t * tile : m;
+    u64 lo = d > n12 ? d - n12 : 0, hi = d < n0 ? d : n0;
+    while (lo < hi) {
+      const u64 mid = (lo + hi) >> 1;
+      const u64 b = d - 1 - mid;
+      if (dc3_rec_less(rec0[mid], rec12[b], byrank[b]))
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    split[t] = lo;
+  }
+}
+
+// One workgroup per tile of kDc3Tile merged suffixes: both input runs in LDS,
+// each thread finds its start on the merge path and merges kDc3Items
+// suffixes, and the tile's part of the suffix array is written in order.
+constexpr int kDc3Items = 4;
+constexpr int kDc3Tile = 256 * kDc3Items;
+
+__global__ __launch_bounds__(256) void dc3_merge_tile_kernel(
+    const Dc3Rec* __restrict__ rec0, const u32* __restrict__ pos0,
+    const Dc3Rec* __restrict__ rec12, const u32* __restrict__ byrank,
+    const u64* __restrict__ split, u64 n0, u64 n12, u32* __restrict__ sa,
+    u64* __restrict__ counters) {
+  __shared__ Dc3Rec s_a[kDc3Tile], s_b[kDc3Tile];
+  __shared__ u32 s_pa[kDc3Tile], s_pb[kDc3Tile], s_out[kDc3Tile];
+  const u64 m = n0 + n12;
+  const u64 t = blockIdx.x;
+  const u64 d0 = t * kDc3Tile;
+  const u64 d1 = d0 + kDc3Tile < m ? d0 + kDc3Tile : m;
+  const u64 a0 = split[t], a1 = split[t + 1];
+  const u64 b0 = d0 - a0, b1 = d1 - a1;
+  const u32 na = u32(a1 - a0), nb = u32(b1 - b0), nt = u32(d1 - d0);
+  if (a1 < a0 || b1 < b0 || na + nb != nt || nt > u32(kDc3Tile)) {
+    if (threadIdx.x == 0)
+      atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+               (unsigned long long)kErrBounds);
+    return;
+  }
+  for (u32 k = threadIdx.x; k < na; k += blockDim.x) {
+    s_a[k] = rec0[a0 + k];
+    s_pa[k] = pos0[a0 + k];
+  }
+  for (u32 k = threadIdx.x; k < nb; k += blockDim.x) {
+    s_b[k] = rec12[b0 + k];
+    s_pb[k] = byrank[b0 + k];
+  }
+  __syncthreads();
+  const u32 dd = threadIdx.x * kDc3Items;
+  if (dd < nt) {
+    u32 lo = dd > nb ? dd - nb : 0, hi = dd < na ? dd : na;
+    while (lo < hi) {
+      const u32 mid = (lo + hi) >> 1;
+      const u32 b = dd - 1 - mid;
+      if (dc3_rec_less(s_a[mid], s_b[b], s_pb[b]))
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    u32 ia = lo, ib = dd - lo;
+#pragma unroll
+    for (int k = 0; k < kDc3Items; ++k) {
+      if (dd + k >= nt) break;
+      const bool take_a = ib >= nb || (ia < na && dc3_rec_less(s_a[ia], s_b[ib], s_pb[ib]));
+      s_out[dd + k] = take_a ? s_pa[ia++] : s_pb[ib++];
+    }
+  }
+  __syncthreads();
+  for (u32 k = threadIdx.x; k < nt; k += blockDim.x) sa[d0 + k] = s_out[k];
 }
 
 // rank12[p] = rankp[p] for sample positions, 0 at positions divisible by 3.
@@ -199,7 +257,15 @@ struct Dc3Level {
   u32* tmp = nullptr;     // sorted order when the names are unique
   u32* rankp = nullptr;   // sample ranks by position
   u32* byrank = nullptr;  // sample positions by rank
+  Dc3Rec* rec0 = nullptr;  // comparison records of the sorted mod-0 suffixes
+  Dc3Rec* rec12 = nullptr; // and of the sample suffixes by rank
+  u32* pos0 = nullptr;
+  u64* split = nullptr;    // merge-path splits
   ~Dc3Level() {
+    (void)hipFree(rec0);
+    (void)hipFree(rec12);
+    (void)hipFree(pos0);
+    (void)hipFree(split);
     (void)hipFree(child);
     (void)hipFree(childsa);
     (void)hipFree(tmp);
@@ -294,11 +360,25 @@ sa_status dc3_level(sa_ctx* c, const T* x, u64 m, u32 add, u64 max_sym, u32* sa,
   }
   run_sort(c, full, n0, npass_for(c, bsym + brank), 1, 0, s);
 
-  // Step 4: merge.
+  // Step 4: comparison records, merge-path splits, merge by tiles.
+  const u64 ntiles = ceil_div(m, u64(kDc3Tile));
+  if (!dev_alloc(&L.rec0, n0) || !dev_alloc(&L.rec12, std::max<u64>(n12, 1)) ||
+      !dev_alloc(&L.pos0, n0) || !dev_alloc(&L.split, ntiles + 1))
+    return SA_ENOMEM;
   {
-    Tracer t(c, s, SA_KERNEL_OTHER, double(m) * 8.0);
-    hipLaunchKernelGGL((dc3_merge_kernel<T>), dim3(stream_grid(c, m, 256)), dim3(256), 0, s, str,
-                       n0, n12, full.vA, full.vB, c->plan, L.rankp, L.byrank, sa, c->counters);
+    // Position in; two characters and two ranks gathered; a 16-byte record out.
+    Tracer t(c, s, SA_KERNEL_OTHER, double(m) * 32.0);
+    hipLaunchKernelGGL((dc3_records_kernel<T>), dim3(stream_grid(c, m, 256)), dim3(256), 0, s,
+                       str, n0, n12, full.vA, full.vB, c->plan, L.rankp, L.byrank, L.rec0, L.pos0,
+                       L.rec12);
+    hipLaunchKernelGGL(dc3_partition_kernel, dim3(u32(ceil_div(ntiles + 1, 256))), dim3(256), 0,
+                       s, L.rec0, L.rec12, L.byrank, n0, n12, u64(kDc3Tile), ntiles, L.split);
+  }
+  {
+    // Records and positions in, the suffix array out.
+    Tracer t(c, s, SA_KERNEL_OTHER, double(m) * 24.0);
+    hipLaunchKernelGGL(dc3_merge_tile_kernel, dim3(u32(ntiles)), dim3(256), 0, s, L.rec0, L.pos0,
+                       L.rec12, L.byrank, L.split, n0, n12, sa, c->counters);
   }
   if (rank_out)
     hipLaunchKernelGGL(dc3_rank_out_kernel, dim3(stream_grid(c, m, 256)), dim3(256), 0, s,
