@@ -93,8 +93,16 @@ struct SortGeom {
 // with q = ceil(n / h), so that positions ordered by key are ordered by
 // residue modulo h, then by quotient: suffix i + h directly follows suffix i
 // when both are present. Keys stay below h * q <= n + h - 1.
-__host__ __device__ inline u64 opk_key(u64 i, u64 h, u64 q) { return (i % h) * q + i / h; }
-__host__ __device__ inline u64 opk_pos(u64 key, u64 h, u64 q) { return (key % q) * h + key / q; }
+// (32-bit division when the operands fit: 64-bit division is a long
+// instruction sequence on the GPU.)
+__host__ __device__ inline u64 opk_key(u64 i, u64 h, u64 q) {
+  if ((i | h) >> 32 == 0) return u64(u32(i) % u32(h)) * q + u32(i) / u32(h);
+  return (i % h) * q + i / h;
+}
+__host__ __device__ inline u64 opk_pos(u64 key, u64 h, u64 q) {
+  if ((key | q) >> 32 == 0) return u64(u32(key) % u32(q)) * h + u32(key) / u32(q);
+  return (key % q) * h + key / q;
+}
 
 __host__ __device__ inline SortGeom sort_geom(u64 count, u32 tile) {
   SortGeom g;
