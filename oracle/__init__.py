@@ -16,8 +16,9 @@ compiles it with g++ on demand and wraps it with ctypes over numpy arrays:
   discarding by sorting (Alg. 5 with the comparator of Eq. 1 and Alg. 6): the
   comparator's position order, the suffix array with per-round item counts, and
   the working items of one round.
-* :func:`dc3_sample_ranks` -- the ranks among themselves of the suffixes that
-  start at positions not divisible by 3 (the sample of DC3), by definition.
+* :func:`dc3_sample_ranks`, :func:`dcx_sample_ranks` -- the ranks among
+  themselves of the suffixes that start in a difference cover sample (DC3:
+  positions not divisible by 3; DC7: positions 0, 1, 3 mod 7), by definition.
 * :func:`prefix_ranks` -- the closed form of the names for prefix length ``h``:
   1 + the number of suffixes whose padded length-``h`` prefix is smaller.
 * :func:`brute_sa` -- the definition: sort all suffixes lexicographically.
@@ -78,7 +79,8 @@ def configure(lib: ctypes.CDLL) -> ctypes.CDLL:
     lib.oracle_pdd_sa.argtypes = [u8p, u64, u64, u32p, u64p, u64, u64p]
     lib.oracle_pdd_round.argtypes = [u8p, u64, u64, u64, u32p, u32p, u8p, u64p]
     lib.oracle_dc3_sample_ranks.argtypes = [u8p, u64, u32p, u32p]
-    for f in ("oracle_dc3_sample_ranks", "oracle_opk_order", "oracle_pdd_sa", "oracle_pdd_round","oracle_sa", "oracle_pd_names", "oracle_prefix_ranks", "oracle_pa_names",
+    lib.oracle_dcx_sample_ranks.argtypes = [u8p, u64, ctypes.c_uint32, ctypes.c_uint32, u32p]
+    for f in ("oracle_dc3_sample_ranks", "oracle_dcx_sample_ranks", "oracle_opk_order", "oracle_pdd_sa", "oracle_pdd_round","oracle_sa", "oracle_pd_names", "oracle_prefix_ranks", "oracle_pa_names",
               "oracle_pa_sa",
               "oracle_brute_sa", "oracle_check_sa", "oracle_num_threads",
               "oracle_lcp", "oracle_bwt", "oracle_sa_interval"):
@@ -210,6 +212,20 @@ def dc3_sample_ranks(text) -> tuple[np.ndarray, np.ndarray]:
                                       _p(r2, ctypes.c_uint32)):
         raise ValueError("bad arguments")
     return r1, r2
+
+
+def dcx_sample_ranks(text, x: int, cover) -> np.ndarray:
+    """Per position: the 1-based rank of the suffix among the suffixes starting
+    at positions i with i mod x in ``cover``, 0 elsewhere."""
+    t = _text(text)
+    out = np.zeros(t.size, dtype=np.uint32)
+    mask = 0
+    for d in cover:
+        mask |= 1 << int(d)
+    if _lib().oracle_dcx_sample_ranks(_p(t, ctypes.c_uint8), t.size, x, mask,
+                                      _p(out, ctypes.c_uint32)):
+        raise ValueError("bad arguments")
+    return out
 
 
 def prefix_ranks(text, h: int) -> np.ndarray:

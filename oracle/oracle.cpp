@@ -392,6 +392,25 @@ int oracle_dc3_sample_ranks(const uint8_t* T, uint64_t n, uint32_t* r1, uint32_t
   return 0;
 }
 
+// Difference cover sample ranks for any cover (DC7: X = 7, D = {0, 1, 3};
+// DC3: X = 3, D = {1, 2}): out[i] = 1-based rank of suffix i among the
+// suffixes whose start i has i mod X in D, 0 for the others. `dmask` has bit
+// d set for d in D. By definition, from the suffix array.
+int oracle_dcx_sample_ranks(const uint8_t* T, uint64_t n, uint32_t X, uint32_t dmask,
+                            uint32_t* out) {
+  if (n >= (uint64_t(1) << 32) || X == 0 || X > 32) return 1;
+  if (n == 0) return 0;
+  std::vector<uint32_t> sa(n);
+  oracle_sa(T, n, sa.data());
+  uint32_t rank = 0;
+  for (uint64_t i = 0; i < n; ++i) out[i] = 0;
+  for (uint64_t j = 0; j < n; ++j) {
+    const uint64_t i = sa[j];
+    if ((dmask >> (i % X)) & 1u) out[i] = ++rank;
+  }
+  return 0;
+}
+
 // Closed form of the names for prefix length h: ranks[i] = 1 + #{ j :
 // pad_h(j) < pad_h(i) }, where pad_h(i) is T[i, i+h) cut at n (the sentinel
 // ending it). Computed by sorting positions with the padded-prefix comparison.

@@ -212,6 +212,14 @@ def pins_pass() -> bool:
         if r1.tolist() != [rank[i] for i in range(1, n, 3)] or \
                 r2.tolist() != [rank[i] for i in range(2, n, 3)]:
             return False
+        # DC7's cover {0, 1, 3} mod 7 (and DC3's, through the general form).
+        for x, cover in ((7, (0, 1, 3)), (3, (1, 2))):
+            sample = [i for i in py_brute_sa(tt.tobytes()) if i % x in cover]
+            want = [0] * n
+            for k, i in enumerate(sample):
+                want[i] = k + 1
+            if oracle.dcx_sample_ranks(tt, x, cover).tolist() != want:
+                return False
     if oracle.lcp(b"banana", [5, 3, 1, 0, 4, 2]).tolist() != [0, 1, 3, 0, 0, 2]:
         return False
     bw, d = oracle.bwt(b"banana", [5, 3, 1, 0, 4, 2])

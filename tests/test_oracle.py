@@ -230,6 +230,8 @@ MUTANTS = {
     "dc3_rank_zero_based": ("    ++rank;\n    if (i % 3 == 1)", "    if (i % 3 == 1)"),
     "dc3_ranks_swapped": ("      r1[i / 3] = rank;\n    else\n      r2[i / 3] = rank;",
                           "      r2[i / 3] = rank;\n    else\n      r1[i / 3] = rank;"),
+    "dcx_cover_ignored": ("    if ((dmask >> (i % X)) & 1u) out[i] = ++rank;",
+                          "    if ((dmask >> (i % X)) & 1u) out[i] = ++rank; else ++rank;"),
     "brute_signed": ("return std::lexicographical_compare(T + a, T + n, T + b, T + n);",
                      "return std::lexicographical_compare((const signed char*)T + a, "
                      "(const signed char*)T + n, (const signed char*)T + b, "
