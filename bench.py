@@ -304,7 +304,7 @@ def run_build(name: str, steps: int, warmup: int, cpu: bool, sort_items: int = 0
 
 
 # ---------------------------------------------------------------------------
-# Rows beyond the headline path: prefix quadrupling, DC3, sort-based
+# Rows beyond the headline path: prefix quadrupling, DC3, DC7, sort-based
 # discarding and the index structures built from a suffix array. Each is
 # checked against the headline path's suffix array of the same text and timed
 # with HIP events; its kernel table comes from as many traced runs.
@@ -381,7 +381,8 @@ def run_extras(steps: int = 2, warmup: int = 1) -> dict:
     del d_text, ref, sa
     torch.cuda.empty_cache()
 
-    # DC3, sort-based discarding and the index structures on the Markov 2^28 text.
+    # DC3, DC7, sort-based discarding and the index structures on the Markov
+    # 2^28 text.
     text, _ = make_text("markov_256m")
     n = int(text.size)
     d_text = torch.from_numpy(text).to(dev)
@@ -394,6 +395,13 @@ def run_extras(steps: int = 2, warmup: int = 1) -> dict:
     table = _traced(b, lambda: b.build_dc3(d_text, out=sa), 1)
     out["markov_256m_dc3"] = _summary(
         "markov_256m_dc3", n, ms, table,
+        {"levels": info["rounds"], "level_sizes": info["active"], "equals_doubling_sa": same})
+    ms = _timed(lambda: b.build_dc7(d_text, out=sa), steps, warmup)
+    info = b.last_info()
+    same = bool(torch.equal(sa, ref))
+    table = _traced(b, lambda: b.build_dc7(d_text, out=sa), 1)
+    out["markov_256m_dc7"] = _summary(
+        "markov_256m_dc7", n, ms, table,
         {"levels": info["rounds"], "level_sizes": info["active"], "equals_doubling_sa": same})
     counts = [None]
 
@@ -731,7 +739,7 @@ def main() -> int:
     ap.add_argument("--serve-legs", default="server,per_text",
                     help="serve workload: which legs to run (server, per_text or both)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip quadrupling, DC3, sort-based discarding and the index rows")
+                    help="skip quadrupling, DC3, DC7, sort-based discarding and the index rows")
     ap.add_argument("--extras-only", action="store_true",
                     help="run only those rows (one JSON object)")
     ap.add_argument("--sort-items", type=int, default=0,

@@ -207,6 +207,21 @@ sa_status sa_build_sorted_pairs(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, 
 sa_status sa_build_dc3(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t* d_sa,
                        uint32_t* d_rank12, void* stream);
 
+/* Suffix array by the difference cover algorithm DC7 (Section 2.2): the
+ * sample is the suffixes at positions i mod 7 in {0, 1, 3}; their seven-
+ * character tuples are sorted and named, equal names send the name string
+ * (positions 0, 7, ... then 1, 8, ... then 3, 10, ...) to DC3, the other
+ * four classes are sorted by (characters up to the next sample position, its
+ * rank), and the five sorted lists are merged with the method's comparison
+ * (at most six characters, then two sample ranks). Same result as sa_build.
+ *   d_rank_sample: device u32[n] or NULL: for each position i with i mod 7 in
+ *                  {0, 1, 3}, the 1-based rank of suffix i among those
+ *                  suffixes; 0 at the other positions.
+ * Levels in sa_last_build_info (rounds, active[k]); allocates its arrays
+ * (about 70 bytes per text byte) on top of the context's workspace. */
+sa_status sa_build_dc7(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, uint32_t* d_sa,
+                       uint32_t* d_rank_sample, void* stream);
+
 /* The sorting step on its own (the Sort of Alg. 1 and 5): stable LSD radix
  * sort of `count` (key, value) pairs in place, ordered by the low `key_bits`
  * bits of the key (1..64; higher bits must be zero). d_keys: device u64[count],

@@ -133,6 +133,22 @@ class SuffixArrayBuilder:
                                          _stream_handle(self.device)), "sa_build_dc3")
         return (sa, r12) if with_ranks else sa
 
+    def build_dc7(self, text: torch.Tensor, out: torch.Tensor | None = None,
+                  with_ranks: bool = False):
+        """Suffix array by DC7 (``sa_build_dc7``). With ``with_ranks`` returns
+        (sa, ranks): the sample ranks by position (0 outside the sample)."""
+        t = self._text(text)
+        n = t.numel()
+        sa = self._out(out, n, "out")
+        rk = torch.empty(n, dtype=torch.int32, device=self.device) if with_ranks else None
+        with torch.cuda.device(self.device):
+            check(self._lib.sa_build_dc7(self._ctx, ctypes.c_void_p(t.data_ptr()), n,
+                                         ctypes.c_void_p(sa.data_ptr()),
+                                         ctypes.c_void_p(rk.data_ptr() if rk is not None
+                                                         else None),
+                                         _stream_handle(self.device)), "sa_build_dc7")
+        return (sa, rk) if with_ranks else sa
+
     def build_batch(self, texts: torch.Tensor, offsets, out: torch.Tensor | None = None):
         """Suffix arrays of many texts in one batched build.
 

@@ -31,7 +31,7 @@ ISA_MODES = {"auto": 0, "eager": 1, "lazy": 2}
 EXPORTED = [
     "sa_ctx_create", "sa_ctx_destroy", "sa_build", "sa_build_noalloc", "sa_build_batch",
     "sa_last_build_info",
-    "sa_build_rounds", "sa_build_sorted_pairs", "sa_build_dc3",
+    "sa_build_rounds", "sa_build_sorted_pairs", "sa_build_dc3", "sa_build_dc7",
     "sa_radix_sort_pairs", "sa_workspace_bytes", "sa_ctx_set_trace", "sa_ctx_reset_stats",
     "sa_ctx_set_isa_mode", "sa_ctx_set_tuning", "sa_ctx_get_tuning", "sa_ctx_tuning_source",
     "sa_tune", "sa_tune_save", "sa_tune_lookup",
@@ -132,6 +132,7 @@ def _declare(lib: ctypes.CDLL) -> None:
         "sa_build_rounds": ([vp, vp, u64, u32, vp, vp, vp], i32),
         "sa_build_sorted_pairs": ([vp, vp, u64, u32, vp, vp, u32, vp], i32),
         "sa_build_dc3": ([vp, vp, u64, vp, vp, vp], i32),
+        "sa_build_dc7": ([vp, vp, u64, vp, vp, vp], i32),
         "sa_radix_sort_pairs": ([vp, vp, vp, u64, u32, vp], i32),
         "sa_workspace_bytes": ([u64, u32], ctypes.c_size_t),
         "sa_ctx_set_trace": ([vp, i32], i32),

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 SOURCES = [os.path.join(CSRC, f)
            for f in ("sa_kernels.hip", "sa_capi.hip", "multi.hip", "tune.hip", "index.hip",
-                     "sortpair.hip", "dc3.hip")]
+                     "sortpair.hip", "dc3.hip", "dc7.hip")]
 HEADERS = [os.path.join(CSRC, f) for f in ("common.h", "kernels.h", "driver.h")] + [
     os.path.join(ROOT, "include", "sa.h")]
 LIB = os.path.join(PKG, "libsa_mi355x.so")

@@ -261,17 +261,6 @@ struct Dc3Level {
   Dc3Rec* rec12 = nullptr; // and of the sample suffixes by rank
   u32* pos0 = nullptr;
   u64* split = nullptr;    // merge-path splits
-  ~Dc3Level() {
-    (void)hipFree(rec0);
-    (void)hipFree(rec12);
-    (void)hipFree(pos0);
-    (void)hipFree(split);
-    (void)hipFree(child);
-    (void)hipFree(childsa);
-    (void)hipFree(tmp);
-    (void)hipFree(rankp);
-    (void)hipFree(byrank);
-  }
 };
 
 template <typename T>
@@ -294,8 +283,8 @@ sa_status dc3_level(sa_ctx* c, const T* x, u64 m, u32 add, u64 max_sym, u32* sa,
   const u64 n12 = m12 - dummy;  // real sample suffixes
   const int bsym = bits_of(max_sym);
   Dc3Level L;
-  if (!dev_alloc(&L.child, m12) || !dev_alloc(&L.tmp, m12) || !dev_alloc(&L.rankp, m + 3) ||
-      !dev_alloc(&L.byrank, std::max<u64>(n12, 1)))
+  if (!level_alloc(c, depth, 0, m12, &L.child) || !level_alloc(c, depth, 1, m12, &L.tmp) ||
+      !level_alloc(c, depth, 2, m + 3, &L.rankp) || !level_alloc(c, depth, 3, n12, &L.byrank))
     return SA_ENOMEM;
   launch_fill_u32(L.rankp, m + 3, 0, s);
   const Bufs full = full_bufs(c);
@@ -343,7 +332,7 @@ sa_status dc3_level(sa_ctx* c, const T* x, u64 m, u32 add, u64 max_sym, u32* sa,
   const u32* sa12 = L.tmp;
   if (nonunique > 0) {
     // Equal triples: the sample's order is the suffix order of the names.
-    if (!dev_alloc(&L.childsa, m12)) return SA_ENOMEM;
+    if (!level_alloc(c, depth, 4, m12, &L.childsa)) return SA_ENOMEM;
     st = dc3_level<u32>(c, L.child, m12, 0, m12, L.childsa, nullptr, depth + 1, s);
     if (st != SA_OK) return st;
     sa12 = L.childsa;
@@ -362,8 +351,8 @@ sa_status dc3_level(sa_ctx* c, const T* x, u64 m, u32 add, u64 max_sym, u32* sa,
 
   // Step 4: comparison records, merge-path splits, merge by tiles.
   const u64 ntiles = ceil_div(m, u64(kDc3Tile));
-  if (!dev_alloc(&L.rec0, n0) || !dev_alloc(&L.rec12, std::max<u64>(n12, 1)) ||
-      !dev_alloc(&L.pos0, n0) || !dev_alloc(&L.split, ntiles + 1))
+  if (!level_alloc(c, depth, 5, n0, &L.rec0) || !level_alloc(c, depth, 6, n12, &L.rec12) ||
+      !level_alloc(c, depth, 7, n0, &L.pos0) || !level_alloc(c, depth, 8, ntiles + 1, &L.split))
     return SA_ENOMEM;
   {
     // Position in; two characters and two ranks gathered; a 16-byte record out.
@@ -383,8 +372,13 @@ sa_status dc3_level(sa_ctx* c, const T* x, u64 m, u32 add, u64 max_sym, u32* sa,
   if (rank_out)
     hipLaunchKernelGGL(dc3_rank_out_kernel, dim3(stream_grid(c, m, 256)), dim3(256), 0, s,
                        L.rankp, m, rank_out);
-  // The level's arrays are freed on return: wait for the kernels that read them.
-  return readback(c, s);
+  // The arrays stay with the context; the top level checks the error flags.
+  return depth == 0 ? readback(c, s) : SA_OK;
+}
+
+sa_status dc3_names(sa_ctx* c, const u32* x, u64 m, u64 max_sym, u32* sa, u32 depth,
+                    hipStream_t s) {
+  return dc3_level<u32>(c, x, m, 0, max_sym, sa, nullptr, depth, s);
 }
 
 sa_status build_dc3(sa_ctx* c, const u8* text, u64 n, u32* d_sa, u32* d_rank12, hipStream_t s) {

@@ -73,6 +73,9 @@ struct sa_ctx {
   u64* toff = nullptr;    // batch text offsets on the device
   u64 toff_cap = 0;
   u64* status = nullptr;  // sort look-back: [tiles][radix]
+  // Arrays of the difference cover builds, per (recursion depth, slot), kept
+  // between builds so that repeated builds allocate nothing.
+  std::vector<std::pair<void*, size_t>> level_bufs;
   // Sort-based pairing (sa_build_sorted_pairs): three item buffers.
   u64* pair_k[3] = {nullptr, nullptr, nullptr};
   u32* pair_v[3] = {nullptr, nullptr, nullptr};
@@ -191,6 +194,20 @@ void bind_small(sa_ctx* c, char* p);
 sa_status init_small(char* p);
 void drop_graphs(sa_ctx* c);
 void free_pair_workspace(sa_ctx* c);
+// The difference cover builds' array `slot` of recursion depth `depth`, at
+// least `bytes` long (grown on demand, owned by the context).
+void* level_buf(sa_ctx* c, u32 depth, u32 slot, size_t bytes);
+void free_level_bufs(sa_ctx* c);
+constexpr u32 kLevelSlots = 24;
+template <typename T>
+bool level_alloc(sa_ctx* c, u32 depth, u32 slot, u64 count, T** p) {
+  *p = static_cast<T*>(level_buf(c, depth, slot, std::max<u64>(count, 1) * sizeof(T)));
+  return *p != nullptr;
+}
+// Suffix array of a string of m names (values 1..max_sym, 0 past the end) by
+// DC3, at recursion depth `depth` (dc3.hip; DC7 recurses through it).
+sa_status dc3_names(sa_ctx* c, const u32* x, u64 m, u64 max_sym, u32* sa, u32 depth,
+                    hipStream_t s);
 hipEvent_t take_event(sa_ctx* c);
 
 // Brackets one launch with events when tracing.

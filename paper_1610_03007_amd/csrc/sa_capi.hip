@@ -90,6 +90,27 @@ sa_status init_small(char* p) {
   return SA_OK;
 }
 
+void* level_buf(sa_ctx* c, u32 depth, u32 slot, size_t bytes) {
+  const size_t k = size_t(depth) * kLevelSlots + slot;
+  if (c->level_bufs.size() <= k) c->level_bufs.resize(k + 1, {nullptr, 0});
+  auto& e = c->level_bufs[k];
+  if (e.second >= bytes) return e.first;
+  (void)hipFree(e.first);
+  e = {nullptr, 0};
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  e = {p, bytes};
+  return p;
+}
+
+void free_level_bufs(sa_ctx* c) {
+  for (auto& e : c->level_bufs) (void)hipFree(e.first);
+  c->level_bufs.clear();
+}
+
 void drop_graphs(sa_ctx* c) {
   for (GraphEntry& e : c->graph_cache)
     if (e.exec) (void)hipGraphExecDestroy(e.exec);
@@ -814,6 +835,7 @@ sa_status sa_ctx_destroy(sa_ctx* ctx) {
   (void)hipSetDevice(ctx->device);
   free_workspace(ctx);
   free_pair_workspace(ctx);
+  free_level_bufs(ctx);
   drop_graphs(ctx);
   if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   (void)hipFree(ctx->small);
