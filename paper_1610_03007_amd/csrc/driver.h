@@ -283,7 +283,7 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
 
 // Per-slot tables of the multi-text engine (multi.hip), in one allocation.
 struct TableLayout {
-  size_t o_base, o_len, o_h, o_r0, o_nt, o_no, o_nc;  // uploaded each round
+  size_t o_base, o_len, o_h, o_start, o_r0, o_nt, o_no, o_nc;  // uploaded each round
   size_t up_bytes;                                     // extent of the uploaded part
   size_t o_code, o_pres, o_wc, o_surv;
   size_t bytes;

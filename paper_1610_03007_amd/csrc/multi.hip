@@ -44,6 +44,7 @@ TableLayout table_layout(u32 nslots) {
   L.o_base = take(S * 8);
   L.o_len = take(S * 8);
   L.o_h = take(S * 8);
+  L.o_start = take(S * 8);
   L.o_r0 = take(S);
   L.o_nt = take(S * 4);
   L.o_no = take((S + 1) * 8);
@@ -79,8 +80,9 @@ struct Engine {
   u32* h_wc = nullptr;    // pinned
   u32* h_surv = nullptr;  // pinned
   char* h_up = nullptr;   // pinned mirror of the per-round upload tables
-  size_t up_bytes = 0, o_up_base = 0, o_up_len = 0, o_up_h = 0, o_up_r0 = 0, o_up_nt = 0,
-         o_up_no = 0, o_up_nc = 0;
+  size_t up_bytes = 0, o_up_base = 0, o_up_len = 0, o_up_h = 0, o_up_start = 0, o_up_r0 = 0,
+         o_up_nt = 0, o_up_no = 0, o_up_nc = 0;
+  std::vector<u64> start;  // host mirror of tab.start
   u64 active = 0;         // survivors carried into the next round
   std::vector<u32> live;  // slots with elements in the active set or joining now
   // Batched build only (every text starts round 0 together): round 0 writes no
@@ -117,6 +119,7 @@ struct Engine {
     up_bytes = L.up_bytes;
     o_up_base = o_base, o_up_len = o_len, o_up_h = o_h, o_up_r0 = o_r0, o_up_nt = o_nt,
     o_up_no = o_no, o_up_nc = o_nc;
+    o_up_start = L.o_start;
     if (hipMalloc(&dev, bytes) != hipSuccess) {
       dev = nullptr;
       (void)hipGetLastError();
@@ -132,6 +135,7 @@ struct Engine {
     tab.h = reinterpret_cast<u64*>(p + o_h);
     tab.round0 = reinterpret_cast<u8*>(p + o_r0);
     tab.surv = reinterpret_cast<u32*>(p + o_surv);
+    tab.start = reinterpret_cast<u64*>(p + L.o_start);
     d_new_t = reinterpret_cast<u32*>(p + o_nt);
     d_new_out = reinterpret_cast<u64*>(p + o_no);
     d_new_chunk0 = reinterpret_cast<u64*>(p + o_nc);
@@ -140,6 +144,7 @@ struct Engine {
         hipHostMalloc(reinterpret_cast<void**>(&h_up), up_bytes) != hipSuccess)
       return SA_ENOMEM;
     base.assign(S, 0);
+    start.assign(S, 0);
     len.assign(S, 0);
     h.assign(S, 0);
     chars.assign(S, 0);
@@ -188,12 +193,26 @@ struct Engine {
       h[t] = u64(chars[t]) << (round[t] - 1);
     }
     for (u32 t : nt) round0[t] = 1;
+    // The sorted array holds each text's elements together, in slot order:
+    // the joining texts' whole length, the others' survivors of last round.
+    std::fill(start.begin(), start.end(), u64(0));
+    {
+      std::vector<u64> cnt(slots, 0);
+      for (u32 t : nt) cnt[t] = len[t];
+      for (u32 t : live) cnt[t] = h_surv[t];
+      u64 at = 0;
+      for (u32 t = 0; t < slots; ++t) {
+        start[t] = at;
+        at += cnt[t];
+      }
+    }
     // Upload the per-round tables (a few values per slot) in one copy from
     // the pinned mirror. The previous round synchronised the stream, so the
     // mirror is free to be rewritten.
     std::memcpy(h_up + o_up_base, base.data(), slots * 8);
     std::memcpy(h_up + o_up_len, len.data(), slots * 8);
     std::memcpy(h_up + o_up_h, h.data(), slots * 8);
+    std::memcpy(h_up + o_up_start, start.data(), slots * 8);
     std::memcpy(h_up + o_up_r0, round0.data(), slots);
     if (m) {
       std::memcpy(h_up + o_up_nt, nt.data(), m * 4);
@@ -242,6 +261,7 @@ struct Engine {
       a.tbase = tab.base;
       a.tlen = tab.len;
       a.tround0 = tab.round0;
+      a.tstart = tab.start;
       run_rerank(c, bufs, a, sa_arena, total, total, s);
       last_args = a;
       // Survivors per text; their number is read on the device.

@@ -1312,6 +1312,8 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     u64 start = base;
     if (sh >= 64) {
       start = 0;  // one group holds every element
+    } else if (wave == 1 && a.tstart && sh == a.idshift) {
+      start = a.tstart[kb >> a.idshift];  // a round-0 text: its elements start there
     } else if (base > 0) {
       const u64 x = kb >> sh;
       if (TIE && wave == 0) {
