@@ -322,7 +322,7 @@ sa_status dc3_level(sa_ctx* c, const T* x, u64 m, u32 add, u64 max_sym, u32* sa,
   {
     Tracer t(c, s, SA_KERNEL_RERANK, double(m12) * 16.0);
     const u32 grid = u32(std::min<u64>(std::max<u64>(1, ceil_div(m12, kRerankTile)),
-                                       u64(c->num_cus) * 8));
+                                       u64(c->num_cus) * rerank_wgs_per_cu(a.tie != 0)));
     launch_rerank_compact(full.kA, full.kB, full.vA, full.vB, c->plan, a, c->ctl, L.child, L.tmp,
                           c->act_idx, nullptr, c->act_rank, c->counters, grid, s);
   }

@@ -304,7 +304,7 @@ sa_status build_dc7(sa_ctx* c, const u8* text, u64 n, u32* d_sa, u32* d_rank, hi
     Tracer t(c, s, SA_KERNEL_RERANK, double(ms) * 16.0);
     const RerankArgs a = single_args(ms, ms, 0, kRerankScatterIsa);
     const u32 grid = u32(std::min<u64>(std::max<u64>(1, ceil_div(ms, kRerankTile)),
-                                       u64(c->num_cus) * 8));
+                                       u64(c->num_cus) * rerank_wgs_per_cu(false)));
     launch_rerank_compact(full.kA, full.kB, full.vA, full.vB, c->plan, a, c->ctl, A.child, A.tmp,
                           c->act_idx, nullptr, c->act_rank, c->counters, grid, s);
   }

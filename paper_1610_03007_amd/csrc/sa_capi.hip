@@ -245,7 +245,7 @@ void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, u6
   if (args.mode & kRerankIsaOnly) bytes = count * 16.0;
   Tracer t(c, s, (args.mode & kRerankIsaOnly) ? SA_KERNEL_ISA_SCATTER : SA_KERNEL_RERANK, bytes);
   const u32 grid = u32(std::min<u64>(std::max<u64>(1, ceil_div(bound, kRerankTile)),
-                                     u64(c->num_cus) * 8));
+                                     u64(c->num_cus) * rerank_wgs_per_cu(args.tie != 0)));
   launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->ctl, c->isa, d_sa,
                         args.tbase ? nullptr : c->act_idx, args.tbase ? c->act_ti : nullptr,
                         c->act_rank, c->counters, grid, s);

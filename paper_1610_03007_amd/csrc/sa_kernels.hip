@@ -11,6 +11,8 @@
 // decoupled look-back over tiles taken from an atomic ticket, so a tile only
 // ever waits for tiles that are already running; every wait is bounded.
 
+#include <atomic>
+
 #include "kernels.h"
 
 namespace sa {
@@ -1495,6 +1497,23 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
              (unsigned long long)kErrBounds);
   __syncthreads();  // the next tile reuses the LDS aggregates
   }
+}
+
+int rerank_wgs_per_cu(bool tie) {
+  static std::atomic<int> cache[2];
+  int n = cache[tie ? 1 : 0].load(std::memory_order_relaxed);
+  if (n > 0) return n;
+  const hipError_t e =
+      tie ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rerank_compact_kernel<true>,
+                                                         kRerankBlock, 0)
+          : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, rerank_compact_kernel<false>,
+                                                         kRerankBlock, 0);
+  if (e != hipSuccess || n <= 0) {
+    (void)hipGetLastError();
+    return 4;
+  }
+  cache[tie ? 1 : 0].store(n, std::memory_order_relaxed);
+  return n;
 }
 
 void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
