@@ -160,8 +160,8 @@ constexpr int kSortItemsDefault = 8;
 constexpr int kSortTileMin = 2048;       // smallest tile (512 x 4); status arrays are sized for it
 constexpr int kHistBlock = 256;
 constexpr int kRerankBlock = 256;
-constexpr int kRerankRows = 16;  // rows of 64 elements per wave
-constexpr int kRerankTile = kRerankBlock * kRerankRows;  // 4096 elements
+constexpr int kRerankRows = 8;  // rows of 64 elements per wave
+constexpr int kRerankTile = kRerankBlock * kRerankRows;  // 2048 elements
 
 // Device-side 64-bit counters shared by one build (slot indices).
 enum CounterSlot : int {

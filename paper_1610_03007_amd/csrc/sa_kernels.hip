@@ -1350,6 +1350,26 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     }
   }
 
+  // Multi-text: the key's top field names the text and the keys are sorted,
+  // so when the wave's first and last elements lie in one text (the common
+  // case: texts span many rows) its table entries serve every element of the
+  // wave, loaded once instead of once per element.
+  bool one_text = false;
+  u64 ot = 0, ot_base = 0, ot_len = 0;
+  bool ot_round0 = false;
+  if (a.tbase && wbase < count) {
+    const u64 wend = wbase + u64(R) * kWave;
+    const u64 wlast = (wend < count ? wend : count) - 1;
+    const u64 tf = keys[wbase] >> a.idshift;
+    if ((keys[wlast] >> a.idshift) == tf) {
+      one_text = true;
+      ot = tf;
+      ot_base = a.tbase[tf];
+      ot_len = a.tlen[tf];
+      ot_round0 = a.tround0[tf] != 0;
+    }
+  }
+
   // Flags per element (bit r: head, bit 16 + r: unique; gflags bit r: group
   // start) and the wave's aggregates: last head, last group start (tile-local
   // position + 1, 0 = none) and survivor count.
@@ -1385,7 +1405,8 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     }
     const bool valid = e < count;
     int gsh = a.gshift;
-    if (valid && a.tbase && a.tround0[k[r] >> a.idshift]) gsh = a.idshift;  // group = text
+    if (valid && a.tbase && (one_text ? ot_round0 : a.tround0[k[r] >> a.idshift] != 0))
+      gsh = a.idshift;  // group = text
     const bool head = valid && (e == 0 || diff_prev);
     const bool grp = valid && (e == 0 || (gsh < 64 && (k[r] >> gsh) != (kp >> gsh)));
     const bool uniq = head && (e + 1 == count || diff_next);
@@ -1456,7 +1477,12 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     // the key's high bits; ranks and positions are local to it.
     u64 gb = 0, nt = a.n, t = 0;
     bool first_round = a.rmask == 0;
-    if (a.tbase) {
+    if (one_text) {
+      t = ot;
+      gb = ot_base;
+      nt = ot_len;
+      first_round = ot_round0;
+    } else if (a.tbase) {
       t = k[r] >> a.idshift;
       gb = a.tbase[t];
       nt = a.tlen[t];
