@@ -1301,34 +1301,8 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const u64 base = tile * T;
   const u64 wbase = base + u64(wave) * (R * kWave);  // first element of the wave
 
-  // What precedes the tile: wave 0 finds the start of the run of keys equal to
-  // keys[base] and wave 1 the start of its group (the last head and the last
-  // group start before the tile, when the tile does not begin with one).
-  if (wave < 2) {
-    const u64 kb = keys[base];
-    int sh = 0;
-    if (wave == 1) {
-      sh = a.gshift;
-      if (a.tbase && a.tround0[kb >> a.idshift]) sh = a.idshift;  // group = text
-    }
-    u64 start = base;
-    if (sh >= 64) {
-      start = 0;  // one group holds every element
-    } else if (wave == 1 && a.tstart && sh == a.idshift) {
-      start = a.tstart[kb >> a.idshift];  // a round-0 text: its elements start there
-    } else if (base > 0) {
-      const u64 x = kb >> sh;
-      if (TIE && wave == 0) {
-        const u32 tb = tie[base];
-        if (keys[base - 1] == x && tie[base - 1] == tb)
-          start = run_start_wave<true>(keys, tie, base, 0, x, tb);
-      } else if ((keys[base - 1] >> sh) == x) {
-        start = run_start_wave<false>(keys, nullptr, base, sh, x, 0);
-      }
-    }
-    if (lane == 0) s_prefix[wave] = start;
-  }
-
+  // The tile's elements are requested first, so that they are in flight
+  // while the waves look up what precedes the tile and the text tables.
   u64 k[R];
   u32 v[R];
 #pragma unroll
@@ -1359,15 +1333,52 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   bool ot_round0 = false;
   if (a.tbase && wbase < count) {
     const u64 wend = wbase + u64(R) * kWave;
-    const u64 wlast = (wend < count ? wend : count) - 1;
-    const u64 tf = keys[wbase] >> a.idshift;
-    if ((keys[wlast] >> a.idshift) == tf) {
+    const u64 kf = __shfl(k[0], 0, kWave);  // keys[wbase]
+    const u64 kl = wend <= count ? __shfl(k[R - 1], kWave - 1, kWave) : keys[count - 1];
+    const u64 tf = kf >> a.idshift;
+    if ((kl >> a.idshift) == tf) {
       one_text = true;
       ot = tf;
       ot_base = a.tbase[tf];
       ot_len = a.tlen[tf];
       ot_round0 = a.tround0[tf] != 0;
     }
+  }
+
+  // What precedes the tile: wave 0 finds the start of the run of keys equal to
+  // keys[base] and wave 1 the start of its group (the last head and the last
+  // group start before the tile, when the tile does not begin with one).
+  if (wave < 2) {
+    const u64 kb = keys[base];
+    const u64 kbp = base > 0 ? keys[base - 1] : 0;
+    int sh = 0;
+    u64 text_start = 0;
+    if (wave == 1) {
+      sh = a.gshift;
+      if (a.tbase) {
+        // Both entries of the text at once: the start is used when the text
+        // is in its round 0 (its elements form one group).
+        const u64 tk = kb >> a.idshift;
+        if (a.tstart) text_start = a.tstart[tk];
+        if (a.tround0[tk]) sh = a.idshift;  // group = text
+      }
+    }
+    u64 start = base;
+    if (sh >= 64) {
+      start = 0;  // one group holds every element
+    } else if (wave == 1 && a.tstart && sh == a.idshift) {
+      start = text_start;  // a round-0 text: its elements start there
+    } else if (base > 0) {
+      const u64 x = kb >> sh;
+      if (TIE && wave == 0) {
+        const u32 tb = tie[base];
+        if (kbp == x && tie[base - 1] == tb)
+          start = run_start_wave<true>(keys, tie, base, 0, x, tb);
+      } else if ((kbp >> sh) == x) {
+        start = run_start_wave<false>(keys, nullptr, base, sh, x, 0);
+      }
+    }
+    if (lane == 0) s_prefix[wave] = start;
   }
 
   // Flags per element (bit r: head, bit 16 + r: unique; gflags bit r: group
