@@ -378,6 +378,14 @@ def run_extras(steps: int = 2, warmup: int = 1) -> dict:
         {"rounds": info["rounds"], "rounds_doubling": dbl["rounds"],
          "active_per_round": info["active"], "passes_per_round": info["passes_run"],
          "equals_doubling_sa": same})
+    # DC7 on the same text: its work does not grow with the common prefixes.
+    ms = _timed(lambda: b.build_dc7(d_text, out=sa), steps, warmup)
+    info = b.last_info()
+    same = bool(torch.equal(sa, ref))
+    table = _traced(b, lambda: b.build_dc7(d_text, out=sa), 1)
+    out["repetitive_1g_dc7"] = _summary(
+        "repetitive_1g_dc7", n, ms, table,
+        {"levels": info["rounds"], "level_sizes": info["active"], "equals_doubling_sa": same})
     del d_text, ref, sa
     torch.cuda.empty_cache()
 

@@ -66,8 +66,12 @@ namespace {
 struct Engine {
   sa_ctx* c = nullptr;
   u32 slots = 0;
-  int idbits = 0;   // slot bits at the top of every key
+  int idbits = 0;   // slot bits at the top of every later-round key
   int B = 0;        // bits of a rank
+  // Where the slot sits in round-0 keys: 64 - idbits (the top, as in later
+  // rounds, whose keys a round-0 text shares its sort with), or lower, right
+  // above the characters, when every text starts round 0 together.
+  int round0_shift = 0;
   void* dev = nullptr;  // one allocation for all tables
   TextTab tab{};
   u32* d_new_t = nullptr;
@@ -110,6 +114,7 @@ struct Engine {
     slots = nslots;
     idbits = id_bits;
     B = rank_bits;
+    round0_shift = 64 - id_bits;
     const TableLayout L = table_layout(nslots);
     const size_t S = nslots;
     const size_t bytes = L.bytes;
@@ -172,6 +177,9 @@ struct Engine {
     }
     const Bufs full = full_bufs(c);
     const int idshift = 64 - idbits;
+    // Round-0 keys below the top share no sort with later-round keys.
+    const bool compact0 = round0_shift != idshift;
+    if (compact0 && !live.empty() && !joining.empty()) return SA_EINVAL;
     // Work list of the joining texts.
     std::vector<u32> nt;
     std::vector<u64> nout(1, 0), nchunk(1, 0);
@@ -232,17 +240,20 @@ struct Engine {
       {
         Tracer tr(c, s, SA_KERNEL_OTHER, double(A0));
         launch_multi_presence(text_arena, tab, nl, s);
-        launch_multi_codes(tab, nl, idbits, c->round0_trim, c->radix_bits, s);
+        // A compact layout's character budget ends on a digit boundary already.
+        launch_multi_codes(tab, nl, idbits, round0_shift, compact0 ? 0 : c->round0_trim,
+                           c->radix_bits, s);
       }
       Tracer tr(c, s, SA_KERNEL_PACK_TEXT, double(A0) * 13.0);
-      launch_multi_pack0(text_arena, tab, nl, idshift, c->keysA, c->valsA, s);
+      launch_multi_pack0(text_arena, tab, nl, round0_shift, c->keysA, c->valsA, s);
     }
     const Bufs bufs = lazy ? later : full;
     if (active) {
       Tracer tr(c, s, SA_KERNEL_PACK_PAIRS, double(active) * 24.0);
       if (lazy)
-        launch_multi_pack_pairs_lazy(c->act_ti, c->act_rank, active, tab, B, idshift, c->isa,
-                                     c->live, text_arena, keys0, bufs.kA, bufs.vA, s);
+        launch_multi_pack_pairs_lazy(c->act_ti, c->act_rank, active, tab, B, idshift,
+                                     round0_shift, c->isa, c->live, text_arena, keys0, bufs.kA,
+                                     bufs.vA, s);
       else
         launch_multi_pack_pairs(c->act_ti, c->act_rank, active, tab, B, idshift, c->isa,
                                 c->keysA + A0, c->valsA + A0, s);
@@ -256,7 +267,7 @@ struct Engine {
       a.gshift = B;  // group = (slot, rank) for texts past round 0
       a.rshift = B;
       a.rmask = (u64(1) << B) - 1;
-      a.idshift = idshift;
+      a.idshift = m ? round0_shift : idshift;  // (equal when the round mixes)
       a.mode = (defer_round0_isa && m) ? 0 : kRerankScatterIsa;
       a.tbase = tab.base;
       a.tlen = tab.len;
@@ -380,6 +391,15 @@ sa_status build_batch_impl(sa_ctx* c, const u8* text, const u64* h_off, u32 T, u
   st = eng.init(c, T, idbits, B);
   if (st != SA_OK) return st;
   eng.defer_round0_isa = true;
+  // Every text starts round 0 together, so the round-0 keys need not share
+  // the later rounds' layout: the slot goes right above the characters, whose
+  // budget (with round0_trim) ends one radix digit below 64 bits, and the
+  // first sort runs one sweep fewer than with the slot at the top.
+  if (c->round0_trim) {
+    const int rb = c->radix_bits;
+    const int s0 = (passes_for(64, rb) - 1) * rb - idbits;
+    if (s0 >= 9 && s0 < 64 - idbits) eng.round0_shift = s0;  // (a code has at most 9 bits)
+  }
   std::vector<u32> joining;
   for (u32 t = 0; t < T; ++t) {
     eng.base[t] = h_off[t];

@@ -1259,15 +1259,17 @@ __device__ u64 run_start_wave(const u64* __restrict__ keys, const u32* __restric
 // from a population count. Rows carry the last head / group start forward;
 // waves combine through LDS. No tile waits for another: the run and the group
 // that the tile's first element continues from an earlier tile are found by
-// searching the sorted keys (run_start_wave), and the survivors take their
-// output range with one atomic add per tile, so survivors keep their sorted
-// order inside a tile but tiles land in any order (the next round sorts them
-// anyway).
+// searching the sorted keys (run_start_wave). Survivors collect in an LDS
+// buffer of one tile's size, which takes its output range with one atomic add
+// whenever it is full and once at the end, so survivors keep their sorted
+// order within a workgroup's buffer but buffers land in any order (the next
+// round sorts them anyway).
 // TIE (quadrupling rounds): the key is (keys[p], tie word), the tie words
 // being the value buffer the sort did not end in; groups still come from the
 // key's upper part.
 template <bool TIE>
-__global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
+__global__ __launch_bounds__(kRerankBlock) __attribute__((amdgpu_waves_per_eu(4)))
+void rerank_compact_kernel(
     const u64* __restrict__ keysA, const u64* __restrict__ keysB,
     const u32* __restrict__ valsA, const u32* __restrict__ valsB,
     const SortPlan* __restrict__ plan, const RerankArgs a, const SortCtl* __restrict__ ctl,
@@ -1280,7 +1282,15 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const u64 count = ctl->count;
   const int mode = a.mode;
   __shared__ u32 s_wh[NW], s_wg[NW], s_ws[NW];
-  __shared__ u64 s_prefix[3];
+  __shared__ u64 s_prefix[2];
+  // Survivors of the workgroup's tiles, gathered here and written out in one
+  // range per buffer-full: one reservation on the shared survivor counter per
+  // T survivors instead of one per tile (the atomics of all workgroups on
+  // that one word serialise).
+  __shared__ u64 s_sv[T];   // act_ti value (multi-text) or position
+  __shared__ u32 s_svr[T];  // new name
+  __shared__ u32 s_fill, s_tile_at, s_flush_n;
+  __shared__ u64 s_flush_at;
 
   const u32 fb = plan->final_buf;
   const u64* keys = fb ? keysB : keysA;
@@ -1297,6 +1307,25 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   const int wave = tid / kWave;
   const u64 lt_mask = (u64(1) << lane) - 1;
   const u64 tiles = ceil_div(count, u64(T));
+  if (tid == 0) s_fill = 0;  // ordered before its use by the tile's first barrier
+  bool bad = false;
+  // Writes buffer entries [0, s_flush_n) at s_flush_at (every thread).
+  auto flush = [&]() {
+    const u32 m = s_flush_n;
+    const u64 at = s_flush_at;
+    if (at + m > count) {
+      bad = true;
+      return;
+    }
+    for (u32 q = u32(tid); q < m; q += kRerankBlock) {
+      const u64 w = s_sv[q];
+      if (act_ti)
+        act_ti[at + q] = w;
+      else
+        act_idx[at + q] = u32(w);
+      act_rank[at + q] = s_svr[q];
+    }
+  };
   for (u64 tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
   const u64 base = tile * T;
   const u64 wbase = base + u64(wave) * (R * kWave);  // first element of the wave
@@ -1444,12 +1473,23 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     u32 tts = 0;
 #pragma unroll
     for (int w = 0; w < NW; ++w) tts += s_ws[w];
-    s_prefix[2] = (tts && !no_survivors)
-                      ? atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
-                                  (unsigned long long)tts)
-                      : 0;
+    u32 fill = s_fill, fn = 0;
+    if (no_survivors) tts = 0;
+    if (fill + tts > u32(T)) {  // no room for this tile's survivors: empty the buffer first
+      s_flush_at = atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
+                             (unsigned long long)fill);
+      fn = fill;
+      fill = 0;
+    }
+    s_flush_n = fn;
+    s_tile_at = fill;
+    s_fill = fill + tts;
   }
   __syncthreads();
+  if (s_flush_n) {
+    flush();
+    __syncthreads();  // the buffer is refilled below
+  }
 
   // Carries into the wave's first row: from earlier waves of the tile, else
   // from before the tile.
@@ -1464,8 +1504,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
   }
   u64 carry_h = eh ? base + eh - 1 : s_prefix[0];
   u64 carry_g = eg ? base + eg - 1 : s_prefix[1];
-  u64 out_base = s_prefix[2] + es;
-  bool bad = false;
+  u32 out_base = s_tile_at + es;  // buffer slot of the wave's first survivor
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const u64 e = wbase + u64(r) * kWave + lane;
@@ -1479,10 +1518,10 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     const u64 hmine = hm & upto, gmine = gm & upto;
     const u64 ss = hmine ? row0 + u64(63 - __clzll((long long)hmine)) : carry_h;
     const u64 gs = gmine ? row0 + u64(63 - __clzll((long long)gmine)) : carry_g;
-    const u64 out = out_base + u64(__popcll(sm & lt_mask));
+    const u32 out = out_base + u32(__popcll(sm & lt_mask));
     if (hm) carry_h = row0 + u64(63 - __clzll((long long)hm));
     if (gm) carry_g = row0 + u64(63 - __clzll((long long)gm));
-    out_base += u64(__popcll(sm));
+    out_base += u32(__popcll(sm));
     if (!valid) continue;
     // Text of the element: the whole text, or (multi-text) the one named by
     // the key's high bits; ranks and positions are local to it.
@@ -1501,7 +1540,7 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     }
     const u64 r0 = first_round ? 1 : ((k[r] >> a.rshift) & a.rmask);
     const u64 nr = r0 + ss - gs;
-    if (v[r] >= nt || nr == 0 || nr > nt || (!uniq && out >= count)) {
+    if (v[r] >= nt || nr == 0 || nr > nt || (!uniq && !no_survivors && out >= u32(T))) {
       bad = true;
       continue;
     }
@@ -1522,18 +1561,25 @@ __global__ __launch_bounds__(kRerankBlock) void rerank_compact_kernel(
     if (uniq) {
       if (first_round || !((gflags >> (16 + r)) & 1u)) sa_out[gb + nr - 1] = v[r];
     } else {
-      if (act_ti)
-        act_ti[out] = (t << 32) | v[r];
-      else
-        act_idx[out] = v[r];
-      act_rank[out] = u32(nr);
+      s_sv[out] = act_ti ? ((t << 32) | v[r]) : u64(v[r]);
+      s_svr[out] = u32(nr);
     }
   }
+  __syncthreads();  // the next tile reuses the LDS aggregates
+  }
+  // The survivors still in the buffer.
+  if (tid == 0) {
+    const u32 fill = s_fill;
+    s_flush_n = fill;
+    if (fill)
+      s_flush_at = atomicAdd(reinterpret_cast<unsigned long long*>(counters + kCtrActive),
+                             (unsigned long long)fill);
+  }
+  __syncthreads();
+  if (s_flush_n) flush();
   if (bad)
     atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
              (unsigned long long)kErrBounds);
-  __syncthreads();  // the next tile reuses the LDS aggregates
-  }
 }
 
 int rerank_wgs_per_cu(bool tie) {
@@ -1808,8 +1854,11 @@ void launch_multi_presence(const u8* arena, TextTab tab, NewList nl, hipStream_t
                      per);
 }
 
+// Code table and characters per key of each joining text. The characters take
+// at most `avail_bits` key bits (below the text id's idbits); with `trim` the
+// count is then cut to end on a radix digit boundary.
 __global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList nl, int idbits,
-                                                          int trim, int rb) {
+                                                          int avail_bits, int trim, int rb) {
   __shared__ u32 wsum[4];
   const u32 t = nl.t[blockIdx.x];
   const int d = threadIdx.x;
@@ -1828,7 +1877,7 @@ __global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList n
   if (d == 0) {
     u32 w = 32 - __clz(total);
     if (w == 0) w = 1;
-    const u32 avail = 64u - u32(idbits);
+    const u32 avail = u32(avail_bits);
     u32 c = avail / w;
     if (c < 1) c = 1;
     const u32 used = u32(idbits) + c * w;
@@ -1852,9 +1901,11 @@ __global__ __launch_bounds__(256) void multi_codes_kernel(TextTab tab, NewList n
   }
 }
 
-void launch_multi_codes(TextTab tab, NewList nl, int idbits, int trim, int rb, hipStream_t s) {
+void launch_multi_codes(TextTab tab, NewList nl, int idbits, int avail_bits, int trim, int rb,
+                        hipStream_t s) {
   if (nl.m == 0) return;
-  hipLaunchKernelGGL(multi_codes_kernel, dim3(nl.m), dim3(256), 0, s, tab, nl, idbits, trim, rb);
+  hipLaunchKernelGGL(multi_codes_kernel, dim3(nl.m), dim3(256), 0, s, tab, nl, idbits, avail_bits,
+                     trim, rb);
 }
 
 __global__ __launch_bounds__(kPackBlock) void multi_pack0_kernel(const u8* __restrict__ arena,
@@ -1970,7 +2021,7 @@ void launch_multi_isa_scatter_list(const u64* act_ti, const u32* act_rank, const
 
 __global__ __launch_bounds__(256) void multi_pack_pairs_lazy_kernel(
     const u64* __restrict__ act_ti, const u32* __restrict__ act_rank, u64 count, TextTab tab,
-    int b, int idshift, const u32* __restrict__ isa, const u32* __restrict__ live,
+    int b, int idshift, int idshift0, const u32* __restrict__ isa, const u32* __restrict__ live,
     const u8* __restrict__ arena, const u64* __restrict__ keys0, u64* __restrict__ keys,
     u32* __restrict__ vals) {
   const u64 p = u64(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1998,7 +2049,7 @@ __global__ __launch_bounds__(256) void multi_pack_pairs_lazy_kernel(
         const u64 pos = j + q;
         k = (k << w) | u64(pos < nt ? code[txt[pos]] : u16(0));
       }
-      k |= t << idshift;
+      k |= t << idshift0;  // the round-0 keys' layout
       u64 lo = gb, hi = gb + nt;
       while (lo < hi) {
         const u64 mid = (lo + hi) >> 1;
@@ -2015,13 +2066,13 @@ __global__ __launch_bounds__(256) void multi_pack_pairs_lazy_kernel(
 }
 
 void launch_multi_pack_pairs_lazy(const u64* act_ti, const u32* act_rank, u64 count, TextTab tab,
-                                  int b, int idshift, const u32* isa, const u32* live,
-                                  const u8* arena, const u64* keys0, u64* keys, u32* vals,
-                                  hipStream_t s) {
+                                  int b, int idshift, int idshift0, const u32* isa,
+                                  const u32* live, const u8* arena, const u64* keys0, u64* keys,
+                                  u32* vals, hipStream_t s) {
   if (count == 0) return;
   hipLaunchKernelGGL(multi_pack_pairs_lazy_kernel, dim3(u32(ceil_div(count, 256))), dim3(256), 0,
-                     s, act_ti, act_rank, count, tab, b, idshift, isa, live, arena, keys0, keys,
-                     vals);
+                     s, act_ti, act_rank, count, tab, b, idshift, idshift0, isa, live, arena,
+                     keys0, keys, vals);
 }
 
 __global__ __launch_bounds__(256) void multi_count_survivors_kernel(

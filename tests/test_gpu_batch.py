@@ -154,6 +154,32 @@ def test_batch_equals_single_builds(builder):
         assert np.array_equal(single.cpu().numpy().view(np.uint32), sa[int(off[t]):int(off[t + 1])])
 
 
+@pytest.mark.parametrize("round0_full", [0, 1])
+def test_batch_round0_layout(builder, round0_full):
+    """100 DNA and Markov texts (7 slot bits) with 8-bit digits: with round-0
+    trimming the slot sits right above the characters, which take at most
+    56 - 7 = 49 bits, so round 0 runs at most 7 sweeps; without it the slot
+    takes the top bits of 64-bit keys (8 sweeps). Both layouts give the same
+    arrays."""
+    rng = np.random.default_rng(77)
+    texts = []
+    for i in range(100):
+        n = int(rng.integers(1, 40000))
+        t = W.dna(n, seed=300 + i) if i % 2 else W.markov3(n, chain_seed=300 + i)
+        texts.append(np.ascontiguousarray(t, np.uint8))
+    builder.set_tuning(round0_full=round0_full, radix_bits=8, sort_items=8, sort_block=512)
+    try:
+        sa, off = run_batch(builder, texts)
+        info = builder.last_info()
+    finally:
+        builder.auto_tuning()
+    check_each(texts, sa, off)
+    if round0_full:
+        assert info["passes_run"][0] == 8, info["passes_run"][:2]
+    else:
+        assert info["passes_run"][0] <= 7, info["passes_run"][:2]
+
+
 def test_batch_errors(builder):
     from paper_1610_03007_amd import SAError
     d = torch.zeros(10, dtype=torch.uint8, device="cuda:0")
