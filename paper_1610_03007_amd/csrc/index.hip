@@ -3,14 +3,19 @@
 // Burrows-Wheeler transform of text$, and an FM index that answers pattern
 // queries by backward search over the transform.
 //
-// LCP array. With Phi[SA[j]] = SA[j - 1] (the suffix just before suffix i in
-// sorted order), the permuted array PLCP[i] = lcp(suffix i, suffix Phi[i])
-// satisfies PLCP[i + 1] >= PLCP[i] - 1, so a left-to-right pass over the text
-// positions extends each common prefix from the previous one minus one
-// (Kasai et al.'s argument, in the Phi form of Kaerkkaeinen, Manzini and
-// Puglisi). On the GPU each thread runs that pass over its own stretch of
-// positions, starting the first common prefix from zero; then LCP[j] =
-// PLCP[SA[j]].
+// LCP array, in two parts. First, in suffix array order, LCP[j] is found by
+// comparing suffixes SA[j - 1] and SA[j] directly over at most kLcpCap bytes
+// (eight at a time); where they agree on all of them the entry is "long".
+// Second, only for the long entries: with Phi[SA[j]] = SA[j - 1] (the suffix
+// just before suffix i in sorted order), the permuted array PLCP[i] =
+// lcp(suffix i, suffix Phi[i]) satisfies PLCP[i + 1] >= PLCP[i] - 1, so a
+// left-to-right pass over the text positions extends each common prefix from
+// the previous one minus one (Kasai et al.'s argument, in the Phi form of
+// Kaerkkaeinen, Manzini and Puglisi), and a long one from at least kLcpCap.
+// Each thread runs that pass over its own stretch of positions (skipping
+// stretches without long positions, found in a bitmap); then LCP[j] =
+// PLCP[SA[j]] for the long entries. Texts with short common prefixes take the
+// first part almost alone; repetitive ones fall back to the second.
 //
 // FM index. Rows of the transform are the sorted suffixes of text$ (row 0 is
 // $ alone, row r >= 1 is suffix SA[r - 1]); B[r] is the character before row
@@ -32,6 +37,8 @@ namespace {
 
 constexpr u32 kNone = 0xFFFFFFFFu;  // no predecessor (SA[0]); never a position (n < 2^32)
 constexpr int kLcpStretch = 512;     // positions per thread in the PLCP pass
+constexpr u32 kLcpCap = 32;          // bytes compared in suffix array order
+constexpr u32 kLcpLong = 0xFFFFFFFFu;  // LCP entry still to come from the PLCP pass
 constexpr int kOccBlock = 256;       // rows per occurrence sample
 constexpr int kOccGroup = 64;        // sample blocks per workgroup of the count kernel
 constexpr int kScanChunk = 4096;     // entries per workgroup of the sample scan
@@ -42,48 +49,118 @@ __device__ inline void flag_error(u64* err) {
   atomicOr(reinterpret_cast<unsigned long long*>(err), (unsigned long long)kErrBounds);
 }
 
-// Phi[SA[j]] = SA[j - 1], Phi[SA[0]] = kNone.
-__global__ __launch_bounds__(256) void phi_kernel(const u32* __restrict__ sa, u64 n,
-                                                  u32* __restrict__ phi, u64* __restrict__ err) {
+// Length of the common prefix of text[x, n) and text[y, n), at most `cap`,
+// comparing eight bytes at a time where whole aligned words around both
+// stretches lie inside the text (byte by byte otherwise).
+__device__ inline u32 common_prefix(const u8* __restrict__ text, u64 n, u64 x, u64 y, u32 cap) {
+  u64 lim = n - (x > y ? x : y);
+  if (lim > cap) lim = cap;
+  const uintptr_t t0 = reinterpret_cast<uintptr_t>(text);
+  const uintptr_t ax = (t0 + x) & ~uintptr_t(7), ay = (t0 + y) & ~uintptr_t(7);
+  const u64 words = (lim + 7) / 8 + 1;  // aligned words covering lim bytes from either start
+  if (ax >= t0 && ay >= t0 && ax + 8 * words <= t0 + n && ay + 8 * words <= t0 + n) {
+    const u64* px = reinterpret_cast<const u64*>(ax);
+    const u64* py = reinterpret_cast<const u64*>(ay);
+    const u32 sx = u32(t0 + x - ax) * 8, sy = u32(t0 + y - ay) * 8;  // bit offsets
+    u64 wx = px[0], wy = py[0];
+    for (u64 k = 0; 8 * k < lim; ++k) {
+      const u64 nx = px[k + 1], ny = py[k + 1];
+      // Bytes [8k, 8k + 8) of each stretch, little-endian.
+      const u64 vx = sx ? (wx >> sx) | (nx << (64 - sx)) : wx;
+      const u64 vy = sy ? (wy >> sy) | (ny << (64 - sy)) : wy;
+      const u64 d = vx ^ vy;
+      if (d) {
+        const u64 m = 8 * k + u64(__builtin_ctzll(d) / 8);
+        return u32(m < lim ? m : lim);
+      }
+      wx = nx;
+      wy = ny;
+    }
+    return u32(lim);
+  }
+  u32 m = 0;
+  while (m < lim && text[x + m] == text[y + m]) ++m;
+  return m;
+}
+
+// LCP in suffix array order up to kLcpCap; a long entry marks its position in
+// `long_bits` and records Phi there.
+__global__ __launch_bounds__(256) void lcp_direct_kernel(const u8* __restrict__ text, u64 n,
+                                                         const u32* __restrict__ sa,
+                                                         u32* __restrict__ lcp,
+                                                         u32* __restrict__ phi,
+                                                         u32* __restrict__ long_bits,
+                                                         u64* __restrict__ err) {
   const u64 stride = u64(gridDim.x) * blockDim.x;
   for (u64 j = u64(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride) {
-    const u32 s = sa[j];
-    const u32 prev = j ? sa[j - 1] : kNone;
-    if (s >= n || (j && prev >= n)) {
-      flag_error(err);
+    if (j == 0) {
+      lcp[0] = 0;
       continue;
     }
-    phi[s] = prev;
+    const u32 a = sa[j - 1], b = sa[j];
+    if (a >= n || b >= n || a == b) {
+      flag_error(err);
+      lcp[j] = 0;
+      continue;
+    }
+    const u32 m = common_prefix(text, n, a, b, kLcpCap);
+    if (m < kLcpCap) {
+      lcp[j] = m;
+    } else {
+      lcp[j] = kLcpLong;
+      phi[b] = a;
+      atomicOr(&long_bits[b >> 5], 1u << (b & 31u));
+    }
   }
 }
 
-// PLCP over stretches of kLcpStretch positions, in place over Phi.
-__global__ __launch_bounds__(256) void plcp_kernel(const u8* __restrict__ text, u64 n,
-                                                   u32* __restrict__ phi_plcp) {
+// PLCP at the long positions, over stretches of kLcpStretch positions, in
+// place over Phi. A long position's common prefix is at least kLcpCap and at
+// least the previous position's minus one when that one was long too.
+__global__ __launch_bounds__(256) void plcp_long_kernel(const u8* __restrict__ text, u64 n,
+                                                        const u32* __restrict__ long_bits,
+                                                        u32* __restrict__ phi_plcp) {
+  static_assert(kLcpStretch % 32 == 0, "whole bitmap words per stretch");
   const u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   const u64 lo = t * kLcpStretch;
   if (lo >= n) return;
   const u64 hi = lo + kLcpStretch < n ? lo + kLcpStretch : n;
   u64 l = 0;
-  for (u64 i = lo; i < hi; ++i) {
-    const u32 p = phi_plcp[i];
-    if (p == kNone) {
+  for (u64 w0 = lo; w0 < hi; w0 += 32) {
+    u32 bits = long_bits[w0 >> 5];
+    if (!bits) {
       l = 0;
-    } else {
-      // Extend from the previous common prefix minus one.
-      while (i + l < n && p + l < n && text[i + l] == text[p + l]) ++l;
+      continue;
     }
-    phi_plcp[i] = u32(l);
-    l = l ? l - 1 : 0;
+    for (u64 i = w0; i < hi && i < w0 + 32; ++i) {
+      if (!((bits >> (i - w0)) & 1u)) {
+        l = 0;
+        continue;
+      }
+      const u64 p = phi_plcp[i];
+      if (l < kLcpCap) l = kLcpCap;
+      // Extend eight bytes at a time while both stretches agree on all of them.
+      for (;;) {
+        const u64 room = n - (i > p ? i : p);
+        if (l >= room) break;
+        const u32 step = room - l < 4096 ? u32(room - l) : 4096u;
+        const u32 m = common_prefix(text, n, i + l, p + l, step);
+        l += m;
+        if (m < step) break;
+      }
+      phi_plcp[i] = u32(l);
+      l = l ? l - 1 : 0;
+    }
   }
 }
 
-// LCP[j] = PLCP[SA[j]].
-__global__ __launch_bounds__(256) void lcp_gather_kernel(const u32* __restrict__ sa, u64 n,
-                                                         const u32* __restrict__ plcp,
-                                                         u32* __restrict__ lcp) {
+// LCP[j] = PLCP[SA[j]] for the long entries.
+__global__ __launch_bounds__(256) void lcp_long_gather_kernel(const u32* __restrict__ sa, u64 n,
+                                                              const u32* __restrict__ plcp,
+                                                              u32* __restrict__ lcp) {
   const u64 stride = u64(gridDim.x) * blockDim.x;
   for (u64 j = u64(blockIdx.x) * blockDim.x + threadIdx.x; j < n; j += stride) {
+    if (lcp[j] != kLcpLong) continue;
     const u32 s = sa[j];
     lcp[j] = s < n ? plcp[s] : 0u;
   }
@@ -329,14 +406,16 @@ sa_status sa_lcp(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, const uint32_t*
   sa_status st = ensure_workspace(ctx, n);
   if (st != SA_OK) return st;
   launch_fill_u64(ctx->counters, kCtrCount, 0, s);
-  u32* phi = ctx->isa;  // Phi, then PLCP in place
+  u32* phi = ctx->isa;        // Phi at the long positions, then PLCP in place
+  u32* long_bits = ctx->live;  // the long positions
+  launch_fill_u32(long_bits, ceil_div(n, 32), 0, s);
   const u32 g = grid_for(n, 256, 8192);
-  hipLaunchKernelGGL(phi_kernel, dim3(g), dim3(256), 0, s, d_sa, n, phi,
-                     ctx->counters + kCtrError);
+  hipLaunchKernelGGL(lcp_direct_kernel, dim3(g), dim3(256), 0, s, d_text, n, d_sa, d_lcp, phi,
+                     long_bits, ctx->counters + kCtrError);
   const u64 threads = ceil_div(n, kLcpStretch);
-  hipLaunchKernelGGL(plcp_kernel, dim3(u32(ceil_div(threads, 256))), dim3(256), 0, s, d_text, n,
-                     phi);
-  hipLaunchKernelGGL(lcp_gather_kernel, dim3(g), dim3(256), 0, s, d_sa, n, phi, d_lcp);
+  hipLaunchKernelGGL(plcp_long_kernel, dim3(u32(ceil_div(threads, 256))), dim3(256), 0, s,
+                     d_text, n, long_bits, phi);
+  hipLaunchKernelGGL(lcp_long_gather_kernel, dim3(g), dim3(256), 0, s, d_sa, n, phi, d_lcp);
   return finish(ctx, s);
 }
 

@@ -97,6 +97,38 @@ def test_tiles_and_stretches(builder, kind, n):
     check_all(builder, t, seed=n)
 
 
+@pytest.mark.parametrize("offset", range(8))
+def test_lcp_cap_and_alignment(builder, offset):
+    """Common prefixes on both sides of the 32 bytes compared in suffix array
+    order (planted repeats of 24..48 bytes and a few long ones), with the text
+    starting 0..7 bytes past an aligned address, so that the eight-byte
+    comparisons run on every alignment and fall back near both ends."""
+    rng = np.random.default_rng(900 + offset)
+    n = 50000
+    t = rng.integers(0, 4, n).astype(np.uint8)
+    for _ in range(400):
+        ln = int(rng.integers(24, 49))
+        a, b = (int(x) for x in rng.integers(0, n - ln, 2))
+        t[b:b + ln] = t[a:a + ln]
+    for _ in range(4):
+        ln = int(rng.integers(500, 3000))
+        a, b = (int(x) for x in rng.integers(0, n - ln, 2))
+        t[b:b + ln] = t[a:a + ln]
+    t[-40:] = t[1000:1040]  # a suffix that ends inside a repeat
+    buf = torch.zeros(n + 16, dtype=torch.uint8, device="cuda:0")
+    buf[offset:offset + n] = torch.from_numpy(t).to("cuda:0")
+    d = buf[offset:offset + n]
+    sa = builder.build(d)
+    torch.cuda.synchronize()
+    want_sa = oracle.sa(t)
+    assert np.array_equal(sa.cpu().numpy().view(np.uint32), want_sa)
+    lcp = builder.lcp(d, sa)
+    torch.cuda.synchronize()
+    want = oracle.lcp(t, want_sa)
+    assert (want >= 32).sum() > 100 and ((want > 20) & (want < 32)).sum() > 50
+    assert np.array_equal(lcp.cpu().numpy().view(np.uint32), want)
+
+
 def test_closed_forms(builder):
     n = 70000
     a = np.full(n, 97, np.uint8)
