@@ -324,9 +324,11 @@ sa_status sa_tune_lookup(const char* path, const char* arch, const char* mode, u
 
 /* LCP array: d_lcp[0] = 0 and, for j >= 1, d_lcp[j] = the number of leading
  * bytes suffixes d_sa[j - 1] and d_sa[j] have in common. d_lcp: device u32[n].
- * Uses 4n bytes of the context's workspace (which grows to a build's size).
- * Method: Kasai et al.'s bound lcp(i + 1) >= lcp(i) - 1 along the text, in
- * the permuted (Phi) form; every step runs in the library's kernels. */
+ * Uses 4n + n/8 bytes of the context's workspace (which grows to a build's
+ * size). Method: each entry compared directly over at most 32 bytes; the
+ * entries that reach 32 follow from Kasai et al.'s bound
+ * lcp(i + 1) >= lcp(i) - 1 along the text, in the permuted (Phi) form. Every
+ * step runs in the library's kernels. */
 sa_status sa_lcp(sa_ctx* ctx, const uint8_t* d_text, uint64_t n, const uint32_t* d_sa,
                  uint32_t* d_lcp, void* stream);
 
