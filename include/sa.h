@@ -272,6 +272,10 @@ typedef struct {
                             (Section 2.1): rank quadruples sorted as two 2b-bit words, half
                             the rounds, always with the eager ISA. sa_build and
                             sa_build_rounds only; batches and the server double. */
+  uint32_t isa_direct;   /* 0 (default): in a single text of at least 2^26 bytes, a round with
+                            at least 2^22 active suffixes writes its names into the ISA grouped
+                            by position (256 buckets, one after the other); 1: every name is
+                            written straight from the re-rank. */
 } sa_tuning;
 /* Sets an explicit tuning, used by every later build of the context. t = NULL
  * goes back to automatic choice: the cache entry for each input, else the

@@ -78,11 +78,13 @@ class Tuning(ctypes.Structure):
                 ("round0_full", ctypes.c_uint32), ("sort_wgs_per_cu", ctypes.c_uint32),
                 ("sort_block", ctypes.c_uint32), ("sort_match", ctypes.c_uint32),
                 ("radix_bits", ctypes.c_uint32), ("rounds_ahead", ctypes.c_uint32),
-                ("round_graphs", ctypes.c_uint32), ("prefix_mult", ctypes.c_uint32)]
+                ("round_graphs", ctypes.c_uint32), ("prefix_mult", ctypes.c_uint32),
+                ("isa_direct", ctypes.c_uint32)]
 
 
 TUNING_KNOBS = ("sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu", "sort_block",
-                "sort_match", "radix_bits", "rounds_ahead", "round_graphs", "prefix_mult")
+                "sort_match", "radix_bits", "rounds_ahead", "round_graphs", "prefix_mult",
+                "isa_direct")
 
 
 def tuning_dict(t: "Tuning") -> dict:

@@ -159,6 +159,16 @@ constexpr int kSortBlockDefault = 512;   // default sweep shape: 512 threads x 8
 constexpr int kSortItemsDefault = 8;
 constexpr int kSortTileMin = 2048;       // smallest tile (512 x 4); status arrays are sized for it
 constexpr int kHistBlock = 256;
+// Staged ISA writes of a re-rank over a large active set: (position, name)
+// pairs grouped by position bucket (kStageBuckets equal ranges of the text)
+// and then written one bucket after the other, so that the writes in flight
+// fall in one bucket's stretch of the ISA instead of all of it.
+constexpr int kStageBuckets = 256;
+constexpr u32 kStageMaxWgs = 1024;               // re-rank workgroups with a count row
+constexpr u64 kStageMinCount = u64(1) << 22;     // active elements (read on the device)
+constexpr u64 kStageMinN = u64(1) << 26;         // text length (ISA of 256 MiB)
+constexpr u64 kStageSkip = ~u64(0);              // staged entry: name unchanged
+
 constexpr int kRerankBlock = 256;
 constexpr int kRerankRows = 8;  // rows of 64 elements per wave
 constexpr int kRerankTile = kRerankBlock * kRerankRows;  // 2048 elements
@@ -176,7 +186,8 @@ enum CounterSlot : int {
   kCtrIndexAux = kMaxPasses + 7,     // index builds: the row of $ in the transform
   kCtrPairI = kMaxPasses + 8,        // sort-based pairing: non-unique items paired this round
   kCtrPairU = kMaxPasses + 9,        // sort-based pairing: unique items kept for the next round
-  kCtrCount = kMaxPasses + 10,
+  kCtrStage = kMaxPasses + 10,       // staged ISA writes of the last re-rank
+  kCtrCount = kMaxPasses + 11,
 };
 
 }  // namespace sa

@@ -39,7 +39,7 @@ struct TuneTable {
 struct GraphKey {
   u64 n, bound;
   const void* ptr[12];
-  u32 knobs[10];
+  u32 knobs[12];
 };
 struct GraphEntry {
   GraphKey key;
@@ -93,6 +93,7 @@ struct sa_ctx {
   u32* present = nullptr;
   u16* code = nullptr;
   u64* sample = nullptr;  // lazy ISA: sampled round-0 sorted keys
+  u32* stage_hist = nullptr;  // staged ISA writes: counts per (bucket, re-rank workgroup)
   // Pinned mirror of counters | rc | plan_log, refreshed by every readback.
   void* h_mirror = nullptr;
   u64* h_counters = nullptr;
@@ -116,6 +117,7 @@ struct sa_ctx {
   int sort_match = 0;                  // sweep digit matching: 0 ballots, 1 LDS table
   int radix_bits = kRadixBits;         // radix-sort digit width
   int prefix_mult = 2;                 // 2: prefix doubling; 4: prefix quadrupling (sa_build)
+  bool stage_isa = true;               // names of long single texts staged by position bucket
   int num_cus = 256;
   u64 lazy_ratio = kLazyRatioDefault;
   int round0_trim = 1;  // round-0 keys fill whole radix digits
@@ -166,8 +168,9 @@ constexpr size_t kSmallPlan = (sizeof(SortPlan) + 255) / 256 * 256;
 constexpr size_t kSmallPresent = 256 * sizeof(u32);
 constexpr size_t kSmallCode = 256 * sizeof(u16);
 constexpr size_t kSmallSample = size_t(kLazySamples) * sizeof(u64);
+constexpr size_t kSmallStage = size_t(kStageBuckets) * kStageMaxWgs * sizeof(u32);
 constexpr size_t kSmallBytes = kSmallHist + kMirrorBytes + kSmallCtl + kSmallPlan + kSmallPresent +
-                               kSmallCode + kSmallSample;
+                               kSmallCode + kSmallSample + kSmallStage;
 static_assert(kSmallCounters % 8 == 0 && kSmallRoundCtl % 8 == 0, "mirror alignment");
 static_assert(sizeof(SortCtl) <= kSmallCtl, "control block");
 

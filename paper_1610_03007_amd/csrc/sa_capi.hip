@@ -246,9 +246,23 @@ void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, u6
   Tracer t(c, s, (args.mode & kRerankIsaOnly) ? SA_KERNEL_ISA_SCATTER : SA_KERNEL_RERANK, bytes);
   const u32 grid = u32(std::min<u64>(std::max<u64>(1, ceil_div(bound, kRerankTile)),
                                      u64(c->num_cus) * rerank_wgs_per_cu(args.tie != 0)));
-  launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, args, c->ctl, c->isa, d_sa,
-                        args.tbase ? nullptr : c->act_idx, args.tbase ? c->act_ti : nullptr,
+  // Names of one long text go through the staged writes (when the device
+  // count turns out large enough): its ISA is far larger than the caches.
+  RerankArgs a = args;
+  const bool stage = (a.mode & kRerankScatterIsa) && !(a.mode & (kRerankPairOut | kRerankEmit)) &&
+                     !a.tbase && a.n >= kStageMinN && grid <= kStageMaxWgs && c->stage_isa;
+  if (stage) {
+    a.stage_a = bf.kA;
+    a.stage_b = bf.kB;
+    a.stage_hist = c->stage_hist;
+    a.stage_w = u32(ceil_div(a.n, u64(kStageBuckets)));
+  }
+  launch_rerank_compact(bf.kA, bf.kB, bf.vA, bf.vB, c->plan, a, c->ctl, c->isa, d_sa,
+                        a.tbase ? nullptr : c->act_idx, a.tbase ? c->act_ti : nullptr,
                         c->act_rank, c->counters, grid, s);
+  if (stage)
+    launch_stage_isa(bf.kA, bf.kB, c->plan, c->ctl, c->stage_hist, grid, a.stage_w, a.n, c->isa,
+                     c->counters, u32(c->num_cus) * 4, s);
 }
 
 // Re-rank arguments of a single text: round 0 (one group, every rank 1) or a
@@ -382,10 +396,10 @@ GraphKey later_key(const sa_ctx* c, const LaterRound& L) {
   const void* p[12] = {L.bufs.kA, L.bufs.kB, L.bufs.vA, L.bufs.vB, L.text, L.keys0, L.d_sa,
                        c->isa, c->act_idx, c->small, c->status, c->live};
   std::memcpy(k.ptr, p, sizeof(p));
-  const u32 knobs[10] = {u32(L.b),           u32(L.npass),           L.lazy ? 1u : 0u,
+  const u32 knobs[11] = {u32(L.b),           u32(L.npass),           L.lazy ? 1u : 0u,
                          u32(c->sort_items), u32(c->sort_block),     u32(c->sort_match),
                          u32(c->sort_wgs_per_cu), u32(c->num_cus),   u32(c->radix_bits),
-                         L.quad ? 1u : 0u};
+                         L.quad ? 1u : 0u,   c->stage_isa ? 1u : 0u};
   std::memcpy(k.knobs, knobs, sizeof(knobs));
   return k;
 }
@@ -635,6 +649,8 @@ void bind_small(sa_ctx* c, char* p) {
   c->code = reinterpret_cast<u16*>(p);
   p += kSmallCode;
   c->sample = reinterpret_cast<u64*>(p);
+  p += kSmallSample;
+  c->stage_hist = reinterpret_cast<u32*>(p);
 }
 
 // ---------------------------------------------------------------------------

@@ -1291,6 +1291,7 @@ void rerank_compact_kernel(
   __shared__ u32 s_svr[T];  // new name
   __shared__ u32 s_fill, s_tile_at, s_flush_n;
   __shared__ u64 s_flush_at;
+  __shared__ u32 s_bh[kStageBuckets];  // staged ISA writes per position bucket
 
   const u32 fb = plan->final_buf;
   const u64* keys = fb ? keysB : keysA;
@@ -1308,6 +1309,10 @@ void rerank_compact_kernel(
   const u64 lt_mask = (u64(1) << lane) - 1;
   const u64 tiles = ceil_div(count, u64(T));
   if (tid == 0) s_fill = 0;  // ordered before its use by the tile's first barrier
+  const bool staged = scatter && a.stage_w != 0 && count >= kStageMinCount;
+  u64* const stage = fb ? a.stage_a : a.stage_b;  // the key buffer the sort did not end in
+  if (staged)
+    for (int b = tid; b < kStageBuckets; b += kRerankBlock) s_bh[b] = 0;
   bool bad = false;
   // Writes buffer entries [0, s_flush_n) at s_flush_at (every thread).
   auto flush = [&]() {
@@ -1542,6 +1547,7 @@ void rerank_compact_kernel(
     const u64 nr = r0 + ss - gs;
     if (v[r] >= nt || nr == 0 || nr > nt || (!uniq && !no_survivors && out >= u32(T))) {
       bad = true;
+      if (staged) stage[e] = kStageSkip;
       continue;
     }
     if (pair_out) {
@@ -1556,7 +1562,17 @@ void rerank_compact_kernel(
     // The ISA already holds every active suffix's previous name, so a name
     // that did not change (a group that did not split, or the first sub-group
     // of one that did) is not written again.
-    if (scatter && (first_round || nr != r0)) isa[gb + v[r]] = u32(nr);
+    if (staged) {
+      u64 w = kStageSkip;
+      if (first_round || nr != r0) {
+        const u32 pos = u32(gb + v[r]);
+        w = (u64(pos) << 32) | u64(u32(nr));
+        atomicAdd(&s_bh[pos / a.stage_w], 1u);
+      }
+      stage[e] = w;
+    } else if (scatter && (first_round || nr != r0)) {
+      isa[gb + v[r]] = u32(nr);
+    }
     if (isa_only) continue;
     if (uniq) {
       if (first_round || !((gflags >> (16 + r)) & 1u)) sa_out[gb + nr - 1] = v[r];
@@ -1577,6 +1593,9 @@ void rerank_compact_kernel(
   }
   __syncthreads();
   if (s_flush_n) flush();
+  if (staged)
+    for (int b = tid; b < kStageBuckets; b += kRerankBlock)
+      a.stage_hist[size_t(b) * gridDim.x + blockIdx.x] = s_bh[b];
   if (bad)
     atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
              (unsigned long long)kErrBounds);
@@ -1611,6 +1630,129 @@ void launch_rerank_compact(const u64* keysA, const u64* keysB, const u32* valsA,
     hipLaunchKernelGGL(rerank_compact_kernel<false>, dim3(grid), dim3(kRerankBlock), 0, s, keysA,
                        keysB, valsA, valsB, plan, args, ctl, isa, sa_out, act_idx, act_ti, act_rank,
                        counters);
+}
+
+// ---------------------------------------------------------------------------
+// Staged ISA writes of a re-rank (see RerankArgs::stage_w). A random 4-byte
+// write costs a memory transaction of its own; with the pairs grouped by
+// position bucket, the writes a wave of the last kernel issues fall in one
+// 1/kStageBuckets stretch of the ISA, whose lines the caches then combine.
+
+// Exclusive scan, in place, of the per-(bucket, workgroup) counts in
+// bucket-major order (one workgroup); the total to counters[kCtrStage].
+__global__ __launch_bounds__(1024) void stage_scan_kernel(const SortCtl* __restrict__ ctl,
+                                                          u32* __restrict__ hist, u32 entries,
+                                                          u64* __restrict__ counters) {
+  if (ctl->count < kStageMinCount) return;
+  __shared__ u32 s_w[1024 / kWave];
+  const u32 tid = threadIdx.x;
+  const u32 per = (entries + 1023) / 1024;
+  const u32 lo = tid * per < entries ? tid * per : entries;
+  const u32 hi = lo + per < entries ? lo + per : entries;
+  u32 sum = 0;
+  for (u32 i = lo; i < hi; ++i) sum += hist[i];
+  const u32 inc = wave_inclusive_sum(sum);
+  if (lane_id() == kWave - 1) s_w[tid / kWave] = inc;
+  __syncthreads();
+  u32 run = inc - sum;
+  for (u32 w = 0; w < tid / kWave; ++w) run += s_w[w];
+  for (u32 i = lo; i < hi; ++i) {
+    const u32 x = hist[i];
+    hist[i] = run;
+    run += x;
+  }
+  if (tid == 1023) counters[kCtrStage] = run;
+}
+
+// Each workgroup takes the tiles its re-rank workgroup took (same grid, same
+// tile order) and moves their staged pairs to the scanned offsets of their
+// buckets in the key buffer the sort ended in.
+__global__ __launch_bounds__(256) void stage_partition_kernel(
+    u64* __restrict__ keysA, u64* __restrict__ keysB, const SortPlan* __restrict__ plan,
+    const SortCtl* __restrict__ ctl, const u32* __restrict__ hist, u32 stage_w, u64 n,
+    u64* __restrict__ counters) {
+  constexpr int T = kRerankTile;
+  constexpr int PER = T / 256;
+  const u64 count = ctl->count;
+  if (count < kStageMinCount) return;
+  const u32 fb = plan->final_buf;
+  const u64* stage = fb ? keysA : keysB;
+  u64* out = fb ? keysB : keysA;
+  __shared__ u32 s_off[kStageBuckets], s_cnt[kStageBuckets];
+  const int tid = threadIdx.x;
+  for (int b = tid; b < kStageBuckets; b += 256) {
+    s_off[b] = hist[size_t(b) * gridDim.x + blockIdx.x];
+    s_cnt[b] = 0;
+  }
+  __syncthreads();
+  const u64 total = counters[kCtrStage];
+  const u64 tiles = ceil_div(count, u64(T));
+  bool bad = false;
+  for (u64 tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    u64 w[PER];
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const u64 e = tile * T + u64(j) * 256 + tid;
+      w[j] = e < count ? stage[e] : kStageSkip;
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      if (w[j] == kStageSkip) continue;
+      const u64 pos = w[j] >> 32;
+      if (pos >= n) {
+        bad = true;
+        continue;
+      }
+      const u32 b = u32(pos) / stage_w;  // < kStageBuckets: stage_w >= n / kStageBuckets
+      const u64 slot = u64(s_off[b]) + atomicAdd(&s_cnt[b], 1u);
+      if (slot >= total) {
+        bad = true;
+        continue;
+      }
+      out[slot] = w[j];
+    }
+    __syncthreads();
+    for (int b = tid; b < kStageBuckets; b += 256) {
+      s_off[b] += s_cnt[b];
+      s_cnt[b] = 0;
+    }
+    __syncthreads();
+  }
+  if (bad)
+    atomicOr(reinterpret_cast<unsigned long long*>(counters + kCtrError),
+             (unsigned long long)kErrBounds);
+}
+
+// ISA[position] = name for the grouped pairs, in order: the threads in flight
+// write into one or two buckets' stretches. Scattered 4-byte writes run
+// fastest with few in flight: about four 256-thread workgroups per CU (twice
+// as many take twice as long).
+__global__ __launch_bounds__(256) void stage_apply_kernel(const u64* __restrict__ keysA,
+                                                          const u64* __restrict__ keysB,
+                                                          const SortPlan* __restrict__ plan,
+                                                          const SortCtl* __restrict__ ctl,
+                                                          const u64* __restrict__ counters, u64 n,
+                                                          u32* __restrict__ isa) {
+  if (ctl->count < kStageMinCount) return;
+  const u64* in = plan->final_buf ? keysB : keysA;
+  const u64 total = counters[kCtrStage];
+  const u64 stride = u64(gridDim.x) * blockDim.x;
+  for (u64 e = u64(blockIdx.x) * blockDim.x + threadIdx.x; e < total; e += stride) {
+    const u64 w = in[e];
+    const u64 pos = w >> 32;
+    if (pos < n) isa[pos] = u32(w);
+  }
+}
+
+void launch_stage_isa(u64* keysA, u64* keysB, const SortPlan* plan, const SortCtl* ctl,
+                      u32* stage_hist, u32 grid, u32 stage_w, u64 n, u32* isa, u64* counters,
+                      u32 apply_grid, hipStream_t s) {
+  hipLaunchKernelGGL(stage_scan_kernel, dim3(1), dim3(1024), 0, s, ctl, stage_hist,
+                     u32(kStageBuckets) * grid, counters);
+  hipLaunchKernelGGL(stage_partition_kernel, dim3(grid), dim3(256), 0, s, keysA, keysB, plan, ctl,
+                     stage_hist, stage_w, n, counters);
+  hipLaunchKernelGGL(stage_apply_kernel, dim3(apply_grid), dim3(256), 0, s, keysA, keysB, plan,
+                     ctl, counters, n, isa);
 }
 
 // ---------------------------------------------------------------------------

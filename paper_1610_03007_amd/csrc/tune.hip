@@ -168,6 +168,7 @@ bool tuning_valid(const sa_tuning& t) {
   if (t.lazy_ratio < 3 || t.round0_full > 1 || t.sort_wgs_per_cu > 16) return false;
   if (t.rounds_ahead > 64 || t.round_graphs > 1) return false;
   if (t.prefix_mult != 0 && t.prefix_mult != 2 && t.prefix_mult != 4) return false;
+  if (t.isa_direct > 1) return false;
   return true;
 }
 
@@ -333,6 +334,7 @@ void apply_tuning(sa_ctx* c, const sa_tuning& t) {
   c->graphs = t.round_graphs == 0;
   c->radix_bits = t.radix_bits ? int(t.radix_bits) : kRadixBits;
   c->prefix_mult = t.prefix_mult == 4 ? 4 : 2;
+  c->stage_isa = t.isa_direct == 0;
 }
 
 sa_tuning current_tuning(const sa_ctx* c) {
@@ -348,6 +350,7 @@ sa_tuning current_tuning(const sa_ctx* c) {
   t.rounds_ahead = c->rounds_ahead;
   t.round_graphs = c->graphs ? 0u : 1u;
   t.prefix_mult = u32(c->prefix_mult);
+  t.isa_direct = c->stage_isa ? 0u : 1u;
   return t;
 }
 

@@ -28,13 +28,14 @@ def write(tmp_path, entries, fmt=FORMAT):
 
 
 def test_tuning_struct_layout():
-    """The binding's sa_tuning mirror has the header's ten 32-bit fields, in
+    """The binding's sa_tuning mirror has the header's eleven 32-bit fields, in
     order (the library writes the whole struct)."""
     import ctypes
     names = [f[0] for f in _native.Tuning._fields_]
     assert names == ["sort_items", "lazy_ratio", "round0_full", "sort_wgs_per_cu", "sort_block",
-                     "sort_match", "radix_bits", "rounds_ahead", "round_graphs", "prefix_mult"]
-    assert ctypes.sizeof(_native.Tuning) == 40
+                     "sort_match", "radix_bits", "rounds_ahead", "round_graphs", "prefix_mult",
+                     "isa_direct"]
+    assert ctypes.sizeof(_native.Tuning) == 44
     header = open(os.path.join(os.path.dirname(__file__), "..", "include", "sa.h")).read()
     body = header[header.index("typedef struct {\n  uint32_t sort_items;"):]
     body = body[:body.index("} sa_tuning;")]
@@ -83,7 +84,7 @@ def test_knobs_round_trip(tmp_path):
     assert found
     assert t == {"sort_items": 12, "sort_wgs_per_cu": 6, "lazy_ratio": 64, "round0_full": 1,
                  "sort_block": 256, "sort_match": 0, "radix_bits": 8, "rounds_ahead": 0,
-                 "round_graphs": 0, "prefix_mult": 2}
+                 "round_graphs": 0, "prefix_mult": 2, "isa_direct": 0}
     p = write(tmp_path, [entry(sort_items=8, sort_block=512, sort_match=1)])
     t = _native.tune_lookup(p, "gfx950", "single", 1 << 28, 7)[1]
     assert t["sort_block"] == 512 and t["sort_match"] == 1
