@@ -337,8 +337,8 @@ sa_status dc3_level(sa_ctx* c, const T* x, u64 m, u32 add, u64 max_sym, u32* sa,
     if (st != SA_OK) return st;
     sa12 = L.childsa;
   }
-  hipLaunchKernelGGL(dc3_ranks_kernel, dim3(grid12), dim3(256), 0, s, sa12, m12, n0, m, dummy,
-                     L.rankp, L.byrank, c->counters);
+  hipLaunchKernelGGL(dc3_ranks_kernel, dim3(scatter_grid(c, m12)), dim3(256), 0, s, sa12, m12, n0,
+                     m, dummy, L.rankp, L.byrank, c->counters);
 
   // Step 3: the mod-0 suffixes by (x[i], rank(i + 1)).
   const int brank = std::max(1, bits_of(n12));

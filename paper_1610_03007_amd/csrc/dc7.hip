@@ -317,7 +317,7 @@ sa_status build_dc7(sa_ctx* c, const u8* text, u64 n, u32* d_sa, u32* d_rank, hi
     if (st != SA_OK) return st;
     sa_s = A.childsa;
   }
-  hipLaunchKernelGGL(d7_ranks_kernel, dim3(stream_grid(c, ms, 256)), dim3(256), 0, s, sa_s, ms, L,
+  hipLaunchKernelGGL(d7_ranks_kernel, dim3(scatter_grid(c, ms)), dim3(256), 0, s, sa_s, ms, L,
                      n, A.rankp, A.byrank, c->counters);
 
   // Step 3: the other four classes, by (class, characters to the next sample

@@ -273,6 +273,10 @@ void run_sort(sa_ctx* c, const Bufs& bf, u64 count, int npass, int vals_present,
 void run_rerank(sa_ctx* c, const Bufs& bf, const RerankArgs& args, u32* d_sa, u64 bound,
                 u64 trace_count, hipStream_t s);
 u32 stream_grid(const sa_ctx* c, u64 bound, u32 per_block);
+// Workgroups of 256 threads for a grid-stride kernel whose threads each make
+// scattered 4-byte writes: about four per CU. Scattered writes run fastest with
+// few in flight (twice as many take about twice as long).
+u32 scatter_grid(const sa_ctx* c, u64 bound);
 RerankArgs single_args(u64 count, u64 n, int b, int mode);
 sa_status readback(sa_ctx* c, hipStream_t s);
 u32 passes_run(const sa_ctx* c, int slot, int npass);

@@ -159,6 +159,11 @@ u32 stream_grid(const sa_ctx* c, u64 bound, u32 per_block) {
   return u32(std::min<u64>(want, u64(c->num_cus) * 16));
 }
 
+u32 scatter_grid(const sa_ctx* c, u64 bound) {
+  const u64 want = std::max<u64>(1, ceil_div(bound, 256));
+  return u32(std::min<u64>(want, u64(c->num_cus) * 4));
+}
+
 // Sweep workgroups one CU holds at once for each tile shape (register and LDS
 // limits of the kernel instances).
 int default_wgs_per_cu(int items, int block, bool table, int rb) {

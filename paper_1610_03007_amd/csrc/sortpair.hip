@@ -201,7 +201,7 @@ sa_status build_sortpair(sa_ctx* c, const u8* text, u64 n, u32* d_sa, u64* h_cou
     {
       Tracer t(c, s, SA_KERNEL_PACK_PAIRS, double(pcount) * 24.0);
       launch_fill_u64(c->counters + kCtrPairI, 2, 0, s);
-      const u32 grid = stream_grid(c, pcount, 256);
+      const u32 grid = scatter_grid(c, pcount);  // discarded suffixes scatter into SA
       hipLaunchKernelGGL(npairs_kernel, dim3(grid), dim3(256), 0, s, pb.kA, pb.kB, pb.vA, pb.vB,
                          c->plan, c->ctl, n, h, q, b, h2, q2, c->keysA, c->valsA, c->pair_k[W],
                          c->pair_v[W], d_sa, c->counters);
