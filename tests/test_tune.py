@@ -141,7 +141,8 @@ def test_autotune_save_and_reuse(tmp_path):
         e = doc["entries"][0]
         assert e["mode"] == "single" and e["log2n"] == 18 and e["code_bits"] == 3
         # The cache holds the searched knobs; the launch policies are not tuned.
-        searched = {k: v for k, v in best.items() if k not in ("rounds_ahead", "round_graphs")}
+        searched = {k: v for k, v in best.items()
+                    if k not in ("rounds_ahead", "round_graphs", "isa_direct")}
         assert {k: e[k] for k in searched} == searched
         # The tuner leaves automatic choice in force: the next build uses the entry.
         sa = b.build(d, sigma=4)
