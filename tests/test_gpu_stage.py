@@ -67,3 +67,34 @@ def test_staged_full_build(builder, text):
     finally:
         builder.auto_tuning()
     assert torch.equal(got, want)
+
+
+@pytest.mark.parametrize("mode", ["lazy", "eager"])
+def test_staged_with_isa_modes(builder, mode):
+    """A 2^26-byte DNA text with planted repeats: about 6e6 suffixes survive
+    round 0 (at least 2^22, so the later rounds stage their names), in both
+    ISA forms; the lazy one carves the later rounds' buffers out of the spare
+    keys. Staged and direct writes give the same arrays, which pass the
+    oracle's check."""
+    n = 1 << 26
+    t = W.dna(n, seed=2626).copy()
+    rng = np.random.default_rng(2626)
+    for _ in range(3000):
+        a, b = (int(x) for x in rng.integers(0, n - 1000, 2))
+        t[b:b + 1000] = t[a:a + 1000]
+    d = torch.from_numpy(t).to("cuda:0")
+    builder.set_isa_mode(mode)
+    try:
+        out = {}
+        for direct in (1, 0):
+            builder.set_tuning(isa_direct=direct)
+            out[direct] = builder.build(d)
+            torch.cuda.synchronize()
+            info = builder.last_info()
+            assert info["lazy_isa"] == (1 if mode == "lazy" else 0)
+            assert info["active"][1] >= (1 << 22), info["active"]
+    finally:
+        builder.set_isa_mode("auto")
+        builder.auto_tuning()
+    assert torch.equal(out[0], out[1])
+    assert oracle.check_sa(t, out[0].cpu().numpy().view(np.uint32))[0] == 0
