@@ -81,8 +81,16 @@ def make_text(name: str):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """sha256[:16] of the sort sweep's source: common.h, sa_kernels.hip from its
+    top through the helper namespace (digit extraction, scans, look-back), and
+    the sweep kernel from its leading comment to onesweep_supported."""
+    with open(KERNEL_SOURCE) as f:
+        src = f.read()
+    with open(os.path.join(os.path.dirname(KERNEL_SOURCE), "common.h")) as f:
+        common = f.read()
+    head = src[:src.index("}  // namespace")]
+    sweep = src[src.index("// One stable counting sweep over digit"):src.index("bool onesweep_supported(")]
+    return hashlib.sha256((common + head + sweep).encode()).hexdigest()[:16]
 
 
 def measured_traffic(workload: str):
