@@ -518,7 +518,7 @@ void launch_sort_gen_reset(SortCtl* ctl, hipStream_t s) {
 constexpr int kHistItems = 8;
 
 // Up-front counts of a sort, per chunk of the input (chunk c = tiles
-// [c << ct_log2, (c + 1) << ct_log2)): the digit counts of passes 0 and 1 (the
+// [c * per, (c + 1) * per)): the digit counts of passes 0 and 1 (the
 // first sweep's digit whenever one of them varies) and, over all keys, the OR
 // of the keys and of their complements, which tell the plan which digits are
 // constant. Later sweeps get their chunk counts from the sweep before them.
@@ -529,7 +529,7 @@ constexpr u32 kHistMaxBlocks = 2048;
 // Workgroups per chunk of a histogram launch of `grid` workgroups: a few per
 // chunk, at most grid / nchunks. Workgroups past per * nchunks have no share.
 __device__ inline u32 hist_per_chunk(const SortGeom& geo, u32 grid) {
-  const u64 chunk_elems = u64(geo.tile) << geo.ct_log2;
+  const u64 chunk_elems = u64(geo.tile) * geo.per;
   u64 per = (chunk_elems + kHistBlockElems - 1) / kHistBlockElems;
   const u64 cap = grid / geo.nchunks;
   if (per > cap) per = cap;
@@ -551,7 +551,7 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_kernel(
   const u32 per_chunk = hist_per_chunk(geo, gridDim.x);
   if (blockIdx.x >= per_chunk * geo.nchunks) return;
   const u32 nchunks = geo.nchunks;
-  const u64 chunk_elems = u64(tile) << geo.ct_log2;
+  const u64 chunk_elems = u64(tile) * geo.per;
   for (int i = threadIdx.x; i < NP * RADIX; i += kHistBlock) lh[i] = 0;
   __syncthreads();
   const u32 c = blockIdx.x / per_chunk;
@@ -637,7 +637,7 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_first_kernel(
   const u32 per_chunk = hist_per_chunk(geo, gridDim.x);
   if (blockIdx.x >= per_chunk * geo.nchunks) return;
   const u32 nchunks = geo.nchunks;
-  const u64 chunk_elems = u64(tile) << geo.ct_log2;
+  const u64 chunk_elems = u64(tile) * geo.per;
   __shared__ u32 lh[RADIX];
   for (int i = threadIdx.x; i < RADIX; i += kHistBlock) lh[i] = 0;
   __syncthreads();
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kHistBlock) void radix_histogram_first_kernel(
 // a smaller count has one).
 u32 radix_histogram_grid(u64 bound, u32 tile) {
   const SortGeom geo = sort_geom(bound, tile);
-  const u64 chunk_elems = u64(tile) << geo.ct_log2;
+  const u64 chunk_elems = u64(tile) * geo.per;
   u64 per = ceil_div(chunk_elems, kHistBlockElems);
   const u64 cap = kHistMaxBlocks / geo.nchunks;
   if (per > cap) per = cap;
@@ -822,7 +822,6 @@ void onesweep_pass_kernel(
   if (count == 0) return;
   const u32 gen = ctl->gen_base + u32(pass);
   const SortGeom geo = sort_geom(count, u32(TILE));
-  const u32 ct_log2 = geo.ct_log2;
   const u32 nchunks = geo.nchunks;
   const u32 src = plan->src[pass];
   const bool iota = plan->iota[pass] != 0;
@@ -839,8 +838,8 @@ void onesweep_pass_kernel(
   const int wave = tid / kWave;
   const u32 chunk = blockIdx.x % nchunks;
   const u64 tiles = ceil_div(count, u64(TILE));
-  const u64 c_first = u64(chunk) << ct_log2;
-  u64 c_end = c_first + (u64(1) << ct_log2);
+  const u64 c_first = u64(chunk) * geo.per;
+  u64 c_end = c_first + geo.per;
   if (c_end > tiles) c_end = tiles;
 
   // Start of each digit's output range for this chunk: global digit offset
@@ -1070,9 +1069,9 @@ void onesweep_pass_kernel(
         if (o < count) {
           kout[o] = k;
           if (next >= 0) {
-            // Output chunk o / (TILE << ct_log2), with TILE = kTileOdd << kTileTz:
+            // Output chunk (o / TILE) / per, with TILE = kTileOdd << kTileTz:
             // a 32-bit division by the odd factor (o < 2^(32 + kTileTz)).
-            const u32 bin = ((u32(o >> kTileTz) / kTileOdd) >> ct_log2) * RADIX +
+            const u32 bin = chunk_of(geo, u32(o >> kTileTz) / kTileOdd) * RADIX +
                             digit_at<RB>(k, nshift);
             atomicAdd(&s_next[bin >> 1], 1u << (16 * (bin & 1u)));
           }
